@@ -1,0 +1,208 @@
+"""Benchmark of the road-surface stereo path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload road1280_d64]
+                    [--no-cpu-baseline]
+
+One step = one full frame of the plain path on the 1280x720, D = 64 road pair
+(warp -> ZNCC reference + target volumes -> bilateral aggregation of both ->
+WTA + left-right check + parabola subpixel -> post-processing + 3-D points), inputs
+resident in HBM.  Prints ONE JSON line.  `value` is Eq. 13's Mde/s over the whole
+frame: W*H*D / t_frame * 1e-6.  Per-kernel durations come from HIP events on the
+stream the kernels run on; the roofline object covers the dominant kernel
+(bilateral aggregation, ALU-bound).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="road1280_d64",
+                    choices=["road1280_d64", "road320_d32", "road1920_d128"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=24, help="rows in the oracle timing sample")
+    return ap.parse_args()
+
+
+def agg_flops_per_entry(agg_radius: int) -> int:
+    m = (2 * agg_radius + 1) ** 2
+    return 2 * m + 1          # m multiply-adds and the 1/sum(w) scaling (Eq. 8)
+
+
+def source_sha(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel_src: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; else None."""
+    f = os.path.join(ROOT, "profiles", f"aggregate_{workload}_pmc.md")
+    if not os.path.exists(f):
+        return None
+    txt = open(f).read()
+    sha = re.search(r"source_sha:\s*([0-9a-f]+)", txt)
+    tb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not sha or not tb or sha.group(1) != source_sha(kernel_src):
+        return None
+    return float(tb.group(1))
+
+
+def cpu_baseline(case, rows: int):
+    """The FP64 oracle, as it stands, on a band of `rows` full-width rows of the same pair
+    (same D and windows): warp -> both volumes -> both aggregations -> select -> 3-D."""
+    import numpy as np
+    from oracle import stereo as S
+    p, prm = case.pair, case.params
+    H, W = p.left.shape
+    v0 = H // 2 - rows // 2
+    L = np.ascontiguousarray(p.left[v0:v0 + rows])
+    R = np.ascontiguousarray(p.right[v0:v0 + rows])
+    pl = case.plane
+    plane = (pl.a0 + pl.a1 * v0, pl.a1, pl.a2, pl.delta)   # same rows of the same plane
+    cam = (case.camera.f, case.camera.baseline, case.camera.u0, case.camera.v0 - v0)
+    t0 = time.perf_counter()
+    S.reconstruct(L, R, plane, cam, prm.D, prm.block_radius, prm.agg_radius, prm.gamma_d,
+                  prm.gamma_r, prm.lr_threshold, prm.sigma_min)
+    dt = time.perf_counter() - t0
+    return {"value": round(W * rows * prm.D / dt * 1e-6, 4), "unit": "Mpix·disp/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"rows {v0}..{v0 + rows - 1} of the {W}x{H} pair (full width, D={prm.D}), "
+                      f"whole plain path in FP64 NumPy, {dt:.1f} s, single thread"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_1807_07433_amd as rsv
+    from paper_1807_07433_amd import _lib
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    rsv.load()
+    case = {"road1280_d64": synth.road1280_d64, "road320_d32": synth.road320_d32,
+            "road1920_d128": synth.road1920_d128}[a.workload]()
+    p, prm = case.pair, case.params
+    H, W = p.left.shape
+    D = prm.D
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(p.left).to(dev)
+    R = torch.from_numpy(p.right).to(dev)
+    cam = (case.camera.f, case.camera.baseline, case.camera.u0, case.camera.v0)
+
+    f32 = dict(dtype=torch.float32, device=dev)
+    wp = torch.empty((H, W), **f32)
+    cref = torch.empty((D, H, W), **f32)
+    ctar = torch.empty((D, H, W), **f32)
+    aref = torch.empty((D, H, W), **f32)
+    atar = torch.empty((D, H, W), **f32)
+    sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
+           "disp_tar": torch.empty((H, W), dtype=torch.int32, device=dev),
+           "disp_sub": torch.empty((H, W), **f32),
+           "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
+    dfin = torch.empty((H, W), **f32)
+    xyz = torch.empty((H, W, 3), **f32)
+    stages = ["warp", "cost_volume", "aggregate_ref", "aggregate_tar", "select_subpixel",
+              "triangulate"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        rsv.warp(R, case.plane, out=wp)
+        mark(1)
+        rsv.cost_volume(L, wp, prm, out_ref=cref, out_tar=ctar)
+        mark(2)
+        rsv.aggregate(cref, L, prm, out=aref)
+        mark(3)
+        rsv.aggregate(ctar, wp, prm, out=atar)
+        mark(4)
+        rsv.select_subpixel(aref, atar, prm, out=sel)
+        mark(5)
+        rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
+        mark(6)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(a.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_start.record()
+    for i in range(a.steps):
+        step(evs[i])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = t_start.elapsed_time(t_end) / a.steps
+    stage_ms = {s: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / a.steps
+                for k, s in enumerate(stages)}
+
+    mde = W * H * D / (ms_step * 1e-3) * 1e-6
+    t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
+    agg_ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
+    agg_flops = W * H * D * agg_flops_per_entry(prm.agg_radius)
+    achieved = agg_flops / (agg_ms * 1e-3) * 1e-12
+    agg_src = os.path.join(ROOT, "paper_1807_07433_amd", "csrc", "aggregate.hip")
+    traffic = recorded_traffic(agg_src, a.workload)
+
+    out = {
+        "metric": "Mpix·disp/s (cost+aggregate) & frames/s at 1280×720 D=64; batched vs plain",
+        "value": round(mde, 2),
+        "unit": "Mpix·disp/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {W}x{H} uint8 road pair, D={D}, "
+                               f"NCC {2 * prm.block_radius + 1}x{2 * prm.block_radius + 1}, "
+                               f"bilateral {2 * prm.agg_radius + 1}x{2 * prm.agg_radius + 1}",
+                   "width": W, "height": H, "D": D, "parallelism": "single-gpu",
+                   "value_definition": "W*H*D / full-frame time (Eq. 13)"},
+        "fps": round(1000.0 / ms_step, 2),
+        "mde_cost_aggregate": round(W * H * D / (t_ca * 1e-3) * 1e-6, 2),
+        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "wall_s_timed": round(wall, 4),
+        "roofline": {"kernel": "aggregate", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "flops_per_launch": agg_flops, "avg_launch_ms": round(agg_ms, 5)},
+        "library": _lib.LIB_PATH,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, a.cpu_rows)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

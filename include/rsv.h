@@ -1,0 +1,171 @@
+/*
+ * rsv.h -- C ABI of the road-surface stereo library (gfx950 / MI355X).
+ *
+ * The library computes the dense stereo path of Fan et al., "Real-Time Stereo
+ * Vision for Road Surface 3-D Reconstruction" (arXiv 1807.07433): the perspective
+ * warp of the target image (Sec. II-A), ZNCC reference and target cost volumes
+ * (Sec. II-B.1, Eq. 3-5), bilateral cost aggregation (Sec. II-B.2, Eq. 8-10),
+ * winner-take-all with the left-right check (Sec. II-B.3/4, Eq. 11), parabola
+ * subpixel refinement (Eq. 12), post-processing (Sec. II-C) and triangulation
+ * (Sec. II-D).  Two further forms sit on the same kernels: a batched, persistent,
+ * fused form over many pairs of uneven size and disparity range, and the adjoint
+ * of the aggregated reference cost for gradient-based refinement of the plane.
+ *
+ * Conventions for every call
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or torch tensors) unless
+ *     a comment says "host".  The caller owns every buffer; stateless calls never
+ *     allocate or free.  Only a batch plan owns device memory (see rsv_batch_*).
+ *   - Images are row-major [height][pitch] with pitch >= width (in elements).
+ *     Volumes are dense row-major [D][height][width] float32; maps are dense
+ *     [height][width].
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls only enqueue
+ *     work and return; results are visible after the caller synchronises.
+ *   - Arguments are validated on the host before anything is launched; a call
+ *     that returns an error has launched nothing.  Kernel faults surface at the
+ *     caller's next synchronisation.  Stateless calls are re-entrant.
+ *   - Return value: RSV_OK (0) or a negative rsv_status.
+ */
+#ifndef RSV_H_
+#define RSV_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSV_OK = 0,
+  RSV_E_NULL = -1,   /* a required pointer is NULL                                   */
+  RSV_E_SHAPE = -2,  /* size out of range: H or W < block width, D < 1 or D > RSV_MAX_D,
+                        pitch < width, image sizes disagree                          */
+  RSV_E_PARAM = -3,  /* radius unsupported, gamma <= 0, sigma_min < 0, threshold < 0  */
+  RSV_E_DTYPE = -4,  /* unknown or unsupported image element type                    */
+  RSV_E_ALIGN = -5,  /* pointer not aligned to its element size                      */
+  RSV_E_HIP = -6,    /* a HIP runtime call failed; see rsv_last_hip_error()          */
+  RSV_E_NOMEM = -7   /* device allocation failed (batch plans only)                  */
+} rsv_status;
+
+typedef enum { RSV_U8 = 0, RSV_F32 = 1 } rsv_dtype;
+
+enum {
+  RSV_MAX_D = 512,          /* largest residual disparity search range               */
+  RSV_MIN_BLOCK_RADIUS = 1, /* NCC block radius range (block width 2r+1: 3x3 .. 9x9) */
+  RSV_MAX_BLOCK_RADIUS = 4,
+  RSV_MIN_AGG_RADIUS = 1,   /* bilateral window radius range (3x3 .. 13x13)          */
+  RSV_MAX_AGG_RADIUS = 6
+};
+
+/* An image in device memory: element (v, u) is at data[v * pitch + u]. */
+typedef struct {
+  const void* data;
+  int32_t dtype;   /* rsv_dtype: uint8 grey levels or float32 on the same 0..255 scale */
+  int32_t height;
+  int32_t width;
+  int64_t pitch;   /* elements between row starts */
+} rsv_image;
+
+/* Warp plane: shift s(u, v) = a0 + a1*v + a2*u - delta pixels (Eq. 2 gives
+ * a0 = alpha0, a1 = alpha1; a2 is the u-slope left by the road's roll, Sec. II-A;
+ * delta keeps the residual disparities non-negative). */
+typedef struct {
+  double a0, a1, a2, delta;
+} rsv_plane;
+
+/* Rectified pinhole pair (Sec. II-D): focal length f and principal point (u0, v0)
+ * in pixels, baseline in metres. */
+typedef struct {
+  double f, baseline, u0, v0;
+} rsv_camera;
+
+/* Method parameters (Sec. II-B).  gamma_r applies to intensities divided by 255. */
+typedef struct {
+  int32_t D;             /* residual disparity search range, d = 0 .. D-1         */
+  int32_t block_radius;  /* NCC block radius (block width 2*block_radius+1)       */
+  int32_t agg_radius;    /* bilateral window radius                                */
+  int32_t lr_threshold;  /* left-right check tolerance in pixels (0 = Eq. 11 exact) */
+  float gamma_d;         /* spatial parameter of Eq. 9                             */
+  float gamma_r;         /* range parameter of Eq. 10                              */
+  float sigma_min;       /* block std-dev below which the correlation is 0         */
+} rsv_params;
+
+/* ------------------------------------------------------------------ plain path */
+
+/* Perspective warp of the target image into the reference view (Sec. II-A, last
+ * paragraph).  warped[v][u] = linear interpolation of row v of `right` at column
+ * u - s(u, v), clamp-to-edge, written I0 + f*(I1 - I0).
+ *   right   target image, u8 or f32, any pitch
+ *   warped  out, float32 [H][W] dense
+ * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE (H or W < 1, pitch < W). */
+int rsv_warp(rsv_image right, rsv_plane plane, float* warped, void* stream);
+
+/* ZNCC cost volumes (Sec. II-B.1, Eq. 3-5).  With clamp-to-edge blocks B of width
+ * 2*block_radius+1:
+ *   cost_ref[d][v][u] = zncc(B_left(u, v), B_warped(u - d, v))
+ *   cost_tar[d][v][x] = zncc(B_left(x + d, v), B_warped(x, v))
+ * so cost_tar[d][v][x] == cost_ref[d][v][x + d] bit for bit wherever x + d < W
+ * (the identity stated after Eq. 5); beyond that the left block reads are clamped.
+ * The correlation is 0 where either block std-dev is below sigma_min.
+ *   left      reference image, u8 or f32
+ *   warped    float32 [H][W] dense (output of rsv_warp)
+ *   cost_ref  out, float32 [D][H][W]
+ *   cost_tar  out, float32 [D][H][W], or NULL to skip the target volume
+ * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE, RSV_E_PARAM (block_radius,
+ * sigma_min), RSV_E_ALIGN. */
+int rsv_cost_volume(rsv_image left, const float* warped, const rsv_params* p,
+                    float* cost_ref, float* cost_tar, void* stream);
+
+/* Bilateral cost aggregation (Sec. II-B.2, Eq. 8-10) of one volume:
+ *   agg[d][v][u] = sum_q w(p, q) cost[d][q] / sum_q w(p, q),  p = (u, v),
+ *   w = exp(-|q - p|^2 / gamma_d^2) * exp(-((g(q) - g(p)) / 255)^2 / gamma_r^2)
+ * over the (2*agg_radius+1)^2 window; taps outside the image are skipped.  Call it
+ * once per volume: guide = left image for cost_ref, warped image for cost_tar.
+ *   cost   float32 [D][H][W];  guide  u8 or f32 image of the same H, W
+ *   agg    out, float32 [D][H][W] (must not alias cost)
+ * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE, RSV_E_PARAM (agg_radius, gammas),
+ * RSV_E_ALIGN. */
+int rsv_aggregate(const float* cost, rsv_image guide, const rsv_params* p, float* agg,
+                  void* stream);
+
+/* Disparity selection and refinement (Sec. II-B.3 and II-B.4):
+ *   disp_ref = argmax_d agg_ref, disp_tar = argmax_d agg_tar (ties -> lowest d);
+ *   valid    = (u - disp_ref >= 0) && |disp_ref - disp_tar(u - disp_ref, v)| <= lr_threshold
+ *              (Eq. 11 with a tolerance);
+ *   disp_sub = d + (a(d-1) - a(d+1)) / (2a(d-1) + 2a(d+1) - 4a(d)) on agg_ref (Eq. 12),
+ *              d itself at d = 0 or D-1.
+ *   agg_ref, agg_tar  float32 [D][H][W]
+ *   disp_ref, disp_tar  out, int32 [H][W];  disp_sub out, float32 [H][W]
+ *   valid    out, uint8 [H][W] (1 = passes the check)
+ *   top2     out, float32 [2][H][W]: best and second-best agg_ref value, or NULL
+ * Errors: RSV_E_NULL, RSV_E_SHAPE (W > 16384), RSV_E_PARAM, RSV_E_ALIGN. */
+int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t height,
+                        int32_t width, const rsv_params* p, int32_t* disp_ref,
+                        int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
+                        void* stream);
+
+/* Post-processing (Sec. II-C) and 3-D reconstruction (Sec. II-D):
+ *   disp_final = disp_sub + s(u - disp_sub, v)            (every pixel)
+ *   xyz[v][u]  = (x, y, z), z = f*baseline/disp_final, x = (u-u0) z/f, y = (v-v0) z/f,
+ *                NaN where valid == 0 or disp_final <= 0.
+ *   disp_final out, float32 [H][W];  xyz out, float32 [H][W][3] (either may be NULL)
+ * Errors: RSV_E_NULL, RSV_E_SHAPE, RSV_E_PARAM (f or baseline <= 0). */
+int rsv_triangulate(const float* disp_sub, const uint8_t* valid, int32_t height,
+                    int32_t width, rsv_plane plane, rsv_camera cam, float* disp_final,
+                    float* xyz, void* stream);
+
+/* --------------------------------------------------------------- diagnostics */
+
+/* Text for a status code (static storage, never NULL). */
+const char* rsv_status_string(int status);
+
+/* hipError_t of the last failing HIP call made by this thread (0 if none). */
+int rsv_last_hip_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int rsv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSV_H_ */

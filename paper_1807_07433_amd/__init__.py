@@ -1,0 +1,13 @@
+"""Road-surface dense stereo on MI355X (gfx950).
+
+Hand-written HIP kernels behind a C ABI (include/rsv.h, librsv.so) for the path of
+Fan et al., arXiv 1807.07433: perspective warp, ZNCC reference/target cost
+volumes, bilateral cost aggregation, WTA with left-right check, parabola subpixel
+refinement, post-processing and triangulation.  This package is the thin Python
+binding; PyTorch supplies device memory and streams.
+"""
+from ._lib import RsvError, load, LIB_PATH  # noqa: F401
+from .ops import (StereoParams, aggregate, cost_volume, image, reconstruct,  # noqa: F401
+                  select_subpixel, triangulate, warp)
+
+__version__ = "0.1.0"

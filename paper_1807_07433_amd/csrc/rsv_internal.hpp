@@ -1,0 +1,77 @@
+// Internal helpers shared by the HIP translation units of librsv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsv.h"
+
+namespace rsv {
+
+// ------------------------------------------------------------------ host side
+void set_hip_error(hipError_t e);
+
+// Records the launch status of the last kernel; returns RSV_OK or RSV_E_HIP.
+inline int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RSV_E_HIP;
+  }
+  return RSV_OK;
+}
+
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+inline int validate_image(const rsv_image& im) {
+  if (!im.data) return RSV_E_NULL;
+  if (im.dtype != RSV_U8 && im.dtype != RSV_F32) return RSV_E_DTYPE;
+  if (im.height < 1 || im.width < 1 || im.pitch < im.width) return RSV_E_SHAPE;
+  if (im.dtype == RSV_F32 && !aligned(im.data, 4)) return RSV_E_ALIGN;
+  return RSV_OK;
+}
+
+inline int validate_d(const rsv_params* p) {
+  if (!p) return RSV_E_NULL;
+  if (p->D < 1 || p->D > RSV_MAX_D) return RSV_E_SHAPE;
+  return RSV_OK;
+}
+
+inline int validate_cost_params(const rsv_params* p) {
+  if (int s = validate_d(p)) return s;
+  if (p->block_radius < RSV_MIN_BLOCK_RADIUS || p->block_radius > RSV_MAX_BLOCK_RADIUS)
+    return RSV_E_PARAM;
+  if (!(p->sigma_min >= 0.f)) return RSV_E_PARAM;
+  return RSV_OK;
+}
+
+inline int validate_agg_params(const rsv_params* p) {
+  if (int s = validate_d(p)) return s;
+  if (p->agg_radius < RSV_MIN_AGG_RADIUS || p->agg_radius > RSV_MAX_AGG_RADIUS) return RSV_E_PARAM;
+  if (!(p->gamma_d > 0.f) || !(p->gamma_r > 0.f)) return RSV_E_PARAM;
+  return RSV_OK;
+}
+
+inline int validate_select_params(const rsv_params* p) {
+  if (int s = validate_d(p)) return s;
+  if (p->lr_threshold < 0) return RSV_E_PARAM;
+  return RSV_OK;
+}
+
+inline int validate_all_params(const rsv_params* p) {
+  if (int s = validate_cost_params(p)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  return validate_select_params(p);
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ----------------------------------------------------------------- device side
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+template <typename T>
+__device__ __forceinline__ float pixel(const T* img, int64_t pitch, int v, int u) {
+  return static_cast<float>(img[static_cast<int64_t>(v) * pitch + u]);
+}
+
+}  // namespace rsv

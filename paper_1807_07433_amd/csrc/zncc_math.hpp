@@ -1,0 +1,72 @@
+// ZNCC arithmetic shared by the plain cost kernel and the fused batch kernel
+// (Sec. II-B.1, Eq. 3-5).  With n = (2r+1)^2, S = sum of a block and Q = sum of
+// squares, e = sqrt(n Q - S^2) = n * sigma.  For left block values l_i and
+// target block values r_i:
+//     c = sum_i (n l_i - S_l) r_i / (e_l e_r)
+// which is Eq. 3 rewritten with the left block centred (the centred values sum to
+// zero, so mu_r drops out).  For uint8 images n l_i - S_l is an exact integer.
+// Any per-entry constant k may be subtracted from the r_i without changing the
+// sum; subtracting the left block mean keeps the FP32 products small.
+#pragma once
+
+#include "rsv_internal.hpp"
+
+namespace rsv {
+
+// 1 / e, or 0 when the block std-dev e / n is below sigma_min.
+__device__ __forceinline__ float inv_block_norm(double n, double S, double Q, float sigma_min) {
+  const double e2 = n * Q - S * S;
+  if (!(e2 > 0.0)) return 0.f;
+  const double e = sqrt(e2);
+  if (e < n * static_cast<double>(sigma_min)) return 0.f;
+  return static_cast<float>(1.0 / e);
+}
+
+// Left block of width K = 2R+1 read from a row-major tile: produces the centred
+// values n*l - S (FP32), the shift constant S/n and 1/e_l.
+template <int R>
+struct LeftBlock {
+  static constexpr int K = 2 * R + 1;
+  static constexpr int N = K * K;
+  float c[K][K];
+  float shift;
+  float inv;
+
+  __device__ __forceinline__ void load(const float* tile, int stride, float sigma_min) {
+    double S = 0.0, Q = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float x = tile[j * stride + k];
+        c[j][k] = x;
+        S += static_cast<double>(x);
+        Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
+      }
+    inv = inv_block_norm(static_cast<double>(N), S, Q, sigma_min);
+    shift = static_cast<float>(S / N);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        c[j][k] = static_cast<float>(static_cast<double>(N) * static_cast<double>(c[j][k]) - S);
+  }
+};
+
+// 1/e_r of the target block whose top-left corner is tile[0].
+template <int R>
+__device__ __forceinline__ float target_inv(const float* tile, int stride, float sigma_min) {
+  constexpr int K = 2 * R + 1;
+  double S = 0.0, Q = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double x = static_cast<double>(tile[j * stride + k]);
+      S += x;
+      Q = fma(x, x, Q);
+    }
+  return inv_block_norm(static_cast<double>(K * K), S, Q, sigma_min);
+}
+
+}  // namespace rsv

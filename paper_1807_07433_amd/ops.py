@@ -1,0 +1,185 @@
+"""Torch-tensor front end of the C ABI: checks device, dtype and layout, passes
+device pointers and the current HIP stream, raises RsvError on a bad status.
+Every step of the path runs in librsv's kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import Camera, Image, Params, Plane, RsvError, check, load
+
+
+@dataclass(frozen=True)
+class StereoParams:
+    """Method parameters (Sec. II-B); field names match the C struct."""
+    D: int
+    block_radius: int = 3
+    agg_radius: int = 5
+    gamma_d: float = 4.0
+    gamma_r: float = 0.1
+    lr_threshold: int = 1
+    sigma_min: float = 1e-2
+
+
+def _params(p) -> Params:
+    return Params(int(p.D), int(p.block_radius), int(p.agg_radius), int(p.lr_threshold),
+                  float(p.gamma_d), float(p.gamma_r), float(p.sigma_min))
+
+
+def _plane(pl) -> Plane:
+    t = pl.as_tuple() if hasattr(pl, "as_tuple") else tuple(pl)
+    return Plane(*(float(x) for x in t))
+
+
+def _camera(cam) -> Camera:
+    if hasattr(cam, "f"):
+        return Camera(float(cam.f), float(cam.baseline), float(cam.u0), float(cam.v0))
+    return Camera(*(float(x) for x in cam))
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def image(t: torch.Tensor, name: str = "image") -> Image:
+    """rsv_image over a 2-D uint8 / float32 GPU tensor (row stride may exceed width)."""
+    _dev(t, name, (torch.uint8, torch.float32))
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+    dt = _lib.RSV_U8 if t.dtype == torch.uint8 else _lib.RSV_F32
+    return Image(t.data_ptr(), dt, t.shape[0], t.shape[1], t.stride(0))
+
+
+def _contig(t, name, dtype, shape):
+    _dev(t, name, dtype, shape)
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def warp(right: torch.Tensor, plane, out: torch.Tensor | None = None) -> torch.Tensor:
+    lib = load()
+    H, W = right.shape
+    out = out if out is not None else torch.empty((H, W), dtype=torch.float32, device=right.device)
+    _contig(out, "warped", torch.float32, (H, W))
+    check(lib.rsv_warp(image(right, "right"), _plane(plane), out.data_ptr(), _stream(right.device)),
+          "rsv_warp")
+    return out
+
+
+def cost_volume(left: torch.Tensor, warped: torch.Tensor, params, want_tar: bool = True,
+                out_ref: torch.Tensor | None = None, out_tar: torch.Tensor | None = None):
+    lib = load()
+    H, W = left.shape
+    D = int(params.D)
+    _contig(warped, "warped", torch.float32, (H, W))
+    shp = (D, H, W)
+    cref = out_ref if out_ref is not None else torch.empty(shp, dtype=torch.float32, device=left.device)
+    _contig(cref, "cost_ref", torch.float32, shp)
+    ctar = None
+    if want_tar:
+        ctar = out_tar if out_tar is not None else torch.empty(shp, dtype=torch.float32, device=left.device)
+        _contig(ctar, "cost_tar", torch.float32, shp)
+    p = _params(params)
+    check(lib.rsv_cost_volume(image(left, "left"), warped.data_ptr(), C.byref(p), cref.data_ptr(),
+                              _ptr(ctar), _stream(left.device)), "rsv_cost_volume")
+    return cref, ctar
+
+
+def aggregate(cost: torch.Tensor, guide: torch.Tensor, params,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    lib = load()
+    D, H, W = cost.shape
+    _contig(cost, "cost", torch.float32, (int(params.D), H, W))
+    if tuple(guide.shape) != (H, W):
+        raise ValueError("guide must match the volume's H, W")
+    out = out if out is not None else torch.empty_like(cost)
+    _contig(out, "agg", torch.float32, (D, H, W))
+    p = _params(params)
+    check(lib.rsv_aggregate(cost.data_ptr(), image(guide, "guide"), C.byref(p), out.data_ptr(),
+                            _stream(cost.device)), "rsv_aggregate")
+    return out
+
+
+def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor, params, want_top2: bool = False,
+                    out: dict | None = None) -> dict:
+    lib = load()
+    D, H, W = agg_ref.shape
+    _contig(agg_ref, "agg_ref", torch.float32, (int(params.D), H, W))
+    _contig(agg_tar, "agg_tar", torch.float32, (D, H, W))
+    dev = agg_ref.device
+    o = dict(out) if out else {}
+    o.setdefault("disp_ref", torch.empty((H, W), dtype=torch.int32, device=dev))
+    o.setdefault("disp_tar", torch.empty((H, W), dtype=torch.int32, device=dev))
+    o.setdefault("disp_sub", torch.empty((H, W), dtype=torch.float32, device=dev))
+    o.setdefault("valid", torch.empty((H, W), dtype=torch.uint8, device=dev))
+    if want_top2:
+        o.setdefault("top2", torch.empty((2, H, W), dtype=torch.float32, device=dev))
+    _contig(o["disp_ref"], "disp_ref", torch.int32, (H, W))
+    _contig(o["disp_tar"], "disp_tar", torch.int32, (H, W))
+    _contig(o["disp_sub"], "disp_sub", torch.float32, (H, W))
+    _contig(o["valid"], "valid", torch.uint8, (H, W))
+    top2 = o.get("top2")
+    if top2 is not None:
+        _contig(top2, "top2", torch.float32, (2, H, W))
+    p = _params(params)
+    check(lib.rsv_select_subpixel(agg_ref.data_ptr(), agg_tar.data_ptr(), H, W, C.byref(p),
+                                  o["disp_ref"].data_ptr(), o["disp_tar"].data_ptr(),
+                                  o["disp_sub"].data_ptr(), o["valid"].data_ptr(), _ptr(top2),
+                                  _stream(dev)), "rsv_select_subpixel")
+    return o
+
+
+def triangulate(disp_sub: torch.Tensor, valid: torch.Tensor, plane, camera,
+                out_disp: torch.Tensor | None = None, out_xyz: torch.Tensor | None = None):
+    lib = load()
+    H, W = disp_sub.shape
+    _contig(disp_sub, "disp_sub", torch.float32, (H, W))
+    _contig(valid, "valid", torch.uint8, (H, W))
+    dev = disp_sub.device
+    dfin = out_disp if out_disp is not None else torch.empty((H, W), dtype=torch.float32, device=dev)
+    xyz = out_xyz if out_xyz is not None else torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    _contig(dfin, "disp_final", torch.float32, (H, W))
+    _contig(xyz, "xyz", torch.float32, (H, W, 3))
+    check(lib.rsv_triangulate(disp_sub.data_ptr(), valid.data_ptr(), H, W, _plane(plane),
+                              _camera(camera), dfin.data_ptr(), xyz.data_ptr(), _stream(dev)),
+          "rsv_triangulate")
+    return dfin, xyz
+
+
+def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
+                want_top2: bool = False) -> dict:
+    """The plain path, one C-ABI call per stage on the current stream (Fig. 1):
+    warp -> both cost volumes -> aggregation of each -> WTA + L-R + subpixel ->
+    post-processing + 3-D points."""
+    wp = warp(right, plane)
+    cref, ctar = cost_volume(left, wp, params)
+    aref = aggregate(cref, left, params)
+    atar = aggregate(ctar, wp, params)
+    sel = select_subpixel(aref, atar, params, want_top2=want_top2)
+    dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
+    out = dict(warped=wp, cost_ref=cref, cost_tar=ctar, agg_ref=aref, agg_tar=atar,
+               disp_final=dfin, xyz=xyz)
+    out.update(sel)
+    return out
+
+
+__all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "aggregate", "select_subpixel",
+           "triangulate", "reconstruct", "image", "load"]

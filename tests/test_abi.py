@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/rsv.h declares, and rejects bad arguments on the host before any launch."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1807_07433_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+FAKE = 0x1000  # non-NULL, aligned; never dereferenced because validation fails first
+
+
+def declared():
+    names = set()
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(rsv_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("librsv.so is not built; run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "rsv_cost_volume" in names and len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header(lib):
+    assert set(_lib.declared_symbols()) <= set(declared())
+
+
+def test_status_strings_and_version(lib):
+    for s in range(-7, 1):
+        assert lib.rsv_status_string(s)
+    assert lib.rsv_version() >= 100
+    assert lib.rsv_last_hip_error() == 0
+
+
+def _params(**kw):
+    base = dict(D=32, block_radius=3, agg_radius=4, lr_threshold=1, gamma_d=3.0, gamma_r=0.1,
+                sigma_min=0.01)
+    base.update(kw)
+    return _lib.Params(**base)
+
+
+def _img(h=32, w=48, dtype=_lib.RSV_U8, pitch=None, data=FAKE):
+    return _lib.Image(data, dtype, h, w, pitch if pitch is not None else w)
+
+
+def test_warp_validation(lib):
+    pl = _lib.Plane(1.0, 0.1, 0.0, 2.0)
+    assert lib.rsv_warp(_img(data=None), pl, FAKE, None) == -1
+    assert lib.rsv_warp(_img(), pl, None, None) == -1
+    assert lib.rsv_warp(_img(dtype=7), pl, FAKE, None) == -4
+    assert lib.rsv_warp(_img(h=0), pl, FAKE, None) == -2
+    assert lib.rsv_warp(_img(pitch=10), pl, FAKE, None) == -2
+    assert lib.rsv_warp(_img(dtype=_lib.RSV_F32, data=FAKE + 2), pl, FAKE, None) == -5
+    assert lib.rsv_warp(_img(), pl, FAKE + 1, None) == -5
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(D=0), -2), (dict(D=513), -2), (dict(block_radius=0), -3), (dict(block_radius=5), -3),
+    (dict(sigma_min=-1.0), -3)])
+def test_cost_validation(lib, kw, status):
+    p = _params(**kw)
+    assert lib.rsv_cost_volume(_img(), FAKE, C.byref(p), FAKE, FAKE, None) == status
+
+
+def test_cost_validation_shapes_and_nulls(lib):
+    p = _params()
+    assert lib.rsv_cost_volume(_img(h=6), FAKE, C.byref(p), FAKE, FAKE, None) == -2
+    assert lib.rsv_cost_volume(_img(), None, C.byref(p), FAKE, FAKE, None) == -1
+    assert lib.rsv_cost_volume(_img(), FAKE, None, FAKE, FAKE, None) == -1
+    assert lib.rsv_cost_volume(_img(), FAKE, C.byref(p), None, FAKE, None) == -1
+    assert lib.rsv_cost_volume(_img(), FAKE, C.byref(p), FAKE, FAKE + 2, None) == -5
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(agg_radius=0), -3), (dict(agg_radius=7), -3), (dict(gamma_d=0.0), -3),
+    (dict(gamma_r=-1.0), -3), (dict(gamma_r=float("nan")), -3), (dict(D=-3), -2)])
+def test_aggregate_validation(lib, kw, status):
+    p = _params(**kw)
+    assert lib.rsv_aggregate(FAKE, _img(), C.byref(p), FAKE + 64, None) == status
+
+
+def test_aggregate_rejects_aliasing(lib):
+    p = _params()
+    assert lib.rsv_aggregate(FAKE, _img(), C.byref(p), FAKE, None) == -3
+
+
+def test_select_validation(lib):
+    p = _params()
+    ok = [FAKE] * 6
+    assert lib.rsv_select_subpixel(FAKE, FAKE, 0, 10, C.byref(p), *ok, None) == -2
+    assert lib.rsv_select_subpixel(FAKE, FAKE, 10, 16385, C.byref(p), *ok, None) == -2
+    assert lib.rsv_select_subpixel(None, FAKE, 10, 10, C.byref(p), *ok, None) == -1
+    bad = _params(lr_threshold=-1)
+    assert lib.rsv_select_subpixel(FAKE, FAKE, 10, 10, C.byref(bad), *ok, None) == -3
+
+
+def test_triangulate_validation(lib):
+    pl = _lib.Plane(1.0, 0.1, 0.0, 2.0)
+    cam = _lib.Camera(700.0, 0.12, 10.0, 10.0)
+    assert lib.rsv_triangulate(None, FAKE, 10, 10, pl, cam, FAKE, FAKE, None) == -1
+    assert lib.rsv_triangulate(FAKE, FAKE, 10, 10, pl, cam, None, None, None) == -1
+    assert lib.rsv_triangulate(FAKE, FAKE, 10, 10, pl, _lib.Camera(0.0, 0.12, 1, 1), FAKE, FAKE,
+                               None) == -3
+    assert lib.rsv_triangulate(FAKE, FAKE, -1, 10, pl, cam, FAKE, FAKE, None) == -2

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Small cases are compared element by element on every stage; their shapes span
+several tiles and leave ragged tails in every tiled dimension.  Full-size road
+workloads are compared on sampled entries that the oracle computes one by one,
+plus properties that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import stereo as S
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+# (H, W, D, block_radius, agg_radius, seed, dtype, roll a2)
+SMALL = [
+    (37, 150, 31, 3, 4, 11, "u8", 0.0),
+    (70, 201, 64, 3, 5, 12, "u8", 0.004),
+    (45, 133, 17, 1, 1, 13, "u8", 0.0),
+    (29, 97, 9, 2, 6, 14, "f32", -0.01),
+    (52, 141, 40, 4, 3, 15, "u8", 0.0),
+    (24, 70, 1, 3, 2, 16, "u8", 0.0),
+    (9, 9, 5, 4, 6, 17, "u8", 0.0),
+]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _camera(case):
+    c = case.camera
+    return (c.f, c.baseline, c.u0, c.v0)
+
+
+def _oracle_all(case, plane):
+    p, pr = case.pair, case.params
+    return S.reconstruct(p.left, p.right, plane.as_tuple(), _camera(case), pr.D, pr.block_radius,
+                         pr.agg_radius, pr.gamma_d, pr.gamma_r, pr.lr_threshold, pr.sigma_min)
+
+
+def _den(A, d):
+    D, H, W = A.shape
+    v, u = np.mgrid[0:H, 0:W]
+    dm = np.clip(d - 1, 0, D - 1)
+    dp = np.clip(d + 1, 0, D - 1)
+    return 2 * A[dm, v, u] + 2 * A[dp, v, u] - 4 * A[d, v, u]
+
+
+def _check_selection(tag, sel, ref, AL, AR):
+    """Integer disparities (both maps), subpixel and validity against the oracle."""
+    D, H, W = AL.shape
+    v, u = np.mgrid[0:H, 0:W]
+    dref = P.to_np(sel["disp_ref"]).astype(np.int64)
+    dtar = P.to_np(sel["disp_tar"]).astype(np.int64)
+    P.check_disparity(f"{tag} disp_ref", dref, ref["disp_ref"], AL[dref, v, u], AL.max(0))
+    P.check_disparity(f"{tag} disp_tar", dtar, ref["disp_tar"], AR[dtar, v, u], AR.max(0))
+    agree = dref == ref["disp_ref"]
+    interior = (ref["disp_ref"] > 0) & (ref["disp_ref"] < D - 1)
+    P.check_subpixel(f"{tag} disp_sub", P.to_np(sel["disp_sub"]), ref["disp_sub"], agree & interior,
+                     np.where(interior, _den(AL, ref["disp_ref"]), -1.0))
+    assert np.array_equal(P.to_np(sel["disp_sub"])[agree & ~interior],
+                          ref["disp_sub"][agree & ~interior].astype(np.float32))
+    x = np.clip(u - ref["disp_ref"], 0, W - 1)
+    tar_agree = (dtar == ref["disp_tar"])[v, x]
+    m = agree & tar_agree
+    assert np.array_equal(P.to_np(sel["valid"]).astype(bool)[m], ref["valid"][m]), f"{tag} valid"
+
+
+@pytest.mark.parametrize("H,W,D,r,rho,seed,dtype,a2", SMALL)
+def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
+    rsv = rsv_gpu
+    case = synth.small_case(H, W, D, r, rho, seed, dtype=dtype)
+    pl = synth.Plane(case.plane.a0, case.plane.a1, a2, case.plane.delta)
+    _say(f"[small] H={H} W={W} D={D} r={r} rho={rho} seed={seed} {dtype} a2={a2}")
+    ref = _oracle_all(case, pl)
+    prm = case.params
+    L, R = _gpu(case.pair.left), _gpu(case.pair.right)
+
+    _say("  rsv_warp")
+    wp = rsv.warp(R, pl)
+    P.check_close("warped", P.to_np(wp), ref["warped"], P.COST_TOL)
+
+    _say("  rsv_cost_volume")
+    cref, ctar = rsv.cost_volume(L, wp, prm)
+    torch.cuda.synchronize()
+    cref_n, ctar_n = P.to_np(cref), P.to_np(ctar)
+    P.check_close("cost_ref", cref_n, ref["cost_ref"], P.COST_TOL)
+    P.check_close("cost_tar", ctar_n, ref["cost_tar"], P.COST_TOL)
+    for d in range(D):  # identity stated after Eq. 5, bit for bit
+        assert np.array_equal(ctar_n[d, :, :W - d], cref_n[d, :, d:])
+
+    _say("  rsv_aggregate x2")
+    aref = rsv.aggregate(cref, L, prm)
+    atar = rsv.aggregate(ctar, wp, prm)
+    P.check_close("agg_ref", P.to_np(aref), ref["agg_ref"], P.AGG_TOL)
+    P.check_close("agg_tar", P.to_np(atar), ref["agg_tar"], P.AGG_TOL)
+    # aggregation alone, fed the oracle's volume
+    aref_iso = rsv.aggregate(_gpu(ref["cost_ref"].astype(np.float32)), L, prm)
+    P.check_close("agg_ref(oracle cost)", P.to_np(aref_iso), ref["agg_ref"], P.AGG_TOL)
+
+    _say("  rsv_select_subpixel")
+    sel = rsv.select_subpixel(aref, atar, prm, want_top2=True)
+    _check_selection("end-to-end", sel, ref, ref["agg_ref"], ref["agg_tar"])
+    top2 = P.to_np(sel["top2"])
+    P.check_close("best", top2[0], ref["best"], P.AGG_TOL)
+    if D > 1:
+        P.check_close("second", top2[1], ref["second"], P.AGG_TOL)
+    # selection alone, fed the oracle's aggregated volumes rounded to float32
+    AL32 = ref["agg_ref"].astype(np.float32)
+    AR32 = ref["agg_tar"].astype(np.float32)
+    sel_iso = rsv.select_subpixel(_gpu(AL32), _gpu(AR32), prm)
+    r32 = dict(disp_ref=S.wta(AL32.astype(np.float64))[0], disp_tar=S.wta(AR32.astype(np.float64))[0])
+    assert np.array_equal(P.to_np(sel_iso["disp_ref"]), r32["disp_ref"])
+    assert np.array_equal(P.to_np(sel_iso["disp_tar"]), r32["disp_tar"])
+    assert np.array_equal(P.to_np(sel_iso["valid"]).astype(bool),
+                          S.lr_check(r32["disp_ref"], r32["disp_tar"], prm.lr_threshold))
+    sub32 = S.subpixel(AL32.astype(np.float64), r32["disp_ref"])
+    keep = np.abs(_den(AL32.astype(np.float64), r32["disp_ref"])) >= P.DEN_EXEMPT
+    assert np.max(np.abs(P.to_np(sel_iso["disp_sub"]) - sub32)[keep], initial=0.0) < P.SUB_TOL
+
+    _say("  rsv_triangulate")
+    dfin, xyz = rsv.triangulate(sel["disp_sub"], sel["valid"], pl, _camera(case))
+    ds_gpu = P.to_np(sel["disp_sub"]).astype(np.float64)
+    df_ref = S.postprocess(ds_gpu, pl.as_tuple())
+    P.check_close("disp_final", P.to_np(dfin), df_ref, 1e-4)
+    xyz_ref = S.triangulate(df_ref, P.to_np(sel["valid"]).astype(bool), _camera(case))
+    xyz_g = P.to_np(xyz)
+    assert np.array_equal(np.isnan(xyz_g), np.isnan(xyz_ref))
+    ok = ~np.isnan(xyz_ref)
+    assert np.allclose(xyz_g[ok], xyz_ref[ok], rtol=1e-5, atol=1e-6)
+
+
+def test_pitched_inputs_match_dense(rsv_gpu):
+    rsv = rsv_gpu
+    case = synth.small_case(40, 120, 16, 3, 4, 21)
+    prm = case.params
+    L = _gpu(case.pair.left)
+    R = _gpu(case.pair.right)
+    Lp = torch.zeros((40, 200), dtype=torch.uint8, device="cuda")[:, 30:150]
+    Rp = torch.zeros((40, 200), dtype=torch.uint8, device="cuda")[:, 7:127]
+    Lp.copy_(L)
+    Rp.copy_(R)
+    _say("[pitched] warp + cost + aggregate with row pitch 200")
+    a = rsv.reconstruct(L, R, case.plane, _camera(case), prm)
+    b = rsv.reconstruct(Lp, Rp, case.plane, _camera(case), prm)
+    for k in ("warped", "cost_ref", "cost_tar", "agg_ref", "agg_tar", "disp_ref", "disp_sub", "valid"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_flat_images_give_zero_costs_and_lowest_d(rsv_gpu):
+    rsv = rsv_gpu
+    L = torch.full((20, 64), 90, dtype=torch.uint8, device="cuda")
+    R = torch.full((20, 64), 90, dtype=torch.uint8, device="cuda")
+    prm = rsv.StereoParams(D=8, block_radius=2, agg_radius=2, gamma_d=2.0)
+    _say("[flat] constant images")
+    out = rsv.reconstruct(L, R, (3.0, 0.0, 0.0, 4.0), (700.0, 0.12, 31.5, 9.5), prm, want_top2=True)
+    assert torch.count_nonzero(out["cost_ref"]) == 0 and torch.count_nonzero(out["agg_tar"]) == 0
+    assert torch.count_nonzero(out["disp_ref"]) == 0
+    assert torch.all(out["disp_sub"] == 0)
+
+
+def test_rerun_is_bitwise_deterministic(rsv_gpu):
+    rsv = rsv_gpu
+    case = synth.small_case(50, 170, 24, 3, 5, 31)
+    _say("[determinism] two runs of the plain path")
+    a = rsv.reconstruct(_gpu(case.pair.left), _gpu(case.pair.right), case.plane, _camera(case),
+                        case.params)
+    b = rsv.reconstruct(_gpu(case.pair.left), _gpu(case.pair.right), case.plane, _camera(case),
+                        case.params)
+    for k in a:
+        assert torch.equal(a[k].nan_to_num(), b[k].nan_to_num()), k
+
+
+# ------------------------------------------------------------------ full size, sampled
+def _agg_columns(cost_at, guide, us, vs, D, prm, chunk=8):
+    """Oracle aggregated values at every d for each sampled pixel: [n, D]."""
+    out = np.empty((us.size, D))
+    dd = np.arange(D)
+    for i in range(0, us.size, chunk):
+        u, v = us[i:i + chunk], vs[i:i + chunk]
+        out[i:i + chunk] = S.aggregate_entries(cost_at, guide, np.repeat(u, D), np.repeat(v, D),
+                                               np.tile(dd, u.size), prm.agg_radius, prm.gamma_d,
+                                               prm.gamma_r).reshape(u.size, D)
+    return out
+
+
+def _sampled_full(rsv, case, n_cost, n_agg, n_pix, seed):
+    p, prm = case.pair, case.params
+    H, W = p.left.shape
+    D = prm.D
+    rng = np.random.default_rng(seed)
+    L, R = _gpu(p.left), _gpu(p.right)
+    _say(f"[full] {case.name} {W}x{H} D={D}: GPU plain path")
+    out = rsv.reconstruct(L, R, case.plane, _camera(case), prm)
+    torch.cuda.synchronize()
+
+    _say("  warp (every pixel)")
+    Wp = S.warp(p.right, case.plane.as_tuple())
+    P.check_close("warped", P.to_np(out["warped"]), Wp, P.COST_TOL)
+
+    def cl(x, y, d):
+        return S.cost_entries(p.left, Wp, x, y, d, prm.block_radius, prm.sigma_min)
+
+    def cr(x, y, d):
+        return S.cost_entries(p.left, Wp, x + d, y, d, prm.block_radius, prm.sigma_min)
+
+    _say(f"  cost volumes ({n_cost} sampled entries each)")
+    u = rng.integers(0, W, n_cost)
+    v = rng.integers(0, H, n_cost)
+    d = rng.integers(0, D, n_cost)
+    gi = (torch.from_numpy(d).cuda(), torch.from_numpy(v).cuda(), torch.from_numpy(u).cuda())
+    P.check_close("cost_ref", P.to_np(out["cost_ref"][gi]), cl(u, v, d), P.COST_TOL)
+    P.check_close("cost_tar", P.to_np(out["cost_tar"][gi]), cr(u, v, d), P.COST_TOL)
+    _say("  cost identity (every entry)")
+    for dd in range(D):
+        assert torch.equal(out["cost_tar"][dd, :, :W - dd], out["cost_ref"][dd, :, dd:])
+
+    _say(f"  aggregated volumes ({n_agg} sampled entries each)")
+    u = rng.integers(0, W, n_agg)
+    v = rng.integers(0, H, n_agg)
+    d = rng.integers(0, D, n_agg)
+    gi = (torch.from_numpy(d).cuda(), torch.from_numpy(v).cuda(), torch.from_numpy(u).cuda())
+    a = S.aggregate_entries(cl, p.left, u, v, d, prm.agg_radius, prm.gamma_d, prm.gamma_r)
+    P.check_close("agg_ref", P.to_np(out["agg_ref"][gi]), a, P.AGG_TOL)
+    a = S.aggregate_entries(cr, Wp, u, v, d, prm.agg_radius, prm.gamma_d, prm.gamma_r)
+    P.check_close("agg_tar", P.to_np(out["agg_tar"][gi]), a, P.AGG_TOL)
+
+    _say(f"  selection at {n_pix} sampled pixels (oracle aggregates every d)")
+    u = rng.integers(0, W, n_pix)
+    v = rng.integers(0, H, n_pix)
+    col = _agg_columns(cl, p.left, u, v, D, prm)
+    ref_d = col.argmax(1)
+    g_d = P.to_np(out["disp_ref"][v, u]).astype(np.int64)
+    P.check_disparity("disp_ref", g_d, ref_d, col[np.arange(n_pix), g_d], col.max(1))
+    x = np.clip(u - ref_d, 0, W - 1)
+    colt = _agg_columns(cr, Wp, x, v, D, prm)
+    ref_t = colt.argmax(1)
+    g_t = P.to_np(out["disp_tar"][v, x]).astype(np.int64)
+    P.check_disparity("disp_tar", g_t, ref_t, colt[np.arange(n_pix), g_t], colt.max(1))
+    ref_valid = (u - ref_d >= 0) & (np.abs(ref_d - ref_t) <= prm.lr_threshold)
+    m = (g_d == ref_d) & (g_t == ref_t)
+    assert np.array_equal(P.to_np(out["valid"][v, u]).astype(bool)[m], ref_valid[m])
+    inner = m & (ref_d > 0) & (ref_d < D - 1)
+    i = np.arange(n_pix)
+    cm, c0, cp = col[i, np.clip(ref_d - 1, 0, D - 1)], col[i, ref_d], col[i, np.clip(ref_d + 1, 0, D - 1)]
+    sub = ref_d + (cm - cp) / np.where(inner, 2 * cm + 2 * cp - 4 * c0, 1.0)
+    P.check_subpixel("disp_sub", P.to_np(out["disp_sub"][v, u]), sub, inner,
+                     np.where(inner, 2 * cm + 2 * cp - 4 * c0, -1.0))
+    return out
+
+
+def test_full_road1280_d64_sampled(rsv_gpu):
+    _sampled_full(rsv_gpu, synth.road1280_d64(), 20000, 1500, 200, 7)
+
+
+def test_full_road1920_d128_sampled(rsv_gpu):
+    _sampled_full(rsv_gpu, synth.road1920_d128(), 10000, 600, 60, 8)
