@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--workload", default="road1280_d64",
                     choices=["road1280_d64", "road320_d32", "road1920_d128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=24, help="rows in the oracle timing sample")
+    ap.add_argument("--cpu-rows", type=int, default=64, help="rows in the oracle timing sample")
     return ap.parse_args()
 
 

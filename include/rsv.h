@@ -28,6 +28,7 @@
 #ifndef RSV_H_
 #define RSV_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -152,6 +153,43 @@ int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t heig
 int rsv_triangulate(const float* disp_sub, const uint8_t* valid, int32_t height,
                     int32_t width, rsv_plane plane, rsv_camera cam, float* disp_final,
                     float* xyz, void* stream);
+
+/* ------------------------------------------------------ differentiable form */
+
+/* Loss of the differentiable form: sum of agg_ref[disp(p)][p] over the pixels p with
+ * mask(p) != 0 and 0 <= disp(p) < D (the aggregated reference cost of Eq. 8 at the
+ * selected disparities, Sec. II-B.3).
+ *   agg_ref  float32 [D][H][W];  disp int32 [H][W];  mask uint8 [H][W]
+ *   out      device double[1], overwritten
+ * Errors: RSV_E_NULL, RSV_E_SHAPE, RSV_E_ALIGN. */
+int rsv_selected_cost_sum(const float* agg_ref, const int32_t* disp, const uint8_t* mask,
+                          int32_t height, int32_t width, int32_t D, double* out, void* stream);
+
+/* Bytes of device workspace rsv_cost_adjoint needs for an H x W pair (0 if invalid). */
+size_t rsv_cost_adjoint_workspace_bytes(int32_t height, int32_t width);
+
+/* Adjoint of the loss above with disp and mask held fixed: gradients with respect to
+ * the warp plane (a0, a1, a2) of Sec. II-A and both input images, through the warp,
+ * the ZNCC of Eq. 3-5 and the bilateral aggregation of Eq. 8-10 (weights recomputed,
+ * never stored; their dependence on the left image is included).
+ *   left, right   float32 images the forward ran on (same H, W)
+ *   plane, p      the forward's plane and parameters (D <= 256)
+ *   cost_ref      the forward's float32 [D][H][W] reference cost volume
+ *   agg_ref       the forward's float32 [D][H][W] aggregated reference volume
+ *   disp, mask    int32 / uint8 [H][W]; pixels with mask == 0 or disp outside [0, D)
+ *                 are not in the loss
+ *   grad_left, grad_right  out float32 [H][W] (dense), overwritten
+ *   grad_plane    out device double[3] = dL/d(a0, a1, a2), overwritten
+ *   loss          out device double[1] (the same sum as rsv_selected_cost_sum), or NULL
+ *   workspace     device buffer of rsv_cost_adjoint_workspace_bytes(H, W) bytes, owned
+ *                 by the caller; its contents are scratch
+ * Results are sums of float atomics: equal to rounding, not bit for bit, run to run.
+ * Errors: RSV_E_NULL, RSV_E_DTYPE (images not float32), RSV_E_SHAPE, RSV_E_PARAM,
+ * RSV_E_ALIGN. */
+int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
+                     const float* cost_ref, const float* agg_ref, const int32_t* disp,
+                     const uint8_t* mask, float* grad_left, float* grad_right,
+                     double* grad_plane, double* loss, void* workspace, void* stream);
 
 /* --------------------------------------------------------------- diagnostics */
 

@@ -52,6 +52,10 @@ _SIGNATURES = {
     "rsv_select_subpixel": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(Params), _P, _P, _P,
                                       _P, _P, _P]),
     "rsv_triangulate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, Plane, Camera, _P, _P, _P]),
+    "rsv_selected_cost_sum": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "rsv_cost_adjoint_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "rsv_cost_adjoint": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, _P, _P, _P, _P, _P,
+                                   _P, _P, _P, _P]),
     "rsv_status_string": (C.c_char_p, [C.c_int]),
     "rsv_last_hip_error": (C.c_int, []),
     "rsv_version": (C.c_int, []),

@@ -1,0 +1,93 @@
+"""Differentiable form: the aggregated reference ZNCC cost at the selected
+disparities, as a torch.autograd.Function whose backward is the hand-written
+adjoint kernel (rsv_cost_adjoint), plus a plane-refinement loop built on it.
+
+    loss = AggregatedZNCC.apply(left, right, theta, delta, params, disp, mask)
+
+theta = (a0, a1, a2) of the warp shift s = a0 + a1 v + a2 u - delta (Sec. II-A).
+The forward runs the plain path's kernels (warp, ZNCC reference volume, bilateral
+aggregation) and sums agg_ref[disp(p)][p] over mask(p) != 0.  disp and mask are held
+fixed inside one evaluation (WTA stays exact and is re-run between steps by
+`select`).  Gradients flow to left, right (float32 images) and theta.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+
+
+def _plane(theta: torch.Tensor, delta: float):
+    t = theta.detach().to("cpu", torch.float64)
+    return (float(t[0]), float(t[1]), float(t[2]), float(delta))
+
+
+class AggregatedZNCC(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, left, right, theta, delta, params, disp, mask):
+        plane = _plane(theta, delta)
+        wp = ops.warp(right, plane)
+        cref, _ = ops.cost_volume(left, wp, params, want_tar=False)
+        aref = ops.aggregate(cref, left, params)
+        loss = ops.selected_cost_sum(aref, disp, mask)
+        ctx.save_for_backward(left, right, cref, aref, disp, mask)
+        ctx.plane = plane
+        ctx.params = params
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        left, right, cref, aref, disp, mask = ctx.saved_tensors
+        gl, gr, gp, _ = ops.cost_adjoint(left, right, ctx.plane, ctx.params, cref, aref, disp, mask)
+        dtype, device = ctx.theta_meta
+        s = gout.to(torch.float64)
+        g_theta = (gp * s).to(device=device, dtype=dtype)
+        sf = s.to(torch.float32)
+        return gl * sf, gr * sf, g_theta, None, None, None, None
+
+
+def select(left, right, plane, params):
+    """Plain-path selection for the current plane: returns (disp_ref int32, mask uint8)
+    with mask = left-right valid and 0 < d < D-1 (pixels where Eq. 12 applies)."""
+    wp = ops.warp(right, plane)
+    cref, ctar = ops.cost_volume(left, wp, params)
+    aref = ops.aggregate(cref, left, params)
+    atar = ops.aggregate(ctar, wp, params)
+    sel = ops.select_subpixel(aref, atar, params)
+    d = sel["disp_ref"]
+    mask = (sel["valid"].bool() & (d > 0) & (d < int(params.D) - 1)).to(torch.uint8)
+    return d, mask
+
+
+def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, reselect_every=1,
+                 callback=None):
+    """Gradient ascent of the summed aggregated correlation over a batch of pairs.
+
+    theta0: (a0, a1, a2) starting plane.  Parameters are scaled so one unit of each moves
+    the shift by about one pixel across the image (a1 by 1/H, a2 by 1/W), then updated
+    with Adam on -loss.  d* and Omega are re-selected every `reselect_every` steps.
+    Returns (theta, history of losses)."""
+    H, W = lefts[0].shape
+    scale = torch.tensor([1.0, 1.0 / H, 1.0 / W], dtype=torch.float64)
+    z = (torch.as_tensor(theta0, dtype=torch.float64) / scale).clone().requires_grad_(True)
+    opt = torch.optim.Adam([z], lr=lr)
+    sel = None
+    hist = []
+    for it in range(steps):
+        theta = z * scale
+        plane = _plane(theta, delta)
+        if sel is None or it % reselect_every == 0:
+            sel = [select(l, r, plane, params) for l, r in zip(lefts, rights)]
+        opt.zero_grad()
+        total = 0.0
+        for (l, r), (d, m) in zip(zip(lefts, rights), sel):
+            loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m)
+            n = max(int(m.sum()), 1)
+            (-loss / n).backward()
+            total += float(loss) / n
+        opt.step()
+        hist.append(total / len(lefts))
+        if callback:
+            callback(it, (z * scale).detach(), hist[-1])
+    return (z * scale).detach(), hist

@@ -1,0 +1,419 @@
+// rsv_cost_adjoint: gradient of the differentiable form
+//     L(theta, I_l, I_r) = sum over p in Omega of A_ref(p, d*(p))
+// (aggregated reference cost of Eq. 8 at frozen disparities d* on a frozen pixel
+// set Omega) with respect to the warp plane (Sec. II-A) and both images.
+//
+// The chain rule runs through the bilateral weights (guide = left image, Eq. 10),
+// the ZNCC of Eq. 3-5 and the linear-interpolation warp:
+//   dL/dc(q, d)  = G(q, d) = sum over p in win(q), p in Omega, d*(p) = d of w(p, q) / Z(p)
+//   dL/dw(p, q)  = (c(q, d*(p)) - A(p)) / Z(p)
+//   G dc/dl_i    = a (r_i - mu_r) - b (l_i - mu_l),  G dc/dr_i = a (l_i - mu_l) - g (r_i - mu_r)
+//   with a = G / sqrt(S_ll S_rr), b = G c / S_ll, g = G c / S_rr.
+// The weights are recomputed (never stored); the forward's cost and aggregated
+// volumes supply c and A.  One block covers 16 x 8 reference pixels q: it gathers
+// G(q, .) for its pixels into private LDS columns (64 disparities at a time),
+// scatters the block gradients into LDS accumulators for the left image and the
+// warped image, then flushes them with float atomics; the warped-image gradient
+// goes through the transpose of the interpolation straight into the right image,
+// and its shift derivative -(I1 - I0) (1, v, u) into the plane gradient.
+#include "bilateral_math.hpp"
+#include "warp_math.hpp"
+
+namespace rsv {
+
+constexpr int kAdjTX = 16;
+constexpr int kAdjTY = 8;
+constexpr int kAdjThreads = kAdjTX * kAdjTY;
+constexpr int kAdjDChunk = 64;
+constexpr int kAdjMaxD = 256;
+
+__global__ void adjoint_zero_kernel(float* __restrict__ a, float* __restrict__ b, int64_t n,
+                                    double* __restrict__ gp, double* __restrict__ loss) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = 0.f;
+    b[i] = 0.f;
+  }
+  if (i < 3) gp[i] = 0.0;
+  if (i == 0 && loss) *loss = 0.0;
+}
+
+// 1 / sum of the Eq. 9-10 weights of each pixel's window (same order as the
+// aggregation kernel, so the same float).
+template <int A>
+__global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, int64_t gpitch, int H,
+                                                   int W, float igd2, float igr2,
+                                                   float* __restrict__ zinv) {
+  constexpr int K = 2 * A + 1;
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (u >= W || v >= H) return;
+  const float gp = pixel(g, gpitch, v, u);
+  float z = 0.f;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int y = v + j - A, x = u + k - A;
+      float wt = 0.f;
+      if (x >= 0 && x < W && y >= 0 && y < H)
+        wt = bilateral_weight(pixel(g, gpitch, y, x), gp, j - A, k - A, igd2, igr2);
+      z += wt;
+    }
+  zinv[static_cast<int64_t>(v) * W + u] = 1.f / z;
+}
+
+struct AdjLayout {
+  int hl, ltw, lth, wtw, wth, ztw, zth;
+  size_t off_lt, off_wt, off_zt, off_dt, off_gl, off_gw, off_col, off_red, bytes;
+};
+
+__host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
+  AdjLayout L;
+  L.hl = R > A ? R : A;
+  L.ltw = kAdjTX + 2 * L.hl;
+  L.lth = kAdjTY + 2 * L.hl;
+  L.wtw = kAdjTX + D - 1 + 2 * R;
+  L.wth = kAdjTY + 2 * R;
+  L.ztw = kAdjTX + 2 * A;
+  L.zth = kAdjTY + 2 * A;
+  size_t o = 0;
+  L.off_red = o;  // doubles first (8-byte aligned)
+  o += sizeof(double) * 4 * kAdjThreads;
+  L.off_lt = o;
+  o += sizeof(float) * L.ltw * L.lth;
+  L.off_wt = o;
+  o += sizeof(float) * L.wtw * L.wth;
+  L.off_zt = o;
+  o += sizeof(float) * L.ztw * L.zth;
+  L.off_dt = o;
+  o += sizeof(int) * L.ztw * L.zth;
+  L.off_gl = o;
+  o += sizeof(float) * L.ltw * L.lth;
+  L.off_gw = o;
+  o += sizeof(float) * L.wtw * L.wth;
+  L.off_col = o;
+  o += sizeof(float) * kAdjDChunk * kAdjThreads;
+  L.bytes = o;
+  return L;
+}
+
+template <int R, int A>
+__global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
+    const float* __restrict__ left, int64_t lpitch, const float* __restrict__ right, int64_t rpitch,
+    int H, int W, int D, rsv_plane pl, float igd2, float igr2, float sigma_min,
+    const float* __restrict__ cost, const float* __restrict__ agg, const int32_t* __restrict__ disp,
+    const uint8_t* __restrict__ mask, const float* __restrict__ zinv, float* __restrict__ gleft,
+    float* __restrict__ gright, double* __restrict__ gplane, double* __restrict__ loss) {
+  constexpr int K = 2 * R + 1;
+  constexpr int N = K * K;
+  constexpr int KA = 2 * A + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const AdjLayout Ly = adj_layout(R, A, D);
+  double* red = reinterpret_cast<double*>(smem + Ly.off_red);
+  float* lt = reinterpret_cast<float*>(smem + Ly.off_lt);
+  float* wt = reinterpret_cast<float*>(smem + Ly.off_wt);
+  float* zt = reinterpret_cast<float*>(smem + Ly.off_zt);
+  int* dt = reinterpret_cast<int*>(smem + Ly.off_dt);
+  float* gl = reinterpret_cast<float*>(smem + Ly.off_gl);
+  float* gw = reinterpret_cast<float*>(smem + Ly.off_gw);
+  float* col = reinterpret_cast<float*>(smem + Ly.off_col);
+
+  const int tid = threadIdx.x;
+  const int tx = tid % kAdjTX, ty = tid / kAdjTX;
+  const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
+  const int qx = x0 + tx, qy = y0 + ty;
+  const bool in = qx < W && qy < H;
+  const int hl = Ly.hl;
+  const int lx0 = x0 - hl, ly0 = y0 - hl;                // left tile / grad-left origin
+  const int wx0 = x0 - (D - 1) - R, wy0 = y0 - R;        // warped tile / grad-warped origin
+  const int zx0 = x0 - A, zy0 = y0 - A;                  // Omega tile origin
+  const int64_t plane = static_cast<int64_t>(H) * W;
+
+  for (int i = tid; i < Ly.ltw * Ly.lth; i += kAdjThreads) {
+    const int r = i / Ly.ltw, c = i - r * Ly.ltw;
+    lt[i] = left[static_cast<int64_t>(clampi(ly0 + r, 0, H - 1)) * lpitch + clampi(lx0 + c, 0, W - 1)];
+    gl[i] = 0.f;
+  }
+  for (int i = tid; i < Ly.wtw * Ly.wth; i += kAdjThreads) {
+    const int r = i / Ly.wtw, c = i - r * Ly.wtw;
+    wt[i] = warp_sample(right, rpitch, W, pl, clampi(wx0 + c, 0, W - 1), clampi(wy0 + r, 0, H - 1));
+    gw[i] = 0.f;
+  }
+  for (int i = tid; i < Ly.ztw * Ly.zth; i += kAdjThreads) {
+    const int r = i / Ly.ztw, c = i - r * Ly.ztw;
+    const int y = zy0 + r, x = zx0 + c;
+    const bool ok = x >= 0 && x < W && y >= 0 && y < H;
+    const int64_t gi = static_cast<int64_t>(y) * W + x;
+    zt[i] = ok ? zinv[gi] : 0.f;
+    const int dv = ok ? disp[gi] : -1;
+    dt[i] = (ok && mask[gi] && dv >= 0 && dv < D) ? dv : -1;  // out-of-range d: not in Omega
+  }
+  __syncthreads();
+
+  // Left block of q (clamp-to-edge reads) and its statistics.
+  float lb[K][K];
+  double S = 0.0, Q = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float x = lt[(ty + hl - R + j) * Ly.ltw + tx + hl - R + k];
+      lb[j][k] = x;
+      S += x;
+      Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
+    }
+  const double mul = S / N;
+  const double sll = fmax(Q - S * S / N, 0.0);
+  const bool okl = sqrt(sll / N) >= static_cast<double>(sigma_min);
+  const float gq = lt[(ty + hl) * Ly.ltw + tx + hl];
+
+  // dL/dw terms (q in the role of p) and the loss.
+  double loss_part = 0.0;
+  const int my_d = dt[(ty + A) * Ly.ztw + tx + A];
+  if (in && my_d >= 0) {
+    const float Aq = agg[my_d * plane + static_cast<int64_t>(qy) * W + qx];
+    const float zi = zt[(ty + A) * Ly.ztw + tx + A];
+    loss_part = Aq;
+    float s = 0.f;
+#pragma unroll
+    for (int j = 0; j < KA; ++j)
+#pragma unroll
+      for (int k = 0; k < KA; ++k) {
+        const int Y = qy + j - A, X = qx + k - A;
+        if (X >= 0 && X < W && Y >= 0 && Y < H) {
+          const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
+          const float w = bilateral_weight(gx, gq, j - A, k - A, igd2, igr2);
+          const float c = cost[my_d * plane + static_cast<int64_t>(Y) * W + X];
+          const float t = (c - Aq) * zi * bilateral_weight_dgq(w, gx, gq, igr2);
+          atomicAdd(&gl[(Y - ly0) * Ly.ltw + X - lx0], t);
+          s += t;
+        }
+      }
+    atomicAdd(&gl[(qy - ly0) * Ly.ltw + qx - lx0], -s);
+  }
+
+  // ZNCC adjoint, 64 disparities at a time.
+  for (int d0 = 0; d0 < D; d0 += kAdjDChunk) {
+    for (int i = 0; i < kAdjDChunk; ++i) col[i * kAdjThreads + tid] = 0.f;
+    if (in) {
+#pragma unroll
+      for (int j = 0; j < KA; ++j)
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+          const int zi = (ty + j) * Ly.ztw + tx + k;
+          const int dp = dt[zi];
+          if (dp >= d0 && dp < d0 + kAdjDChunk) {
+            const float gx = lt[(qy + j - A - ly0) * Ly.ltw + qx + k - A - lx0];
+            const float w = bilateral_weight(gx, gq, j - A, k - A, igd2, igr2);
+            col[(dp - d0) * kAdjThreads + tid] += w * zt[zi];
+          }
+        }
+    }
+    if (in && okl) {
+      const int dn = D - d0 < kAdjDChunk ? D - d0 : kAdjDChunk;
+      for (int i = 0; i < dn; ++i) {
+        const float G = col[i * kAdjThreads + tid];
+        if (G == 0.f) continue;
+        const int d = d0 + i;
+        const float* tb = wt + ty * Ly.wtw + tx - d + (D - 1);  // target block top-left
+        double Sr = 0.0, Qr = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double r = tb[j * Ly.wtw + k];
+            Sr += r;
+            Qr = fma(r, r, Qr);
+          }
+        const double srr = fmax(Qr - Sr * Sr / N, 0.0);
+        if (!(sqrt(srr / N) >= static_cast<double>(sigma_min))) continue;
+        const double mur = Sr / N;
+        const double c = cost[d * plane + static_cast<int64_t>(qy) * W + qx];
+        const double a = G / sqrt(sll * srr);
+        const double b = G * c / sll;
+        const double g = G * c / srr;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int Yl = clampi(qy + j - R, 0, H - 1);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double l = static_cast<double>(lb[j][k]) - mul;
+            const double r = static_cast<double>(tb[j * Ly.wtw + k]) - mur;
+            const int Xl = clampi(qx + k - R, 0, W - 1);
+            const int Xw = clampi(qx - d + k - R, 0, W - 1);
+            atomicAdd(&gl[(Yl - ly0) * Ly.ltw + Xl - lx0], static_cast<float>(a * r - b * l));
+            atomicAdd(&gw[(Yl - wy0) * Ly.wtw + Xw - wx0], static_cast<float>(a * l - g * r));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // Flush: left-image gradient.
+  for (int i = tid; i < Ly.ltw * Ly.lth; i += kAdjThreads) {
+    const int r = i / Ly.ltw, c = i - r * Ly.ltw;
+    const int Y = ly0 + r, X = lx0 + c;
+    const float g = gl[i];
+    if (g != 0.f && X >= 0 && X < W && Y >= 0 && Y < H) atomicAdd(&gleft[static_cast<int64_t>(Y) * W + X], g);
+  }
+  // Flush: warped-image gradient through the warp transpose, and the plane gradient.
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  for (int i = tid; i < Ly.wtw * Ly.wth; i += kAdjThreads) {
+    const int r = i / Ly.wtw, c = i - r * Ly.wtw;
+    const int Y = wy0 + r, X = wx0 + c;
+    const float g = gw[i];
+    if (g == 0.f || X < 0 || X >= W || Y < 0 || Y >= H) continue;
+    const WarpTap tap = warp_tap(pl, X, Y, W);
+    const float* row = right + static_cast<int64_t>(Y) * rpitch;
+    const double i0 = row[tap.c0], i1 = row[tap.c1];
+    atomicAdd(&gright[static_cast<int64_t>(Y) * W + tap.c0], static_cast<float>(g * (1.0 - tap.f)));
+    atomicAdd(&gright[static_cast<int64_t>(Y) * W + tap.c1], static_cast<float>(g * tap.f));
+    const double t = -static_cast<double>(g) * (i1 - i0);
+    t0 += t;
+    t1 += t * Y;
+    t2 += t * X;
+  }
+  red[tid] = t0;
+  red[kAdjThreads + tid] = t1;
+  red[2 * kAdjThreads + tid] = t2;
+  red[3 * kAdjThreads + tid] = loss_part;
+  __syncthreads();
+  for (int s = kAdjThreads / 2; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int m = 0; m < 4; ++m) red[m * kAdjThreads + tid] += red[m * kAdjThreads + tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    atomicAdd(&gplane[0], red[0]);
+    atomicAdd(&gplane[1], red[kAdjThreads]);
+    atomicAdd(&gplane[2], red[2 * kAdjThreads]);
+    if (loss) atomicAdd(loss, red[3 * kAdjThreads]);
+  }
+}
+
+template <int R, int A>
+int launch_adjoint(const rsv_image& l, const rsv_image& r, rsv_plane pl, const rsv_params* p,
+                   const float* cost, const float* agg, const int32_t* disp, const uint8_t* mask,
+                   float* gl, float* gr, double* gp, double* loss, float* zinv, hipStream_t st) {
+  const int H = l.height, W = l.width, D = p->D;
+  const float igd2 = 1.f / (p->gamma_d * p->gamma_d);
+  const float igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  const int64_t n = static_cast<int64_t>(H) * W;
+  adjoint_zero_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st>>>(gl, gr, n, gp, loss);
+  if (int s = check_launch()) return s;
+  zinv_kernel<A><<<dim3((W + 255) / 256, H), dim3(256), 0, st>>>(
+      static_cast<const float*>(l.data), l.pitch, H, W, igd2, igr2, zinv);
+  if (int s = check_launch()) return s;
+  const AdjLayout Ly = adj_layout(R, A, D);
+  auto kern = adjoint_kernel<R, A>;
+  if (Ly.bytes > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(Ly.bytes));
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return RSV_E_HIP;
+    }
+  }
+  const dim3 grid((W + kAdjTX - 1) / kAdjTX, (H + kAdjTY - 1) / kAdjTY);
+  kern<<<grid, dim3(kAdjThreads), Ly.bytes, st>>>(
+      static_cast<const float*>(l.data), l.pitch, static_cast<const float*>(r.data), r.pitch, H, W, D,
+      pl, igd2, igr2, p->sigma_min, cost, agg, disp, mask, zinv, gl, gr, gp, loss);
+  return check_launch();
+}
+
+template <int R>
+int dispatch_adjoint_a(const rsv_image& l, const rsv_image& r, rsv_plane pl, const rsv_params* p,
+                       const float* cost, const float* agg, const int32_t* disp, const uint8_t* mask,
+                       float* gl, float* gr, double* gp, double* loss, float* zinv, hipStream_t st) {
+  switch (p->agg_radius) {
+    case 1: return launch_adjoint<R, 1>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    case 2: return launch_adjoint<R, 2>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    case 3: return launch_adjoint<R, 3>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    case 4: return launch_adjoint<R, 4>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    case 5: return launch_adjoint<R, 5>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    case 6: return launch_adjoint<R, 6>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+    default: return RSV_E_PARAM;
+  }
+}
+
+// Sum of agg[disp(p)][p] over pixels with mask(p) != 0 (the loss of the
+// differentiable form).  Block partial sums in double, then one atomic per block.
+__global__ __launch_bounds__(256) void selected_sum_kernel(const float* __restrict__ agg,
+                                                           const int32_t* __restrict__ disp,
+                                                           const uint8_t* __restrict__ mask, int H,
+                                                           int W, int D, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t n = static_cast<int64_t>(H) * W;
+  double s = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * 256) {
+    const int d = disp[i];
+    if (mask[i] && d >= 0 && d < D) s += agg[d * n + i];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+__global__ void zero_double_kernel(double* p) { *p = 0.0; }
+
+}  // namespace rsv
+
+extern "C" int rsv_selected_cost_sum(const float* agg_ref, const int32_t* disp, const uint8_t* mask,
+                                     int32_t height, int32_t width, int32_t D, double* out,
+                                     void* stream) {
+  using namespace rsv;
+  if (!agg_ref || !disp || !mask || !out) return RSV_E_NULL;
+  if (height < 1 || width < 1 || D < 1 || D > RSV_MAX_D) return RSV_E_SHAPE;
+  if (!aligned(agg_ref, 4) || !aligned(disp, 4) || !aligned(out, 8)) return RSV_E_ALIGN;
+  hipStream_t st = as_stream(stream);
+  zero_double_kernel<<<1, 1, 0, st>>>(out);
+  if (int s = check_launch()) return s;
+  const int64_t n = static_cast<int64_t>(height) * width;
+  const int blocks = static_cast<int>((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+  selected_sum_kernel<<<blocks, 256, 0, st>>>(agg_ref, disp, mask, height, width, D, out);
+  return check_launch();
+}
+
+extern "C" size_t rsv_cost_adjoint_workspace_bytes(int32_t height, int32_t width) {
+  if (height < 1 || width < 1) return 0;
+  return sizeof(float) * static_cast<size_t>(height) * static_cast<size_t>(width);
+}
+
+extern "C" int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
+                                const float* cost_ref, const float* agg_ref, const int32_t* disp,
+                                const uint8_t* mask, float* grad_left, float* grad_right,
+                                double* grad_plane, double* loss, void* workspace, void* stream) {
+  using namespace rsv;
+  if (int s = validate_image(left)) return s;
+  if (int s = validate_image(right)) return s;
+  if (int s = validate_cost_params(p)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (left.dtype != RSV_F32 || right.dtype != RSV_F32) return RSV_E_DTYPE;
+  if (!cost_ref || !agg_ref || !disp || !mask || !grad_left || !grad_right || !grad_plane || !workspace)
+    return RSV_E_NULL;
+  if (left.height != right.height || left.width != right.width) return RSV_E_SHAPE;
+  if (p->D > kAdjMaxD) return RSV_E_SHAPE;
+  const int K = 2 * p->block_radius + 1;
+  if (left.height < K || left.width < K) return RSV_E_SHAPE;
+  if (!aligned(cost_ref, 4) || !aligned(agg_ref, 4) || !aligned(disp, 4) || !aligned(grad_left, 4) ||
+      !aligned(grad_right, 4) || !aligned(grad_plane, 8) || (loss && !aligned(loss, 8)) ||
+      !aligned(workspace, 4))
+    return RSV_E_ALIGN;
+  float* zinv = static_cast<float*>(workspace);
+  hipStream_t st = as_stream(stream);
+  switch (p->block_radius) {
+    case 1: return dispatch_adjoint_a<1>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
+    case 2: return dispatch_adjoint_a<2>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
+    case 3: return dispatch_adjoint_a<3>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
+    case 4: return dispatch_adjoint_a<4>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
+    default: return RSV_E_PARAM;
+  }
+}

@@ -5,7 +5,7 @@
 // (zero for taps outside the image) together with 1 / sum(w), and then walks the
 // disparity slices: slice d of the cost volume is staged tile-plus-halo in LDS
 // (double-buffered) and the thread forms its weighted sum from there.
-#include "rsv_internal.hpp"
+#include "bilateral_math.hpp"
 
 namespace rsv {
 
@@ -34,11 +34,8 @@ __global__ __launch_bounds__(kAggT* kAggT) void aggregate_kernel(
     for (int k = 0; k < K; ++k) {
       const int y = v + j - A, x = u + k - A;
       float wt = 0.f;
-      if (x >= 0 && x < W && y >= 0 && y < H) {
-        const float dg = (pixel(guide, gpitch, y, x) - gp) * (1.f / 255.f);
-        const float r2 = static_cast<float>((j - A) * (j - A) + (k - A) * (k - A));
-        wt = expf(-(r2 * inv_gd2 + dg * dg * inv_gr2));
-      }
+      if (x >= 0 && x < W && y >= 0 && y < H)
+        wt = bilateral_weight(pixel(guide, gpitch, y, x), gp, j - A, k - A, inv_gd2, inv_gr2);
       w[j][k] = wt;
       z += wt;
     }

@@ -164,6 +164,53 @@ def triangulate(disp_sub: torch.Tensor, valid: torch.Tensor, plane, camera,
     return dfin, xyz
 
 
+def selected_cost_sum(agg_ref: torch.Tensor, disp: torch.Tensor, mask: torch.Tensor,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """Loss of the differentiable form: sum of agg_ref[disp(p)][p] over mask(p) != 0."""
+    lib = load()
+    D, H, W = agg_ref.shape
+    _contig(agg_ref, "agg_ref", torch.float32, (D, H, W))
+    _contig(disp, "disp", torch.int32, (H, W))
+    _contig(mask, "mask", torch.uint8, (H, W))
+    out = out if out is not None else torch.empty((), dtype=torch.float64, device=agg_ref.device)
+    _contig(out, "out", torch.float64, ())
+    check(lib.rsv_selected_cost_sum(agg_ref.data_ptr(), disp.data_ptr(), mask.data_ptr(), H, W, D,
+                                    out.data_ptr(), _stream(agg_ref.device)), "rsv_selected_cost_sum")
+    return out
+
+
+def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_ref: torch.Tensor,
+                 agg_ref: torch.Tensor, disp: torch.Tensor, mask: torch.Tensor,
+                 workspace: torch.Tensor | None = None):
+    """Gradients of selected_cost_sum(agg_ref, disp, mask) with respect to the left
+    image, the right image and the plane terms (a0, a1, a2); also returns the loss.
+    left/right are float32; cost_ref/agg_ref are the forward's volumes."""
+    lib = load()
+    H, W = left.shape
+    D = int(params.D)
+    _dev(left, "left", torch.float32)
+    _dev(right, "right", torch.float32, (H, W))
+    _contig(cost_ref, "cost_ref", torch.float32, (D, H, W))
+    _contig(agg_ref, "agg_ref", torch.float32, (D, H, W))
+    _contig(disp, "disp", torch.int32, (H, W))
+    _contig(mask, "mask", torch.uint8, (H, W))
+    dev = left.device
+    nbytes = lib.rsv_cost_adjoint_workspace_bytes(H, W)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty((nbytes + 3) // 4, dtype=torch.float32, device=dev)
+    gl = torch.empty((H, W), dtype=torch.float32, device=dev)
+    gr = torch.empty((H, W), dtype=torch.float32, device=dev)
+    gp = torch.empty(3, dtype=torch.float64, device=dev)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    p = _params(params)
+    check(lib.rsv_cost_adjoint(image(left, "left"), image(right, "right"), _plane(plane), C.byref(p),
+                               cost_ref.data_ptr(), agg_ref.data_ptr(), disp.data_ptr(),
+                               mask.data_ptr(), gl.data_ptr(), gr.data_ptr(), gp.data_ptr(),
+                               loss.data_ptr(), workspace.data_ptr(), _stream(dev)),
+          "rsv_cost_adjoint")
+    return gl, gr, gp, loss
+
+
 def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
                 want_top2: bool = False) -> dict:
     """The plain path, one C-ABI call per stage on the current stream (Fig. 1):
@@ -182,4 +229,4 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "aggregate", "select_subpixel",
-           "triangulate", "reconstruct", "image", "load"]
+           "triangulate", "reconstruct", "selected_cost_sum", "cost_adjoint", "image", "load"]

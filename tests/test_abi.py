@@ -118,3 +118,28 @@ def test_triangulate_validation(lib):
     assert lib.rsv_triangulate(FAKE, FAKE, 10, 10, pl, _lib.Camera(0.0, 0.12, 1, 1), FAKE, FAKE,
                                None) == -3
     assert lib.rsv_triangulate(FAKE, FAKE, -1, 10, pl, cam, FAKE, FAKE, None) == -2
+
+
+def test_selected_sum_validation(lib):
+    assert lib.rsv_selected_cost_sum(None, FAKE, FAKE, 10, 10, 4, FAKE, None) == -1
+    assert lib.rsv_selected_cost_sum(FAKE, FAKE, FAKE, 10, 10, 0, FAKE, None) == -2
+    assert lib.rsv_selected_cost_sum(FAKE, FAKE, FAKE, 10, 10, 4, FAKE + 4, None) == -5
+
+
+def test_adjoint_validation(lib):
+    pl = _lib.Plane(1.0, 0.1, 0.0, 2.0)
+    p = _params(D=16)
+    f32 = _img(dtype=_lib.RSV_F32)
+    args = [FAKE] * 8 + [FAKE, None]   # cost, agg, disp, mask, gl, gr, gp, loss, ws, stream
+    assert lib.rsv_cost_adjoint_workspace_bytes(10, 20) == 800
+    assert lib.rsv_cost_adjoint_workspace_bytes(0, 20) == 0
+    assert lib.rsv_cost_adjoint(_img(), f32, pl, C.byref(p), *args) == -4     # u8 left
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(_params(D=257)), *args) == -2
+    assert lib.rsv_cost_adjoint(f32, _img(h=31, dtype=_lib.RSV_F32), pl, C.byref(p), *args) == -2
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(_params(agg_radius=9)), *args) == -3
+    a = list(args)
+    a[8] = None
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -1
+    a = list(args)
+    a[6] = FAKE + 4                  # grad_plane must be 8-byte aligned
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -5
