@@ -8,8 +8,9 @@ One step = one full frame of the plain path on the 1280x720, D = 64 road pair
 WTA + left-right check + parabola subpixel -> post-processing + 3-D points), inputs
 resident in HBM.  Prints ONE JSON line.  `value` is Eq. 13's Mde/s over the whole
 frame: W*H*D / t_frame * 1e-6.  Per-kernel durations come from HIP events on the
-stream the kernels run on; the roofline object covers the dominant kernel
-(bilateral aggregation, ALU-bound).
+stream the kernels run on; the roofline object covers the frame's dominant kernel.
+The line also carries the batched form on the 64-pair uneven workload against 64
+sequential plain calls (--no-batch skips it) and the FP64 oracle's CPU rate.
 """
 from __future__ import annotations
 
@@ -24,8 +25,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, published
 
 
 def parse():
@@ -37,22 +37,20 @@ def parse():
                     choices=["road1280_d64", "road320_d32", "road1920_d128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows in the oracle timing sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched form")
+    ap.add_argument("--batch-pairs", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=5)
     return ap.parse_args()
-
-
-def agg_flops_per_entry(agg_radius: int) -> int:
-    m = (2 * agg_radius + 1) ** 2
-    return 2 * m + 1          # m multiply-adds and the 1/sum(w) scaling (Eq. 8)
 
 
 def source_sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def recorded_traffic(kernel_src: str, workload: str):
+def recorded_traffic(kernel_src: str, kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
     taken on the current kernel source; else None."""
-    f = os.path.join(ROOT, "profiles", f"aggregate_{workload}_pmc.md")
+    f = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
     if not os.path.exists(f):
         return None
     txt = open(f).read()
@@ -61,6 +59,102 @@ def recorded_traffic(kernel_src: str, workload: str):
     if not sha or not tb or sha.group(1) != source_sha(kernel_src):
         return None
     return float(tb.group(1))
+
+
+def kernel_rooflines(stage_ms, W, H, D, prm):
+    """Algorithmic HBM bytes per launch / average launch time for the three volume
+    kernels (all HBM-bound at these sizes):
+      cost_volume: writes C_ref and C_tar, 8 B per entry (image reads are O(1/D));
+      aggregate:   reads one volume and writes one, 8 B per entry (per launch);
+      select:      reads both aggregated volumes, 8 B per entry."""
+    n = W * H * D
+    per = {"cost_volume": (stage_ms["cost_volume"], 8 * n),
+           "aggregate": (0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]), 8 * n),
+           "select_subpixel": (stage_ms["select_subpixel"], 8 * n)}
+    out = {}
+    for k, (ms, b) in per.items():
+        gbs = b / (ms * 1e-3) / 1e9
+        out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": b, "ms": round(ms, 5)}
+    return out
+
+
+def bench_batch(a, rsv, torch):
+    """The 64-pair uneven batch: one autotuned graph launch of the batched form vs 64
+    sequential plain-path calls on the same pairs (same kernels' arithmetic)."""
+    import synth
+    from paper_1807_07433_amd.batch import BatchPlan
+    cases = synth.batch64_mixed(n_pairs=a.batch_pairs, workers=min(16, os.cpu_count() or 1))
+    dev = torch.device("cuda:0")
+    pairs = []
+    for c in cases:
+        cam = (c.camera.f, c.camera.baseline, c.camera.u0, c.camera.v0)
+        pairs.append((torch.from_numpy(c.pair.left).to(dev), torch.from_numpy(c.pair.right).to(dev),
+                      c.plane, cam, c.params.D))
+    work = sum(c.pair.left.size * c.params.D for c in cases)
+    prm0 = cases[0].params
+    tuning, _ = BatchPlan.autotune(pairs, prm0)
+    plan = BatchPlan(pairs, prm0, tuning)
+    for _ in range(2):
+        plan.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.batch_steps):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / a.batch_steps
+    err = plan.error_flag()
+    info = plan.info()
+    plan.close()
+
+    # 64 sequential plain calls, buffers sized for the largest pair and reused
+    f32 = dict(dtype=torch.float32, device=dev)
+    mx = max(c.pair.left.size * c.params.D for c in cases)
+    vols = [torch.empty(mx, **f32) for _ in range(4)]
+    outs = []
+    for c in cases:
+        H, W = c.pair.left.shape
+        D = c.params.D
+        outs.append(dict(wp=torch.empty((H, W), **f32),
+                         sel={"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
+                              "disp_tar": torch.empty((H, W), dtype=torch.int32, device=dev),
+                              "disp_sub": torch.empty((H, W), **f32),
+                              "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)},
+                         dfin=torch.empty((H, W), **f32), xyz=torch.empty((H, W, 3), **f32),
+                         v=[t[:D * H * W].view(D, H, W) for t in vols]))
+
+    def plain_all():
+        for (left, right, plane, cam, D), c, o in zip(pairs, cases, outs):
+            cr, ct, ar, at = o["v"]
+            rsv.warp(right, plane, out=o["wp"])
+            rsv.cost_volume(left, o["wp"], c.params, out_ref=cr, out_tar=ct)
+            rsv.aggregate(cr, left, c.params, out=ar)
+            rsv.aggregate(ct, o["wp"], c.params, out=at)
+            rsv.select_subpixel(ar, at, c.params, out=o["sel"])
+            rsv.triangulate(o["sel"]["disp_sub"], o["sel"]["valid"], plane, cam, out_disp=o["dfin"],
+                            out_xyz=o["xyz"])
+
+    plain_all()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(a.batch_steps):
+        plain_all()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / a.batch_steps
+    sizes = sorted({(c.pair.left.shape[1], c.pair.left.shape[0], c.params.D) for c in cases})
+    return {"workload": f"batch64_mixed: {len(cases)} uint8 pairs, sizes/D drawn from "
+                        f"{{640x360, 1280x720, 1920x1080}} x {{32, 64, 128}}, NCC 7x7, bilateral 11x11",
+            "sum_whd": work, "distinct_w_h_d": len(sizes),
+            "ms_per_batch": round(ms_batch, 4),
+            "value": round(work / (ms_batch * 1e-3) * 1e-6, 2), "unit": "Mpix·disp/s",
+            "plain_sequential_ms": round(ms_plain, 4),
+            "plain_sequential_value": round(work / (ms_plain * 1e-3) * 1e-6, 2),
+            "speedup_vs_plain": round(ms_plain / ms_batch, 4),
+            "tuning": {"lag_bands": tuning.lag_bands, "grid_blocks": tuning.grid_blocks},
+            "plan": info, "error_flag": err, "steps": a.batch_steps}
 
 
 def cpu_baseline(case, rows: int):
@@ -164,11 +258,14 @@ def main():
 
     mde = W * H * D / (ms_step * 1e-3) * 1e-6
     t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
-    agg_ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
-    agg_flops = W * H * D * agg_flops_per_entry(prm.agg_radius)
-    achieved = agg_flops / (agg_ms * 1e-3) * 1e-12
-    agg_src = os.path.join(ROOT, "paper_1807_07433_amd", "csrc", "aggregate.hip")
-    traffic = recorded_traffic(agg_src, a.workload)
+    kernels = kernel_rooflines(stage_ms, W, H, D, prm)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    roof = dict(kernels[dom])
+    src = {"cost_volume": "cost_tile.hpp", "aggregate": "agg_tile.hpp",
+           "select_subpixel": "select.hip"}[dom]
+    roof["traffic"] = recorded_traffic(os.path.join(ROOT, "paper_1807_07433_amd", "csrc", src),
+                                       dom, a.workload)
+    roof = {"kernel": dom, **roof}
 
     out = {
         "metric": "Mpix·disp/s (cost+aggregate) & frames/s at 1280×720 D=64; batched vs plain",
@@ -192,13 +289,12 @@ def main():
         "mde_cost_aggregate": round(W * H * D / (t_ca * 1e-3) * 1e-6, 2),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "wall_s_timed": round(wall, 4),
-        "roofline": {"kernel": "aggregate", "bound": "alu", "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic,
-                     "flops_per_launch": agg_flops, "avg_launch_ms": round(agg_ms, 5)},
+        "roofline": roof,
+        "kernels": kernels,
         "library": _lib.LIB_PATH,
     }
+    if not a.no_batch:
+        out["batched"] = bench_batch(a, rsv, torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_rows)
     print(json.dumps(out))

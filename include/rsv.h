@@ -154,6 +154,76 @@ int rsv_triangulate(const float* disp_sub, const uint8_t* valid, int32_t height,
                     int32_t width, rsv_plane plane, rsv_camera cam, float* disp_final,
                     float* xyz, void* stream);
 
+/* ------------------------------------------------------------ batched form */
+
+/* One stereo pair of a batch.  Pairs may differ in size and in D; all share the
+ * rsv_params of the plan (p->D is ignored).  The plan keeps the pointers: inputs and
+ * outputs must stay valid while the plan is used. */
+typedef struct {
+  rsv_image left, right;  /* uint8 pair of the same H, W (W <= 16384), any pitch */
+  rsv_plane plane;
+  rsv_camera camera;
+  int32_t D;              /* this pair's residual search range, 1 .. RSV_MAX_D        */
+  int32_t reserved;
+  int32_t* disp_ref;      /* out int32 [H][W] or NULL                                 */
+  int32_t* disp_tar;      /* out int32 [H][W] or NULL                                 */
+  float* disp_sub;        /* out float32 [H][W]                                       */
+  uint8_t* valid;         /* out uint8 [H][W]                                         */
+  float* disp_final;      /* out float32 [H][W] or NULL                               */
+  float* xyz;             /* out float32 [H][W][3] or NULL                            */
+} rsv_pair_desc;
+
+/* Launch shape of a plan (rsv_tuning_default fills the defaults). */
+typedef struct {
+  int32_t lag_bands;    /* cost bands an aggregation tile row trails the band that
+                           completes its window (0 .. 8)                              */
+  int32_t grid_blocks;  /* persistent workgroups; 0 = as many as are resident at once */
+  int32_t reserved[2];
+} rsv_tuning;
+
+typedef struct rsv_batch_plan rsv_batch_plan;
+
+void rsv_tuning_default(rsv_tuning* t);
+
+/* Builds a plan for the whole batch: device workspace for every pair's two cost
+ * volumes and selection state, one work list, and a hipGraph of
+ * [reset counters -> persistent fused kernel -> per-pixel tail].
+ * The persistent kernel runs warp + ZNCC (the arithmetic of rsv_warp and
+ * rsv_cost_volume), bilateral aggregation (that of rsv_aggregate) and
+ * winner-take-all for every pair; the tail runs the left-right check, Eq. 12,
+ * post-processing and triangulation (those of rsv_select_subpixel and
+ * rsv_triangulate).  Every output equals the plain path's bit for bit.
+ *   pairs, n   the batch (host array, copied)
+ *   p          shared parameters (block_radius, agg_radius, gammas, lr_threshold,
+ *              sigma_min)
+ *   tuning     launch shape, or NULL for the defaults (see rsv_autotune)
+ *   out        host pointer receiving the plan
+ * The plan owns its device memory (about 8 * sum(H*W*D) bytes) and graph.
+ * Errors: RSV_E_NULL, RSV_E_SHAPE, RSV_E_PARAM, RSV_E_DTYPE (pairs must be uint8),
+ * RSV_E_NOMEM, RSV_E_HIP. */
+int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
+                          const rsv_tuning* tuning, rsv_batch_plan** out);
+
+/* Launches the plan's graph on `stream` (one hipGraphLaunch).  A plan must not run
+ * concurrently on two streams. */
+int rsv_batch_run(rsv_batch_plan* plan, void* stream);
+
+/* After the caller has synchronised: *flag = 1 if a wait inside the last run hit
+ * its spin limit (results then undefined), else 0. */
+int rsv_batch_error(rsv_batch_plan* plan, int32_t* flag);
+
+/* Work items, persistent workgroups and device bytes of a plan (any may be NULL). */
+int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items, int32_t* grid_blocks,
+                        int64_t* workspace_bytes);
+
+int rsv_batch_plan_destroy(rsv_batch_plan* plan);
+
+/* Times candidate launch shapes (lag_bands x grid_blocks) on this batch, each with
+ * its own temporary plan, and returns the fastest in *out and its time in *best_ms
+ * (may be NULL).  Writes the pairs' outputs.  Synchronises `stream`. */
+int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p, rsv_tuning* out,
+                 float* best_ms, void* stream);
+
 /* ------------------------------------------------------ differentiable form */
 
 /* Loss of the differentiable form: sum of agg_ref[disp(p)][p] over the pixels p with

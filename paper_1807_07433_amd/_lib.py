@@ -56,6 +56,13 @@ _SIGNATURES = {
     "rsv_cost_adjoint_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "rsv_cost_adjoint": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, _P, _P, _P, _P, _P,
                                    _P, _P, _P, _P]),
+    "rsv_tuning_default": (None, [_P]),
+    "rsv_batch_plan_create": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P]),
+    "rsv_batch_run": (C.c_int, [_P, _P]),
+    "rsv_batch_error": (C.c_int, [_P, _P]),
+    "rsv_batch_plan_info": (C.c_int, [_P, _P, _P, _P]),
+    "rsv_batch_plan_destroy": (C.c_int, [_P]),
+    "rsv_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P, _P]),
     "rsv_status_string": (C.c_char_p, [C.c_int]),
     "rsv_last_hip_error": (C.c_int, []),
     "rsv_version": (C.c_int, []),

@@ -80,14 +80,14 @@ def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, resele
         if sel is None or it % reselect_every == 0:
             sel = [select(l, r, plane, params) for l, r in zip(lefts, rights)]
         opt.zero_grad()
-        total = 0.0
+        objective = 0.0
         for (l, r), (d, m) in zip(zip(lefts, rights), sel):
             loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m)
-            n = max(int(m.sum()), 1)
-            (-loss / n).backward()
-            total += float(loss) / n
+            objective = objective + loss / max(int(m.sum()), 1)
+        objective = objective / len(lefts)
+        (-objective).backward()
         opt.step()
-        hist.append(total / len(lefts))
+        hist.append(float(objective.detach()))
         if callback:
             callback(it, (z * scale).detach(), hist[-1])
     return (z * scale).detach(), hist

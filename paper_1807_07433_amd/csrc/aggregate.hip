@@ -1,79 +1,71 @@
 // rsv_aggregate: bilateral cost aggregation (Sec. II-B.2, Eq. 8-10).
 //
-// The weights of Eq. 9-10 depend on the pixel pair only, not on d.  Each thread
-// owns one output pixel, computes its (2A+1)^2 weights once into registers
-// (zero for taps outside the image) together with 1 / sum(w), and then walks the
-// disparity slices: slice d of the cost volume is staged tile-plus-halo in LDS
-// (double-buffered) and the thread forms its weighted sum from there.
-#include "bilateral_math.hpp"
+// The weights of Eq. 9-10 depend on the pixel pair only, never on d, so the
+// aggregation of a 4 x 4 patch over 16 disparities is a small matrix product with a
+// banded weight matrix, run on the matrix cores (agg_tile.hpp, aggregate_mfma.hpp).
+// Each 1024-thread block owns a 16 x 16 output tile and writes its aggregated
+// values plane by plane.  Blocks are numbered so that the tiles handled by one XCD
+// form a contiguous band of the image, keeping halo re-reads inside that XCD's L2.
+#include "agg_tile.hpp"
 
 namespace rsv {
 
-constexpr int kAggT = 16;
+constexpr int kAggThreads = 1024;
+
+// Tile index of block b when consecutive blocks are dealt round-robin to 8 XCDs:
+// XCD x receives the contiguous tile range [x * per + min(x, rem), ...).
+__device__ __forceinline__ int xcd_band_tile(int b, int ntiles) {
+  const int xcd = b & 7, k = b >> 3;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+// agg_tile sink that stores the aggregated values into the output volume.
+struct VolumeSink {
+  float* agg;
+  int H, W, D, by, bx;
+
+  __device__ __forceinline__ void operator()(int t, const PatchPos& pp, int lane, const float4_t& vals) {
+    const int d = 16 * t + (lane & 15);
+    const int Y = by + 4 * pp.pr + (lane >> 4), X0 = bx + 4 * pp.pc;
+    if (d < D && Y < H) {
+      float* o = agg + d * (static_cast<int64_t>(H) * W) + static_cast<int64_t>(Y) * W + X0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (X0 + e < W) o[e] = vals[e];
+    }
+  }
+};
 
 template <int A, typename TG>
-__global__ __launch_bounds__(kAggT* kAggT) void aggregate_kernel(
+__global__ __launch_bounds__(kAggThreads) void aggregate_kernel(
     const float* __restrict__ cost, const TG* __restrict__ guide, int64_t gpitch, int H, int W,
-    int D, float inv_gd2, float inv_gr2, float* __restrict__ agg) {
-  constexpr int K = 2 * A + 1;
-  constexpr int TT = kAggT + 2 * A;
-  __shared__ float tile[2][TT * TT];
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * kAggT + tx;
-  const int ub = blockIdx.x * kAggT, vb = blockIdx.y * kAggT;
-  const int u = ub + tx, v = vb + ty;
-  const bool inside = (u < W) && (v < H);
-
-  // Eq. 9-10 weights; intensities scaled by 1/255 inside the range term.
-  float w[K][K];
-  float z = 0.f;
-  const float gp = pixel(guide, gpitch, clampi(v, 0, H - 1), clampi(u, 0, W - 1));
-#pragma unroll
-  for (int j = 0; j < K; ++j)
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int y = v + j - A, x = u + k - A;
-      float wt = 0.f;
-      if (x >= 0 && x < W && y >= 0 && y < H)
-        wt = bilateral_weight(pixel(guide, gpitch, y, x), gp, j - A, k - A, inv_gd2, inv_gr2);
-      w[j][k] = wt;
-      z += wt;
-    }
-  const float invz = 1.f / z;
-
-  const int64_t plane = static_cast<int64_t>(H) * W;
-  auto stage = [&](int d, float* dst) {
-    const float* src = cost + d * plane;
-    for (int i = tid; i < TT * TT; i += kAggT * kAggT) {
-      const int r = i / TT, c = i - r * TT;
-      const int y = vb - A + r, x = ub - A + c;
-      dst[i] = (x >= 0 && x < W && y >= 0 && y < H) ? src[static_cast<int64_t>(y) * W + x] : 0.f;
-    }
-  };
-  stage(0, tile[0]);
-  __syncthreads();
-  for (int d = 0; d < D; ++d) {
-    const float* cur = tile[d & 1];
-    if (d + 1 < D) stage(d + 1, tile[(d + 1) & 1]);
-    float acc = 0.f;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc = fmaf(w[j][k], cur[(ty + j) * TT + tx + k], acc);
-    if (inside) agg[d * plane + static_cast<int64_t>(v) * W + u] = acc * invz;
-    __syncthreads();
-  }
+    int D, float igd2, float igr2, float* __restrict__ agg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
+  auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
+  VolumeSink sink{agg, H, W, D, by, bx};
+  agg_tile<A, kAggThreads>(cost, H, W, D, igd2, igr2, by, bx, guide_at, sink, smem);
 }
 
 template <int A, typename TG>
 int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
                hipStream_t st) {
-  const dim3 block(kAggT, kAggT);
-  const dim3 grid((g.width + kAggT - 1) / kAggT, (g.height + kAggT - 1) / kAggT);
-  const float inv_gd2 = 1.f / (p->gamma_d * p->gamma_d);
-  const float inv_gr2 = 1.f / (p->gamma_r * p->gamma_r);
-  aggregate_kernel<A, TG><<<grid, block, 0, st>>>(cost, static_cast<const TG*>(g.data), g.pitch,
-                                                  g.height, g.width, p->D, inv_gd2, inv_gr2, agg);
+  const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
+  const float igd2 = 1.f / (p->gamma_d * p->gamma_d);
+  const float igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  const size_t lds = agg_tile_lds_bytes<A>();
+  auto kern = aggregate_kernel<A, TG>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RSV_E_HIP;
+  }
+  kern<<<dim3(tiles), dim3(kAggThreads), lds, st>>>(cost, static_cast<const TG*>(g.data), g.pitch,
+                                                      g.height, g.width, p->D, igd2, igr2, agg);
   return check_launch();
 }
 

@@ -1,0 +1,125 @@
+// Bilateral aggregation (Sec. II-B.2, Eq. 8-10) as a banded contraction on the
+// matrix cores.  For a 4 x 4 patch of output pixels p and 16 disparities d:
+//     A[d][p] = (sum_q w(p, q) C[d][q]) / Z(p),   Z(p) = sum_q w(p, q)
+// where q runs over the union of the 16 windows: (4 + 2A) rows x 16 columns (the
+// columns beyond 4 + 2A carry zero weight).  One v_mfma_f32_16x16x32_f16 consumes
+// two union rows (K = 32): M = 16 pixels, N = 16 disparities.  Weights and costs are
+// each split into fp16 hi + lo parts (x = hi + lo to about 2^-22 relative, |C| <= 1,
+// 0 <= w <= 1), and hi*hi + hi*lo + lo*hi is accumulated in fp32, so the result
+// matches an fp32 weighted sum to ~1e-7.  The weights are computed once per patch
+// and stay in registers for every disparity tile.
+//
+// Lane layout of v_mfma_f32_16x16x32_f16 (wave64; l = lane, i = l % 16, g = l / 16):
+//   A operand: A[i][8g + e], e = 0..7      B operand: B[8g + e][l % 16]
+//   result:    C[4g + e][l % 16], e = 0..3
+// K index 8g + e of K-step s maps to union row 2s + g/2, union column 8 (g % 2) + e.
+#pragma once
+
+#include "bilateral_math.hpp"
+
+namespace rsv {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Geometry of the LDS cost tile of a 16 x 16 output block.
+template <int A>
+struct AggGeo {
+  static constexpr int UR = 4 + 2 * A;       // union rows of one patch
+  static constexpr int KS = UR / 2;          // K-steps of 32
+  static constexpr int TR = 16 + 2 * A;      // tile rows
+  static constexpr int TC = 28;              // tile columns: patch 3's union ends at 12 + 16
+  static constexpr int RAW = TR * TC;
+  // halves per disparity plane; PLANE % 16 == 8 keeps the 16 planes read by one
+  // group of 16 lanes on distinct 4-bank groups
+  static constexpr int PLANE = RAW + ((8 - RAW % 16) + 16) % 16;
+  static constexpr int GT = 16 + 2 * A;      // guide tile side
+};
+
+struct PatchPos {
+  int pr, pc;  // patch row / column inside the 16 x 16 block (0..3)
+};
+
+// Weights w of one lane for one patch, split into hi / lo fp16 parts (w <= 1).
+// Returns 1 / Z for the four output pixels this lane receives from the MFMA
+// (patch row g = lane / 16, columns 0..3), Z = sum of the pixel's weights in fp32.
+template <int A, typename GuideAt>
+__device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, const PatchPos& pp,
+                                                  int lane, int by, int bx, int H, int W,
+                                                  float igd2, float igr2, GuideAt guide_at) {
+  using G = AggGeo<A>;
+  const int i = lane & 15, g = lane >> 4;
+  const int py = i >> 2, px = i & 3;
+  const int Yp = by + 4 * pp.pr + py, Xp = bx + 4 * pp.pc + px;
+  const bool pin = Yp < H && Xp < W;
+  const float gp = pin ? guide_at(4 * pp.pr + py + A, 4 * pp.pc + px + A) : 0.f;
+  float z = 0.f;
+#pragma unroll
+  for (int s = 0; s < G::KS; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = 2 * s + (g >> 1), c = 8 * (g & 1) + e;
+      const int dy = r - A - py, dx = c - A - px;
+      float wt = 0.f;
+      if (pin && dy >= -A && dy <= A && dx >= -A && dx <= A) {
+        const int Y = Yp + dy, X = Xp + dx;
+        if (Y >= 0 && Y < H && X >= 0 && X < W)
+          wt = bilateral_weight(guide_at(4 * pp.pr + r, 4 * pp.pc + c), gp, dy, dx, igd2, igr2);
+      }
+      const _Float16 h = static_cast<_Float16>(wt);
+      whi[s][e] = h;
+      wlo[s][e] = static_cast<_Float16>(wt - static_cast<float>(h));
+      z += wt;
+    }
+  // the four lanes holding pixel i cover disjoint K ranges: sum them
+  z += __shfl_xor(z, 16);
+  z += __shfl_xor(z, 32);
+  float4_t iz;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float ze = __shfl(z, 4 * g + e);
+    iz[e] = ze > 0.f ? 1.f / ze : 0.f;
+  }
+  return iz;
+}
+
+__device__ __forceinline__ half8_t lds_load8(const _Float16* p) {
+  // two 8-byte LDS reads (the address is 8-byte aligned, not always 16)
+  const half4_t a = *reinterpret_cast<const half4_t*>(p);
+  const half4_t b = *reinterpret_cast<const half4_t*>(p + 4);
+  half8_t r;
+  r[0] = a[0]; r[1] = a[1]; r[2] = a[2]; r[3] = a[3];
+  r[4] = b[0]; r[5] = b[1]; r[6] = b[2]; r[7] = b[3];
+  return r;
+}
+
+// acc += W' x C over all K-steps for one patch and one 16-disparity tile held in
+// LDS as hi / lo planes.
+template <int A>
+__device__ __forceinline__ float4_t patch_mfma(const half8_t* whi, const half8_t* wlo,
+                                               const _Float16* hi, const _Float16* lo,
+                                               const PatchPos& pp, int lane) {
+  using G = AggGeo<A>;
+  const int j = lane & 15, g = lane >> 4;
+  const int base = j * G::PLANE + (4 * pp.pr + (g >> 1)) * G::TC + 4 * pp.pc + 8 * (g & 1);
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < G::KS; ++s) {
+    const int off = base + 2 * s * G::TC;
+    const half8_t bh = lds_load8(hi + off);
+    const half8_t bl = lds_load8(lo + off);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi[s], bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi[s], bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo[s], bh, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void split_store(float c, _Float16* hi, _Float16* lo, int idx) {
+  const _Float16 h = static_cast<_Float16>(c);
+  hi[idx] = h;
+  lo[idx] = static_cast<_Float16>(c - static_cast<float>(h));
+}
+
+}  // namespace rsv

@@ -1,0 +1,106 @@
+// One tile of the ZNCC cost volumes (Sec. II-B.1, Eq. 3-5), shared by the plain
+// cost kernel and the batch kernel so both produce the same float for every entry.
+//
+// The tile is 64 consecutive left-block centres u (u may run past W, up to
+// W + D - 2, to fill the target volume) times TH rows.  Each thread owns one centre
+// and walks d = 0 .. D-1: its centred left block stays in registers and the target
+// block slides one column left per step through a register ring, so a step reads
+// one new column of 2R+1 values from LDS and spends (2R+1)^2 FMAs.  The value for
+// (u, v, d) is written to cost_ref[d][v][u] (u < W) and cost_tar[d][v][u - d]
+// (0 <= u - d < W): the identity stated after Eq. 5.
+#pragma once
+
+#include "zncc_math.hpp"
+
+namespace rsv {
+
+constexpr int kCostTW = 64;
+
+__host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
+  const size_t rows = TH + 2 * R;
+  return rows * (kCostTW + D - 1 + 2 * R) + rows * (kCostTW + 2 * R) +
+         static_cast<size_t>(TH) * (kCostTW + D - 1);
+}
+
+// warped_at(y, x) returns the warped target at in-image (y, x).
+template <int R, int TH, typename TL, typename WarpAt>
+__device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t lpitch, WarpAt warped_at,
+                                          int H, int W, int D, float sigma_min, int u0, int v0,
+                                          float* __restrict__ cost_ref, float* __restrict__ cost_tar,
+                                          float* smem) {
+  constexpr int K = 2 * R + 1;
+  constexpr int NT = kCostTW * TH;
+  const int tid = threadIdx.x;
+  const int tx = tid % kCostTW, ty = tid / kCostTW;
+  const int rows = TH + 2 * R;
+  const int wtw = kCostTW + D - 1 + 2 * R;  // warped tile width
+  const int ltw = kCostTW + 2 * R;          // left tile width
+  const int nt = kCostTW + D - 1;           // target centres visited by the tile
+  float* wt = smem;
+  float* lt = wt + rows * wtw;
+  float* ir = lt + rows * ltw;
+  const int cw0 = u0 - (D - 1) - R;  // global column of warped tile column 0
+
+  for (int i = tid; i < rows * wtw; i += NT) {
+    const int r = i / wtw, c = i - r * wtw;
+    wt[i] = warped_at(clampi(v0 - R + r, 0, H - 1), clampi(cw0 + c, 0, W - 1));
+  }
+  for (int i = tid; i < rows * ltw; i += NT) {
+    const int r = i / ltw, c = i - r * ltw;
+    lt[i] = pixel(left, lpitch, clampi(v0 - R + r, 0, H - 1), clampi(u0 - R + c, 0, W - 1));
+  }
+  __syncthreads();
+  // 1/e_r for target centres x = u0 - (D-1) + c, rows v0 + r.
+  for (int i = tid; i < TH * nt; i += NT) {
+    const int r = i / nt, c = i - r * nt;
+    ir[i] = target_inv<R>(wt + r * wtw + c, wtw, sigma_min);
+  }
+
+  LeftBlock<R> lb;
+  lb.load(lt + ty * ltw + tx, ltw, sigma_min);
+  __syncthreads();
+
+  const int u = u0 + tx;
+  const int v = v0 + ty;
+  const bool row_ok = v < H;
+  const int64_t plane = static_cast<int64_t>(H) * W;
+  const int64_t rowoff = static_cast<int64_t>(v) * W;
+  const float* wrow = wt + ty * wtw + tx + (D - 1);  // window column k at step d: wrow[k - d]
+  const float* irow = ir + ty * nt + tx + (D - 1);   // 1/e_r of centre u - d: irow[-d]
+
+  float win[K][K];  // ring: window column k at step d0 + t lives in slot (k - t) mod K
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) win[j][k] = wrow[j * wtw + k] - lb.shift;
+
+  for (int d0 = 0; d0 < D; d0 += K) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int d = d0 + t;
+      if (d >= D) break;
+      if (d > 0) {
+        const int slot = (K - t) % K;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+          for (int s = 0; s < K; ++s)
+            if (s == slot) win[j][s] = wrow[j * wtw - d] - lb.shift;
+        }
+      }
+      float num = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
+      const float c = (num * lb.inv) * irow[-d];
+      if (row_ok) {
+        if (u < W) cost_ref[d * plane + rowoff + u] = c;
+        const int x = u - d;
+        if (cost_tar && x >= 0 && x < W) cost_tar[d * plane + rowoff + x] = c;
+      }
+    }
+  }
+}
+
+}  // namespace rsv

@@ -10,7 +10,7 @@
 // a later d replaces the best only when strictly greater.
 #include <math.h>
 
-#include "rsv_internal.hpp"
+#include "select_math.hpp"
 
 namespace rsv {
 
@@ -101,13 +101,6 @@ __device__ __forceinline__ int argmax_column(const float* __restrict__ p, int64_
   return arg;
 }
 
-// Eq. 12 on the best and its neighbours; the ends of the range are not refined.
-__device__ __forceinline__ float parabola(const Scan& s, int D) {
-  if (s.arg <= 0 || s.arg >= D - 1) return static_cast<float>(s.arg);
-  const float den = 2.f * s.am + 2.f * s.ap - 4.f * s.best;
-  return static_cast<float>(s.arg) + (s.am - s.ap) / den;
-}
-
 __global__ __launch_bounds__(kSelThreads) void select_kernel(
     const float* __restrict__ aref, const float* __restrict__ atar, int H, int W, int D, int tau,
     int32_t* __restrict__ dref, int32_t* __restrict__ dtar, float* __restrict__ dsub,
@@ -127,7 +120,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(
     const int x = u - s.arg;
     const bool ok = (x >= 0) && (abs(s.arg - ltar[x < 0 ? 0 : x]) <= tau);
     dref[row + u] = s.arg;
-    dsub[row + u] = parabola(s, D);
+    dsub[row + u] = parabola(s.arg, s.best, s.am, s.ap, D);
     valid[row + u] = ok ? 1 : 0;
     if (top2) {
       top2[row + u] = s.best;

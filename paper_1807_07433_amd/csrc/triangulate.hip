@@ -4,7 +4,7 @@
 // y = (v - v0) z / f.  Arithmetic in double, rounded once.
 #include <math.h>
 
-#include "warp_math.hpp"
+#include "select_math.hpp"
 
 namespace rsv {
 
@@ -17,21 +17,8 @@ __global__ __launch_bounds__(256) void triangulate_kernel(const float* __restric
   const int v = blockIdx.y;
   if (u >= W || v >= H) return;
   const int64_t i = static_cast<int64_t>(v) * W + u;
-  const double ds = static_cast<double>(dsub[i]);
-  const double df = ds + (pl.a0 + pl.a1 * static_cast<double>(v) +
-                          pl.a2 * (static_cast<double>(u) - ds) - pl.delta);
-  if (dfin) dfin[i] = static_cast<float>(df);
-  if (xyz) {
-    float* o = xyz + 3 * i;
-    if (valid[i] && df > 0.0) {
-      const double z = cam.f * cam.baseline / df;
-      o[0] = static_cast<float>((static_cast<double>(u) - cam.u0) * z / cam.f);
-      o[1] = static_cast<float>((static_cast<double>(v) - cam.v0) * z / cam.f);
-      o[2] = static_cast<float>(z);
-    } else {
-      o[0] = o[1] = o[2] = NAN;
-    }
-  }
+  postprocess_point(dsub[i], valid[i] != 0, u, v, pl, cam, dfin ? dfin + i : nullptr,
+                    xyz ? xyz + 3 * i : nullptr);
 }
 
 }  // namespace rsv

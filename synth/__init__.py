@@ -98,10 +98,16 @@ def road1920_d128(index: int = 0) -> Case:
     return _case("road1920_d128", SCENE_1920, PARAMS_1920, 3000 + index)
 
 
-def batch64_mixed(n_pairs: int = 64, sizes=BATCH_SIZES, ds=BATCH_DS) -> list[Case]:
-    """Uneven batch: every pair has its own size, D, plane and bumps."""
+def _batch_case(args):
+    i, scene, params = args
+    return _case(f"batch64_mixed[{i}]", scene, params, 4000 + i)
+
+
+def batch64_mixed(n_pairs: int = 64, sizes=BATCH_SIZES, ds=BATCH_DS, workers: int = 0) -> list[Case]:
+    """Uneven batch: every pair has its own size, D, plane and bumps.  Each pair is
+    seeded on its own, so `workers` > 1 (a process pool) gives the same pairs."""
     rng = np.random.default_rng(4000)
-    cases = []
+    jobs = []
     for i in range(n_pairs):
         h, w = sizes[rng.integers(len(sizes))]
         D = int(ds[rng.integers(len(ds))])
@@ -110,8 +116,12 @@ def batch64_mixed(n_pairs: int = 64, sizes=BATCH_SIZES, ds=BATCH_DS) -> list[Cas
         nb = int(rng.integers(3, 21))
         scene = RoadScene(h, w, a, b, n_bumps=nb, bump_amp=3.0, noise_right=2.0)
         params = MethodParams(D=D, block_radius=3, agg_radius=5, gamma_d=4.0, gamma_r=0.1)
-        cases.append(_case(f"batch64_mixed[{i}]", scene, params, 4000 + i))
-    return cases
+        jobs.append((i, scene, params))
+    if workers and workers > 1:
+        import concurrent.futures as cf
+        with cf.ProcessPoolExecutor(workers) as ex:
+            return list(ex.map(_batch_case, jobs))
+    return [_batch_case(j) for j in jobs]
 
 
 def diff8_road1280(n_pairs: int = 8) -> tuple[list[Case], list[Plane]]:
