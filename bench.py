@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched form")
     ap.add_argument("--batch-pairs", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy one 512 MiB buffer (reads 512 MiB, writes "
+                         "512 MiB) so counter runs can scale FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -105,7 +108,6 @@ def bench_batch(a, rsv, torch):
     e1.record()
     torch.cuda.synchronize()
     ms_batch = e0.elapsed_time(e1) / a.batch_steps
-    err = plan.error_flag()
     info = plan.info()
     plan.close()
 
@@ -153,8 +155,7 @@ def bench_batch(a, rsv, torch):
             "plain_sequential_ms": round(ms_plain, 4),
             "plain_sequential_value": round(work / (ms_plain * 1e-3) * 1e-6, 2),
             "speedup_vs_plain": round(ms_plain / ms_batch, 4),
-            "tuning": {"lag_bands": tuning.lag_bands, "grid_blocks": tuning.grid_blocks},
-            "plan": info, "error_flag": err, "steps": a.batch_steps}
+            "tuning": tuning.as_dict(), "plan": info, "steps": a.batch_steps}
 
 
 def cpu_baseline(case, rows: int):
@@ -293,6 +294,12 @@ def main():
         "kernels": kernels,
         "library": _lib.LIB_PATH,
     }
+    if a.copy_calibration:
+        src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not a.no_batch:
         out["batched"] = bench_batch(a, rsv, torch)
     if not a.no_cpu_baseline:

@@ -175,10 +175,11 @@ typedef struct {
 
 /* Launch shape of a plan (rsv_tuning_default fills the defaults). */
 typedef struct {
-  int32_t lag_bands;    /* cost bands an aggregation tile row trails the band that
-                           completes its window (0 .. 8)                              */
-  int32_t grid_blocks;  /* persistent workgroups; 0 = as many as are resident at once */
-  int32_t reserved[2];
+  int32_t largest_first;        /* 1: queue the pairs by decreasing W*H*D; 0: as given    */
+  int32_t cost_tiles_per_item;  /* cost work item = this many tiles of 4 rows x 64
+                                   centres (1 .. 16)                                       */
+  int32_t cost_blocks_per_cu;   /* persistent cost workgroups per CU; 0 = as many as fit */
+  int32_t agg_blocks_per_cu;    /* persistent aggregation workgroups per CU; 0 = as fit  */
 } rsv_tuning;
 
 typedef struct rsv_batch_plan rsv_batch_plan;
@@ -186,16 +187,18 @@ typedef struct rsv_batch_plan rsv_batch_plan;
 void rsv_tuning_default(rsv_tuning* t);
 
 /* Builds a plan for the whole batch: device workspace for every pair's two cost
- * volumes and selection state, one work list, and a hipGraph of
- * [reset counters -> persistent fused kernel -> per-pixel tail].
- * The persistent kernel runs warp + ZNCC (the arithmetic of rsv_warp and
- * rsv_cost_volume), bilateral aggregation (that of rsv_aggregate) and
- * winner-take-all for every pair; the tail runs the left-right check, Eq. 12,
+ * volumes and selection state, two work lists, and a hipGraph of
+ *   [reset queue counters] -> [persistent cost kernel] -> [persistent aggregate +
+ *   winner-take-all kernel] -> [per-pixel tail].
+ * The persistent kernels pull work items from atomic counters.  The cost kernel
+ * runs warp + ZNCC (the arithmetic of rsv_warp and rsv_cost_volume).  The second
+ * runs bilateral aggregation (that of rsv_aggregate) with winner-take-all fused in,
+ * writing no aggregated volume.  The tail runs the left-right check, Eq. 12,
  * post-processing and triangulation (those of rsv_select_subpixel and
  * rsv_triangulate).  Every output equals the plain path's bit for bit.
  *   pairs, n   the batch (host array, copied)
  *   p          shared parameters (block_radius, agg_radius, gammas, lr_threshold,
- *              sigma_min)
+ *              sigma_min); p->D is ignored
  *   tuning     launch shape, or NULL for the defaults (see rsv_autotune)
  *   out        host pointer receiving the plan
  * The plan owns its device memory (about 8 * sum(H*W*D) bytes) and graph.
@@ -208,19 +211,18 @@ int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_param
  * concurrently on two streams. */
 int rsv_batch_run(rsv_batch_plan* plan, void* stream);
 
-/* After the caller has synchronised: *flag = 1 if a wait inside the last run hit
- * its spin limit (results then undefined), else 0. */
-int rsv_batch_error(rsv_batch_plan* plan, int32_t* flag);
-
-/* Work items, persistent workgroups and device bytes of a plan (any may be NULL). */
+/* Host arrays n_items[2] and grid_blocks[2] receive the cost / aggregation item
+ * counts and persistent workgroup counts; *workspace_bytes the plan's device bytes.
+ * Any pointer may be NULL. */
 int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items, int32_t* grid_blocks,
                         int64_t* workspace_bytes);
 
 int rsv_batch_plan_destroy(rsv_batch_plan* plan);
 
-/* Times candidate launch shapes (lag_bands x grid_blocks) on this batch, each with
- * its own temporary plan, and returns the fastest in *out and its time in *best_ms
- * (may be NULL).  Writes the pairs' outputs.  Synchronises `stream`. */
+/* Times candidate launch shapes (pair order x cost tiles per item x cost workgroups
+ * per CU) on this batch, each with its own temporary plan, and returns the fastest
+ * in *out and its time in *best_ms (may be NULL).  Writes the pairs' outputs.
+ * Synchronises `stream`. */
 int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p, rsv_tuning* out,
                  float* best_ms, void* stream);
 

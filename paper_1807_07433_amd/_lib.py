@@ -59,7 +59,6 @@ _SIGNATURES = {
     "rsv_tuning_default": (None, [_P]),
     "rsv_batch_plan_create": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P]),
     "rsv_batch_run": (C.c_int, [_P, _P]),
-    "rsv_batch_error": (C.c_int, [_P, _P]),
     "rsv_batch_plan_info": (C.c_int, [_P, _P, _P, _P]),
     "rsv_batch_plan_destroy": (C.c_int, [_P]),
     "rsv_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P, _P]),

@@ -1,5 +1,6 @@
 """Batched form: a plan over many pairs of uneven size and D, run as one graph launch
-(rsv_batch_plan_create / rsv_batch_run).  Marshalling only."""
+of persistent work-queue kernels (rsv_batch_plan_create / rsv_batch_run).
+Marshalling only."""
 from __future__ import annotations
 
 import ctypes as C
@@ -19,7 +20,11 @@ class PairDesc(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("lag_bands", C.c_int32), ("grid_blocks", C.c_int32), ("reserved", C.c_int32 * 2)]
+    _fields_ = [("largest_first", C.c_int32), ("cost_tiles_per_item", C.c_int32),
+                ("cost_blocks_per_cu", C.c_int32), ("agg_blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def default_tuning() -> Tuning:
@@ -77,16 +82,11 @@ class BatchPlan:
         s = _stream() if stream is None else stream
         check(self._lib.rsv_batch_run(self._plan, s), "rsv_batch_run")
 
-    def error_flag(self) -> int:
-        f = C.c_int32()
-        check(self._lib.rsv_batch_error(self._plan, C.byref(f)), "rsv_batch_error")
-        return int(f.value)
-
     def info(self):
-        n, g, b = C.c_int32(), C.c_int32(), C.c_int64()
-        check(self._lib.rsv_batch_plan_info(self._plan, C.byref(n), C.byref(g), C.byref(b)),
-              "rsv_batch_plan_info")
-        return {"items": n.value, "grid_blocks": g.value, "workspace_bytes": b.value}
+        n, g, b = (C.c_int32 * 2)(), (C.c_int32 * 2)(), C.c_int64()
+        check(self._lib.rsv_batch_plan_info(self._plan, n, g, C.byref(b)), "rsv_batch_plan_info")
+        return {"cost_items": n[0], "agg_items": n[1], "cost_blocks": g[0], "agg_blocks": g[1],
+                "workspace_bytes": b.value}
 
     def close(self):
         if self._plan:

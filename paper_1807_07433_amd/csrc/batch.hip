@@ -1,24 +1,23 @@
 // Batched form: many stereo pairs of uneven size and disparity range in one
-// persistent, hipGraph-captured launch.
+// hipGraph launch of persistent work-queue kernels.
 //
-// A plan holds, per pair, the two cost volumes and the running WTA state, plus one
-// global work list.  The persistent kernel (512-thread workgroups) pulls items from
-// an atomic counter:
-//   COST (pair, band, column tile): warp + ZNCC for 8 rows x 64 centres, the same
-//       arithmetic as rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
-//       then marks the band one tile closer to complete.
-//   AGG (pair, tile row, tile column, ref|tar): bilateral aggregation of a 16 x 16
-//       tile on the matrix cores (shared agg_tile, same arithmetic as rsv_aggregate)
-//       with winner-take-all folded in: per pixel the running best, second best and
-//       the winner's neighbours, updated disparity tile by disparity tile exactly as
-//       a scan over d in increasing order would (ties keep the lowest d).  No
+// A plan holds, per pair, the two cost volumes and the WTA state, plus two work
+// lists, and captures the graph
+//     reset counters -> cost kernel -> aggregate+WTA kernel -> tail kernel.
+// The persistent kernels pull items from atomic counters, so pairs of any size and
+// D share the GPU without per-pair launches:
+//   cost items (pair, band of 4 rows, 64 centres): warp + ZNCC with the arithmetic
+//       of rsv_warp / rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
+//   aggregation items (pair, 16 x 16 tile, ref | tar): bilateral aggregation on the
+//       matrix cores with the arithmetic of rsv_aggregate (shared agg_tile) and
+//       winner-take-all folded in: per pixel the running best, second best and the
+//       winner's neighbours, updated disparity tile by disparity tile exactly as a
+//       scan over d in increasing order would (ties keep the lowest d).  No
 //       aggregated volume is written.
-// An AGG item waits (bounded spin) until the cost bands under its window are
-// complete.  Items are listed so that every item an AGG item waits for comes earlier
-// in the list, and an item is only taken by a running workgroup, so every wait ends;
-// a wait that exceeds its spin limit sets an error flag instead of hanging.
-// A tail kernel then applies the left-right check (Eq. 11), the parabola (Eq. 12),
+// The tail applies the left-right check (Eq. 11), the parabola (Eq. 12),
 // post-processing and triangulation per pixel, with the plain path's functions.
+// Every output therefore equals the plain path's bit for bit.  The kernel boundary
+// between cost and aggregation replaces any cross-workgroup wait.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,9 +31,9 @@
 
 namespace rsv {
 
-constexpr int kBatchThreads = 512;
-constexpr int kBandRows = kBatchThreads / kCostTW;  // 8
-constexpr int kSpinLimit = 1 << 22;
+constexpr int kCostThreads = 256;
+constexpr int kBandRows = kCostThreads / kCostTW;  // 4
+constexpr int kAggItemThreads = 1024;
 
 enum : int { kItemCost = 0, kItemAggRef = 1, kItemAggTar = 2 };
 
@@ -52,7 +51,6 @@ struct PairDev {
   float* ref_am;
   float* ref_ap;
   int32_t* tar_arg;
-  int32_t* band_done;
   int32_t* disp_ref;
   int32_t* disp_tar;
   float* disp_sub;
@@ -66,9 +64,7 @@ struct BatchArgs {
   const int4* items;  // {pair, kind, a, b}
   int n_items;
   int* head;
-  int* err;
   float igd2, igr2, sigma_min;
-  int tau;
 };
 
 // Running WTA state of the 256 pixels of one AGG tile, in LDS.
@@ -159,78 +155,83 @@ struct WtaSink {
   }
 };
 
-__device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// Next item of a work list for the whole workgroup (uniform), or -1 when done.
+__device__ __forceinline__ int next_item(int* head, int n_items, int* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
+  __syncthreads();
+  const int it = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();
+  return it < n_items ? it : -1;
+}
 
-template <int R, int A>
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// Cost item {pair, tiles << 8, band, first column tile}: `tiles` consecutive tiles of
+// 64 centres x kBandRows rows.
+template <int R>
+__global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) float cwork[];
   __shared__ int s_item;
+  for (int it; (it = next_item(args.head, args.n_items, &s_item)) >= 0;) {
+    const int4 w = args.items[it];
+    const PairDev* pd = args.pairs + w.x;
+    const uint8_t* right = pd->right;
+    const int64_t rpitch = pd->rpitch;
+    const int W = pd->W;
+    const rsv_plane pl = pd->plane;
+    auto warped_at = [&](int y, int x) { return warp_sample(right, rpitch, W, pl, x, y); };
+    const int last = min(w.w + (w.y >> 8), pd->ncol_tiles);
+    for (int ct = w.w; ct < last; ++ct) {
+      cost_tile<R, kBandRows>(pd->left, pd->lpitch, warped_at, pd->H, W, pd->D, args.sigma_min,
+                              ct * kCostTW, w.z * kBandRows, pd->cref, pd->ctar, cwork);
+      __syncthreads();  // LDS is reused by the next tile
+    }
+  }
+}
+
+template <int A>
+__device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsigned char* smem) {
   WtaState* st = reinterpret_cast<WtaState*>(smem);
   unsigned char* work = smem + ((sizeof(WtaState) + 15) & ~size_t(15));
-  const int tid = threadIdx.x;
-
-  for (;;) {
-    if (tid == 0) s_item = atomicAdd(args.head, 1);
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it >= args.n_items) break;
-    const int4 w = args.items[it];
-    const PairDev P = args.pairs[w.x];
-    if (w.y == kItemCost) {
-      const int v0 = w.z * kBandRows, u0 = w.w * kCostTW;
-      auto warped_at = [&](int y, int x) { return warp_sample(P.right, P.rpitch, P.W, P.plane, x, y); };
-      cost_tile<R, kBandRows>(P.left, P.lpitch, warped_at, P.H, P.W, P.D, args.sigma_min, u0, v0, P.cref,
-                              P.ctar, reinterpret_cast<float*>(work));
-      release_fence();
-      __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(P.band_done + w.z, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const int ty = w.z, tx = w.w;
-      const int by = 16 * ty, bx = 16 * tx;
-      if (tid == 0) {
-        const int b_lo = max(0, (by - A) / kBandRows);
-        const int b_hi = min(P.nbands - 1, (by + 15 + A) / kBandRows);
-        for (int b = b_lo; b <= b_hi; ++b) {
-          int spins = 0;
-          while (__hip_atomic_load(P.band_done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                 P.ncol_tiles) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-              atomicExch(args.err, 1);
-              break;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      acquire_fence();
-      const bool full = w.y == kItemAggRef;
-      WtaSink sink{st, P.D, full};
+  const PairDev* pd = args.pairs + w.x;
+  const int H = pd->H, W = pd->W, D = pd->D;
+  const int by = 16 * w.z, bx = 16 * w.w;
+  const bool full = w.y == kItemAggRef;
+  WtaSink sink{st, D, full};
+  if (full) {
+    const uint8_t* left = pd->left;
+    const int64_t lpitch = pd->lpitch;
+    auto guide = [&](int Y, int X) { return pixel(left, lpitch, Y, X); };
+    agg_tile<A, kAggItemThreads>(pd->cref, H, W, D, args.igd2, args.igr2, by, bx, guide, sink, work);
+  } else {
+    const uint8_t* right = pd->right;
+    const int64_t rpitch = pd->rpitch;
+    const rsv_plane pl = pd->plane;
+    auto guide = [&](int Y, int X) { return warp_sample(right, rpitch, W, pl, X, Y); };
+    agg_tile<A, kAggItemThreads>(pd->ctar, H, W, D, args.igd2, args.igr2, by, bx, guide, sink, work);
+  }
+  // agg_tile ends with a barrier: the state of all 256 pixels is complete
+  if (threadIdx.x < 256) {
+    const int q = threadIdx.x;
+    const int Y = by + (q >> 4), X = bx + (q & 15);
+    if (Y < H && X < W) {
+      const int64_t i = static_cast<int64_t>(Y) * W + X;
       if (full) {
-        auto guide = [&](int Y, int X) { return pixel(P.left, P.lpitch, Y, X); };
-        agg_tile<A, kBatchThreads>(P.cref, P.H, P.W, P.D, args.igd2, args.igr2, by, bx, guide, sink, work);
+        pd->ref_arg[i] = st->arg[q];
+        pd->ref_best[i] = st->best[q];
+        pd->ref_am[i] = st->am[q];
+        pd->ref_ap[i] = st->ap[q];
       } else {
-        auto guide = [&](int Y, int X) { return warp_sample(P.right, P.rpitch, P.W, P.plane, X, Y); };
-        agg_tile<A, kBatchThreads>(P.ctar, P.H, P.W, P.D, args.igd2, args.igr2, by, bx, guide, sink, work);
-      }
-      // agg_tile ends with a barrier: the state is complete
-      for (int q = tid; q < 256; q += kBatchThreads) {
-        const int Y = by + (q >> 4), X = bx + (q & 15);
-        if (Y < P.H && X < P.W) {
-          const int64_t i = static_cast<int64_t>(Y) * P.W + X;
-          if (full) {
-            P.ref_arg[i] = st->arg[q];
-            P.ref_best[i] = st->best[q];
-            P.ref_am[i] = st->am[q];
-            P.ref_ap[i] = st->ap[q];
-          } else {
-            P.tar_arg[i] = st->arg[q];
-          }
-        }
+        pd->tar_arg[i] = st->arg[q];
       }
     }
+  }
+}
+
+template <int A>
+__global__ __launch_bounds__(kAggItemThreads) void batch_agg_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item;
+  for (int it; (it = next_item(args.head, args.n_items, &s_item)) >= 0;) {
+    batch_agg_item<A>(args, args.items[it], smem);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -255,13 +256,8 @@ __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, i
   }
 }
 
-__global__ void batch_reset_kernel(int* head, int* err, int32_t* counters, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    *head = 0;
-    *err = 0;
-  }
-  if (i < n) counters[i] = 0;
+__global__ void batch_reset_kernel(int* heads) {
+  if (threadIdx.x < 2) heads[threadIdx.x] = 0;
 }
 
 }  // namespace rsv
@@ -269,65 +265,54 @@ __global__ void batch_reset_kernel(int* head, int* err, int32_t* counters, int n
 // ------------------------------------------------------------------ host side
 struct rsv_batch_plan {
   int n_pairs = 0;
-  int R = 0, A = 0;
   rsv_tuning tuning{};
-  void* dev_mem = nullptr;       // one allocation: pair table, items, counters, workspace
+  void* dev_mem = nullptr;  // one allocation: pair table, item lists, counters, workspace
   rsv::PairDev* d_pairs = nullptr;
-  int4* d_items = nullptr;
-  int* d_head = nullptr;
-  int* d_err = nullptr;
-  int32_t* d_counters = nullptr;
-  int n_counters = 0;
-  int n_items = 0;
-  int max_pixels = 0;
-  rsv::BatchArgs args{};
+  int* d_heads = nullptr;   // [cost, aggregation]
+  rsv::BatchArgs cost_args{}, agg_args{};
+  int n_cost_items = 0, n_agg_items = 0;
+  int cost_grid = 0, agg_grid = 0;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int grid = 0;
 };
 
 namespace rsv {
 namespace {
 
-template <int R, int A>
-const void* batch_kernel_ptr() {
-  return reinterpret_cast<const void*>(batch_kernel<R, A>);
+template <int R>
+const void* cost_kernel_ptr() {
+  return reinterpret_cast<const void*>(batch_cost_kernel<R>);
+}
+template <int A>
+const void* agg_kernel_ptr() {
+  return reinterpret_cast<const void*>(batch_agg_kernel<A>);
 }
 
-const void* pick_batch_kernel(int R, int A) {
-#define RSV_BK(r)                                             \
-  switch (A) {                                                \
-    case 1: return batch_kernel_ptr<r, 1>();                  \
-    case 2: return batch_kernel_ptr<r, 2>();                  \
-    case 3: return batch_kernel_ptr<r, 3>();                  \
-    case 4: return batch_kernel_ptr<r, 4>();                  \
-    case 5: return batch_kernel_ptr<r, 5>();                  \
-    case 6: return batch_kernel_ptr<r, 6>();                  \
-    default: return nullptr;                                  \
-  }
+const void* pick_cost_kernel(int R) {
   switch (R) {
-    case 1: RSV_BK(1)
-    case 2: RSV_BK(2)
-    case 3: RSV_BK(3)
-    case 4: RSV_BK(4)
+    case 1: return cost_kernel_ptr<1>();
+    case 2: return cost_kernel_ptr<2>();
+    case 3: return cost_kernel_ptr<3>();
+    case 4: return cost_kernel_ptr<4>();
     default: return nullptr;
   }
-#undef RSV_BK
 }
 
-size_t batch_lds_bytes(int R, int A, int maxD) {
-  size_t agg = 0;
+const void* pick_agg_kernel(int A, size_t* lds) {
+  size_t t = 0;
+  const void* k = nullptr;
   switch (A) {
-    case 1: agg = agg_tile_lds_bytes<1>(); break;
-    case 2: agg = agg_tile_lds_bytes<2>(); break;
-    case 3: agg = agg_tile_lds_bytes<3>(); break;
-    case 4: agg = agg_tile_lds_bytes<4>(); break;
-    case 5: agg = agg_tile_lds_bytes<5>(); break;
-    default: agg = agg_tile_lds_bytes<6>(); break;
+    case 1: t = agg_tile_lds_bytes<1>(); k = agg_kernel_ptr<1>(); break;
+    case 2: t = agg_tile_lds_bytes<2>(); k = agg_kernel_ptr<2>(); break;
+    case 3: t = agg_tile_lds_bytes<3>(); k = agg_kernel_ptr<3>(); break;
+    case 4: t = agg_tile_lds_bytes<4>(); k = agg_kernel_ptr<4>(); break;
+    case 5: t = agg_tile_lds_bytes<5>(); k = agg_kernel_ptr<5>(); break;
+    case 6: t = agg_tile_lds_bytes<6>(); k = agg_kernel_ptr<6>(); break;
+    default: return nullptr;
   }
-  const size_t cost = sizeof(float) * cost_tile_lds_floats(maxD, R, kBandRows);
-  return ((sizeof(WtaState) + 15) & ~size_t(15)) + std::max(agg, cost);
+  *lds = ((sizeof(WtaState) + 15) & ~size_t(15)) + t;
+  return k;
 }
 
 int validate_pair(const rsv_pair_desc& pd, int K) {
@@ -337,7 +322,6 @@ int validate_pair(const rsv_pair_desc& pd, int K) {
   if (pd.left.height != pd.right.height || pd.left.width != pd.right.width) return RSV_E_SHAPE;
   if (pd.left.height < K || pd.left.width < K) return RSV_E_SHAPE;
   if (pd.D < 1 || pd.D > RSV_MAX_D) return RSV_E_SHAPE;
-  if (pd.left.width > 16384) return RSV_E_SHAPE;
   if (!pd.disp_sub || !pd.valid) return RSV_E_NULL;
   if (!(pd.camera.f > 0.0) || !(pd.camera.baseline > 0.0)) return RSV_E_PARAM;
   return RSV_OK;
@@ -348,9 +332,10 @@ int validate_pair(const rsv_pair_desc& pd, int K) {
 
 extern "C" void rsv_tuning_default(rsv_tuning* t) {
   if (!t) return;
-  t->lag_bands = 1;
-  t->grid_blocks = 0;
-  t->reserved[0] = t->reserved[1] = 0;
+  t->largest_first = 1;
+  t->cost_tiles_per_item = 2;
+  t->cost_blocks_per_cu = 0;
+  t->agg_blocks_per_cu = 0;
 }
 
 extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
@@ -366,21 +351,31 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   rsv_tuning tn;
   rsv_tuning_default(&tn);
   if (tuning) tn = *tuning;
-  if (tn.lag_bands < 0 || tn.lag_bands > 8 || tn.grid_blocks < 0) return RSV_E_PARAM;
+  if (tn.cost_tiles_per_item < 1 || tn.cost_tiles_per_item > 16 || tn.cost_blocks_per_cu < 0 ||
+      tn.agg_blocks_per_cu < 0)
+    return RSV_E_PARAM;
   int maxD = 0;
   for (int i = 0; i < n; ++i) {
     if (int s = validate_pair(pairs[i], K)) return s;
     maxD = std::max(maxD, pairs[i].D);
   }
 
-  // ---- sizes and the work list
+  // pair order: as given, or largest W*H*D first (the big pairs do not end the queue)
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  if (tn.largest_first)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const double wa = double(pairs[a].left.width) * pairs[a].left.height * pairs[a].D;
+      const double wb = double(pairs[b].left.width) * pairs[b].left.height * pairs[b].D;
+      return wa > wb;
+    });
+
   std::vector<PairDev> pd(n);
-  std::vector<int4> items;
+  std::vector<int4> cost_items, agg_items;
   size_t ws_bytes = 0;
-  int n_counters = 0, max_pixels = 0;
+  int max_pixels = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   std::vector<size_t> off_cref(n), off_ctar(n), off_maps(n);
-  std::vector<int> off_cnt(n);
   for (int i = 0; i < n; ++i) {
     const rsv_pair_desc& q = pairs[i];
     const int H = q.left.height, W = q.left.width, D = q.D;
@@ -391,9 +386,6 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     ws_bytes = align(ws_bytes + sizeof(float) * N * D);
     off_maps[i] = ws_bytes;
     ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float) * 3));
-    off_cnt[i] = n_counters;
-    const int nb = (H + kBandRows - 1) / kBandRows;
-    n_counters += nb;
     max_pixels = std::max<int>(max_pixels, static_cast<int>(N));
     PairDev& P = pd[i];
     P.left = static_cast<const uint8_t*>(q.left.data);
@@ -403,7 +395,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.H = H;
     P.W = W;
     P.D = D;
-    P.nbands = nb;
+    P.nbands = (H + kBandRows - 1) / kBandRows;
     P.ncol_tiles = (W + D - 1 + kCostTW - 1) / kCostTW;
     P.tiles_x = (W + 15) / 16;
     P.plane = q.plane;
@@ -414,47 +406,35 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.valid = q.valid;
     P.disp_final = q.disp_final;
     P.xyz = q.xyz;
-    // work list: cost bands in order; an aggregation tile row follows the cost band
-    // that completes its window, delayed by lag_bands bands
-    const int nty = (H + 15) / 16;
-    int next_row = 0;
-    auto last_band = [&](int ty) { return std::min(nb - 1, (16 * ty + 15 + A) / kBandRows); };
-    for (int b = 0; b < nb; ++b) {
-      for (int ct = 0; ct < P.ncol_tiles; ++ct) items.push_back(make_int4(i, kItemCost, b, ct));
-      while (next_row < nty && last_band(next_row) + tn.lag_bands <= b) {
-        for (int tx = 0; tx < P.tiles_x; ++tx) {
-          items.push_back(make_int4(i, kItemAggRef, next_row, tx));
-          items.push_back(make_int4(i, kItemAggTar, next_row, tx));
-        }
-        ++next_row;
-      }
-    }
-    for (; next_row < nty; ++next_row)
+  }
+  for (int i : order) {
+    const PairDev& P = pd[i];
+    for (int b = 0; b < P.nbands; ++b)
+      for (int ct = 0; ct < P.ncol_tiles; ct += tn.cost_tiles_per_item)
+        cost_items.push_back(make_int4(i, kItemCost | (tn.cost_tiles_per_item << 8), b, ct));
+    for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
       for (int tx = 0; tx < P.tiles_x; ++tx) {
-        items.push_back(make_int4(i, kItemAggRef, next_row, tx));
-        items.push_back(make_int4(i, kItemAggTar, next_row, tx));
+        agg_items.push_back(make_int4(i, kItemAggRef, ty, tx));
+        agg_items.push_back(make_int4(i, kItemAggTar, ty, tx));
       }
   }
 
   rsv_batch_plan* plan = new (std::nothrow) rsv_batch_plan();
   if (!plan) return RSV_E_NOMEM;
   plan->n_pairs = n;
-  plan->R = R;
-  plan->A = A;
   plan->tuning = tn;
-  plan->n_items = static_cast<int>(items.size());
-  plan->n_counters = n_counters;
-  plan->max_pixels = max_pixels;
+  plan->n_cost_items = static_cast<int>(cost_items.size());
+  plan->n_agg_items = static_cast<int>(agg_items.size());
 
   size_t off = 0;
   const size_t o_pairs = off;
   off = align(off + sizeof(PairDev) * n);
-  const size_t o_items = off;
-  off = align(off + sizeof(int4) * items.size());
-  const size_t o_ctl = off;
+  const size_t o_ci = off;
+  off = align(off + sizeof(int4) * cost_items.size());
+  const size_t o_ai = off;
+  off = align(off + sizeof(int4) * agg_items.size());
+  const size_t o_heads = off;
   off = align(off + sizeof(int) * 2);
-  const size_t o_cnt = off;
-  off = align(off + sizeof(int32_t) * n_counters);
   const size_t o_ws = off;
   off += ws_bytes;
   hipError_t e = hipMalloc(&plan->dev_mem, off);
@@ -465,10 +445,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   }
   unsigned char* base = static_cast<unsigned char*>(plan->dev_mem);
   plan->d_pairs = reinterpret_cast<PairDev*>(base + o_pairs);
-  plan->d_items = reinterpret_cast<int4*>(base + o_items);
-  plan->d_head = reinterpret_cast<int*>(base + o_ctl);
-  plan->d_err = plan->d_head + 1;
-  plan->d_counters = reinterpret_cast<int32_t*>(base + o_cnt);
+  plan->d_heads = reinterpret_cast<int*>(base + o_heads);
   for (int i = 0; i < n; ++i) {
     PairDev& P = pd[i];
     const size_t N = static_cast<size_t>(P.H) * P.W;
@@ -480,7 +457,6 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.ref_best = reinterpret_cast<float*>(P.tar_arg + N);
     P.ref_am = P.ref_best + N;
     P.ref_ap = P.ref_am + N;
-    P.band_done = plan->d_counters + off_cnt[i];
   }
   auto fail = [&](hipError_t err) {
     set_hip_error(err);
@@ -489,51 +465,66 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   };
   if ((e = hipMemcpy(plan->d_pairs, pd.data(), sizeof(PairDev) * n, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
-  if ((e = hipMemcpy(plan->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice)) !=
-      hipSuccess)
+  if ((e = hipMemcpy(base + o_ci, cost_items.data(), sizeof(int4) * cost_items.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMemcpy(base + o_ai, agg_items.data(), sizeof(int4) * agg_items.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
 
-  const void* kern = pick_batch_kernel(R, A);
-  if (!kern) {
+  const void* ck = pick_cost_kernel(R);
+  size_t agg_lds = 0;
+  const void* ak = pick_agg_kernel(A, &agg_lds);
+  if (!ck || !ak) {
     rsv_batch_plan_destroy(plan);
     return RSV_E_PARAM;
   }
-  const size_t lds = batch_lds_bytes(R, A, maxD);
-  if ((e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds))) !=
+  const size_t cost_lds = sizeof(float) * cost_tile_lds_floats(maxD, R, kBandRows);
+  if ((e = hipFuncSetAttribute(ck, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(cost_lds))) !=
       hipSuccess)
     return fail(e);
-  int dev = 0, cus = 0;
+  if ((e = hipFuncSetAttribute(ak, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(agg_lds))) !=
+      hipSuccess)
+    return fail(e);
+  int dev = 0, cus = 0, cost_fit = 0, agg_fit = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchThreads, lds)) != hipSuccess)
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cost_fit, ck, kCostThreads, cost_lds)) != hipSuccess)
     return fail(e);
-  if (per_cu < 1) {
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&agg_fit, ak, kAggItemThreads, agg_lds)) != hipSuccess)
+    return fail(e);
+  if (cost_fit < 1 || agg_fit < 1) {
     rsv_batch_plan_destroy(plan);
     return RSV_E_PARAM;
   }
-  plan->grid = tn.grid_blocks > 0 ? tn.grid_blocks : cus * per_cu;
+  const int cpc = tn.cost_blocks_per_cu > 0 ? std::min(tn.cost_blocks_per_cu, cost_fit) : cost_fit;
+  const int apc = tn.agg_blocks_per_cu > 0 ? std::min(tn.agg_blocks_per_cu, agg_fit) : agg_fit;
+  plan->cost_grid = std::min(cus * cpc, std::max(1, plan->n_cost_items));
+  plan->agg_grid = std::min(cus * apc, std::max(1, plan->n_agg_items));
 
-  BatchArgs& a = plan->args;
-  a.pairs = plan->d_pairs;
-  a.items = plan->d_items;
-  a.n_items = plan->n_items;
-  a.head = plan->d_head;
-  a.err = plan->d_err;
-  a.igd2 = 1.f / (p->gamma_d * p->gamma_d);
-  a.igr2 = 1.f / (p->gamma_r * p->gamma_r);
-  a.sigma_min = p->sigma_min;
-  a.tau = p->lr_threshold;
+  BatchArgs& ca = plan->cost_args;
+  ca.pairs = plan->d_pairs;
+  ca.items = reinterpret_cast<const int4*>(base + o_ci);
+  ca.n_items = plan->n_cost_items;
+  ca.head = plan->d_heads;
+  ca.sigma_min = p->sigma_min;
+  ca.igd2 = 1.f / (p->gamma_d * p->gamma_d);
+  ca.igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  BatchArgs& aa = plan->agg_args;
+  aa = ca;
+  aa.items = reinterpret_cast<const int4*>(base + o_ai);
+  aa.n_items = plan->n_agg_items;
+  aa.head = plan->d_heads + 1;
 
-  // graph: reset counters -> persistent kernel -> tail
+  // graph: reset counters -> cost kernel -> aggregation + WTA kernel -> tail
   if ((e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
-  const int nrc = std::max(1, n_counters);
-  batch_reset_kernel<<<(nrc + 255) / 256, 256, 0, plan->capture_stream>>>(plan->d_head, plan->d_err,
-                                                                          plan->d_counters, n_counters);
-  void* kargs[] = {&plan->args};
-  hipLaunchKernel(kern, dim3(plan->grid), dim3(kBatchThreads), kargs, lds, plan->capture_stream);
+  batch_reset_kernel<<<1, 64, 0, plan->capture_stream>>>(plan->d_heads);
+  void* cargs[] = {&plan->cost_args};
+  hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
+  void* aargs[] = {&plan->agg_args};
+  hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
   const int tail_x = std::min(1024, (max_pixels + 255) / 256);
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
@@ -556,24 +547,17 @@ extern "C" int rsv_batch_run(rsv_batch_plan* plan, void* stream) {
   return RSV_OK;
 }
 
-extern "C" int rsv_batch_error(rsv_batch_plan* plan, int32_t* flag) {
-  using namespace rsv;
-  if (!plan || !flag) return RSV_E_NULL;
-  int v = 0;
-  hipError_t e = hipMemcpy(&v, plan->d_err, sizeof(int), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    set_hip_error(e);
-    return RSV_E_HIP;
-  }
-  *flag = v;
-  return RSV_OK;
-}
-
 extern "C" int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items, int32_t* grid_blocks,
                                    int64_t* workspace_bytes) {
   if (!plan) return RSV_E_NULL;
-  if (n_items) *n_items = plan->n_items;
-  if (grid_blocks) *grid_blocks = plan->grid;
+  if (n_items) {
+    n_items[0] = plan->n_cost_items;
+    n_items[1] = plan->n_agg_items;
+  }
+  if (grid_blocks) {
+    grid_blocks[0] = plan->cost_grid;
+    grid_blocks[1] = plan->agg_grid;
+  }
   if (workspace_bytes) {
     size_t sz = 0;
     hipMemPtrGetInfo(plan->dev_mem, &sz);
@@ -600,44 +584,38 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
   rsv_tuning best;
   rsv_tuning_default(&best);
   float best_t = 1e30f;
-  int cus = 0, dev = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RSV_E_HIP;
   int status = RSV_OK;
-  const int lags[] = {0, 1, 2, 4};
-  const int grids[] = {cus, 2 * cus, 4 * cus};
-  for (int lag : lags)
-    for (int g : grids) {
-      rsv_tuning t;
-      rsv_tuning_default(&t);
-      t.lag_bands = lag;
-      t.grid_blocks = g;
-      rsv_batch_plan* plan = nullptr;
-      int s = rsv_batch_plan_create(pairs, n, p, &t, &plan);
-      if (s != RSV_OK) {
-        status = s;
-        continue;
+  for (int lf = 0; lf <= 1; ++lf)
+    for (int tiles : {1, 2, 4})
+      for (int cpc : {0, 2}) {
+        rsv_tuning t;
+        rsv_tuning_default(&t);
+        t.largest_first = lf;
+        t.cost_tiles_per_item = tiles;
+        t.cost_blocks_per_cu = cpc;
+        rsv_batch_plan* plan = nullptr;
+        const int s = rsv_batch_plan_create(pairs, n, p, &t, &plan);
+        if (s != RSV_OK) {
+          status = s;
+          continue;
+        }
+        rsv_batch_run(plan, st);  // warm-up
+        hipEventRecord(e0, st);
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) rsv_batch_run(plan, st);
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        rsv_batch_plan_destroy(plan);
+        if (ms < best_t) {
+          best_t = ms;
+          best = t;
+        }
       }
-      rsv_batch_run(plan, st);  // warm-up
-      hipEventRecord(e0, st);
-      const int reps = 3;
-      for (int r = 0; r < reps; ++r) rsv_batch_run(plan, st);
-      hipEventRecord(e1, st);
-      hipEventSynchronize(e1);
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
-      int32_t err = 0;
-      rsv_batch_error(plan, &err);
-      rsv_batch_plan_destroy(plan);
-      if (!err && ms < best_t) {
-        best_t = ms;
-        best = t;
-      }
-    }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (best_t >= 1e30f) return status != RSV_OK ? status : RSV_E_HIP;

@@ -8,6 +8,9 @@
 // one new column of 2R+1 values from LDS and spends (2R+1)^2 FMAs.  The value for
 // (u, v, d) is written to cost_ref[d][v][u] (u < W) and cost_tar[d][v][u - d]
 // (0 <= u - d < W): the identity stated after Eq. 5.
+// The warped tile is stored minus 128 (kWarpShift): the centred left values sum to
+// zero, so the dot product is unchanged while its FP32 terms stay small.  Its row
+// stride is a compile-time constant so the column reads use immediate offsets.
 #pragma once
 
 #include "zncc_math.hpp"
@@ -15,11 +18,12 @@
 namespace rsv {
 
 constexpr int kCostTW = 64;
+constexpr int kWarpStride = kCostTW + RSV_MAX_D - 1 + 2 * RSV_MAX_BLOCK_RADIUS + 1;  // 584
+constexpr float kWarpShift = 128.f;
 
 __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
   const size_t rows = TH + 2 * R;
-  return rows * (kCostTW + D - 1 + 2 * R) + rows * (kCostTW + 2 * R) +
-         static_cast<size_t>(TH) * (kCostTW + D - 1);
+  return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1);
 }
 
 // warped_at(y, x) returns the warped target at in-image (y, x).
@@ -32,8 +36,9 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   constexpr int NT = kCostTW * TH;
   const int tid = threadIdx.x;
   const int tx = tid % kCostTW, ty = tid / kCostTW;
+  constexpr int wtw = kWarpStride;          // warped tile row stride
   const int rows = TH + 2 * R;
-  const int wtw = kCostTW + D - 1 + 2 * R;  // warped tile width
+  const int wtc = kCostTW + D - 1 + 2 * R;  // warped tile columns in use
   const int ltw = kCostTW + 2 * R;          // left tile width
   const int nt = kCostTW + D - 1;           // target centres visited by the tile
   float* wt = smem;
@@ -41,9 +46,9 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   float* ir = lt + rows * ltw;
   const int cw0 = u0 - (D - 1) - R;  // global column of warped tile column 0
 
-  for (int i = tid; i < rows * wtw; i += NT) {
-    const int r = i / wtw, c = i - r * wtw;
-    wt[i] = warped_at(clampi(v0 - R + r, 0, H - 1), clampi(cw0 + c, 0, W - 1));
+  for (int i = tid; i < rows * wtc; i += NT) {
+    const int r = i / wtc, c = i - r * wtc;
+    wt[r * wtw + c] = warped_at(clampi(v0 - R + r, 0, H - 1), clampi(cw0 + c, 0, W - 1)) - kWarpShift;
   }
   for (int i = tid; i < rows * ltw; i += NT) {
     const int r = i / ltw, c = i - r * ltw;
@@ -72,7 +77,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
 #pragma unroll
   for (int j = 0; j < K; ++j)
 #pragma unroll
-    for (int k = 0; k < K; ++k) win[j][k] = wrow[j * wtw + k] - lb.shift;
+    for (int k = 0; k < K; ++k) win[j][k] = wrow[j * wtw + k];
 
   for (int d0 = 0; d0 < D; d0 += K) {
 #pragma unroll
@@ -85,7 +90,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
         for (int j = 0; j < K; ++j) {
 #pragma unroll
           for (int s = 0; s < K; ++s)
-            if (s == slot) win[j][s] = wrow[j * wtw - d] - lb.shift;
+            if (s == slot) win[j][s] = wrow[j * wtw - d];
         }
       }
       float num = 0.f;

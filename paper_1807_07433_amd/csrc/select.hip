@@ -2,105 +2,87 @@
 // the left-right consistency check (Sec. II-B.4, Eq. 11) and the parabola subpixel
 // refinement (Eq. 12).
 //
-// One block per image row.  Pass 1 scans the target volume for every pixel of the
-// row (threads stride over u, each walking d with coalesced loads) and keeps the
-// target disparities of the row in LDS.  Pass 2 scans the reference volume,
-// keeping best / second-best and the neighbours of the running best, then checks
-// the match against the target row in LDS and refines.  Ties go to the lowest d:
-// a later d replaces the best only when strictly greater.
+// Each thread walks d for one pixel in both aggregated volumes at once (coalesced
+// loads across the row), keeping the target argmax and, for the reference volume,
+// the best, second best and the neighbours of the running best.  Ties go to the
+// lowest d: a later d replaces the best only when strictly greater.
 #include <math.h>
 
 #include "select_math.hpp"
 
 namespace rsv {
 
-constexpr int kSelThreads = 256;
+constexpr int kSelThreads = 1024;
 constexpr int kSelMaxW = 16384;
+constexpr int kSelUnroll = 8;
 
 struct Scan {
   float best, second, am, ap;
   int arg;
 };
 
-// Walk d = 0 .. D-1 of column `p` (stride `plane`).  Loads run ahead of the
-// compare chain in groups of 8.
-__device__ __forceinline__ Scan scan_column(const float* __restrict__ p, int64_t plane, int D) {
-  Scan s;
-  s.best = p[0];
+// One step of the reference scan at disparity d with value a (strictly greater
+// replaces the best, so ties keep the lowest d).
+__device__ __forceinline__ void scan_step(Scan& s, bool& need_next, float& prev, float a, int d) {
+  if (need_next) {
+    s.ap = a;
+    need_next = false;
+  }
+  if (a > s.best) {
+    s.second = s.best;
+    s.best = a;
+    s.arg = d;
+    s.am = prev;
+    need_next = true;
+  } else if (a > s.second) {
+    s.second = a;
+  }
+  prev = a;
+}
+
+// Walk d = 0 .. D-1 of one pixel in both volumes (stride `plane`), loads for both
+// running ahead of the compare chains in groups of kSelUnroll.
+__device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const float* __restrict__ pt,
+                                          int64_t plane, int D, Scan& s, int& targ) {
+  s.best = pr[0];
   s.second = -INFINITY;
   s.am = 0.f;
   s.ap = 0.f;
   s.arg = 0;
   bool need_next = true;  // the value after the current best is its right neighbour
   float prev = s.best;
+  float tbest = pt[0];
+  targ = 0;
   int d = 1;
-  for (; d + 8 <= D; d += 8) {
-    float a[8];
+  for (; d + kSelUnroll <= D; d += kSelUnroll) {
+    float a[kSelUnroll], b[kSelUnroll];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = p[(d + i) * plane];
+    for (int i = 0; i < kSelUnroll; ++i) {
+      a[i] = pr[(d + i) * plane];
+      b[i] = pt[(d + i) * plane];
+    }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (need_next) {
-        s.ap = a[i];
-        need_next = false;
+    for (int i = 0; i < kSelUnroll; ++i) {
+      scan_step(s, need_next, prev, a[i], d + i);
+      if (b[i] > tbest) {
+        tbest = b[i];
+        targ = d + i;
       }
-      if (a[i] > s.best) {
-        s.second = s.best;
-        s.best = a[i];
-        s.arg = d + i;
-        s.am = prev;
-        need_next = true;
-      } else if (a[i] > s.second) {
-        s.second = a[i];
-      }
-      prev = a[i];
     }
   }
   for (; d < D; ++d) {
-    const float a = p[d * plane];
-    if (need_next) {
-      s.ap = a;
-      need_next = false;
+    scan_step(s, need_next, prev, pr[d * plane], d);
+    const float b = pt[d * plane];
+    if (b > tbest) {
+      tbest = b;
+      targ = d;
     }
-    if (a > s.best) {
-      s.second = s.best;
-      s.best = a;
-      s.arg = d;
-      s.am = prev;
-      need_next = true;
-    } else if (a > s.second) {
-      s.second = a;
-    }
-    prev = a;
   }
-  return s;
 }
 
-__device__ __forceinline__ int argmax_column(const float* __restrict__ p, int64_t plane, int D) {
-  float best = p[0];
-  int arg = 0;
-  int d = 1;
-  for (; d + 8 <= D; d += 8) {
-    float a[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = p[(d + i) * plane];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (a[i] > best) {
-        best = a[i];
-        arg = d + i;
-      }
-  }
-  for (; d < D; ++d) {
-    const float a = p[d * plane];
-    if (a > best) {
-      best = a;
-      arg = d;
-    }
-  }
-  return arg;
-}
-
+// One block per image row, walking the row in chunks of kSelThreads columns from
+// left to right.  The left-right lookup at u - d only reaches columns of the
+// current or an earlier chunk, whose target disparities are already in LDS.
 __global__ __launch_bounds__(kSelThreads) void select_kernel(
     const float* __restrict__ aref, const float* __restrict__ atar, int H, int W, int D, int tau,
     int32_t* __restrict__ dref, int32_t* __restrict__ dtar, float* __restrict__ dsub,
@@ -109,22 +91,26 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(
   const int v = blockIdx.x;
   const int64_t plane = static_cast<int64_t>(H) * W;
   const int64_t row = static_cast<int64_t>(v) * W;
-  for (int u = threadIdx.x; u < W; u += kSelThreads) {
-    const int a = argmax_column(atar + row + u, plane, D);
-    ltar[u] = a;
-    dtar[row + u] = a;
-  }
-  __syncthreads();
-  for (int u = threadIdx.x; u < W; u += kSelThreads) {
-    const Scan s = scan_column(aref + row + u, plane, D);
-    const int x = u - s.arg;
-    const bool ok = (x >= 0) && (abs(s.arg - ltar[x < 0 ? 0 : x]) <= tau);
-    dref[row + u] = s.arg;
-    dsub[row + u] = parabola(s.arg, s.best, s.am, s.ap, D);
-    valid[row + u] = ok ? 1 : 0;
-    if (top2) {
-      top2[row + u] = s.best;
-      top2[plane + row + u] = s.second;
+  for (int c0 = 0; c0 < W; c0 += kSelThreads) {
+    const int u = c0 + threadIdx.x;
+    Scan s{};
+    int ta = 0;
+    if (u < W) {
+      scan_pair(aref + row + u, atar + row + u, plane, D, s, ta);
+      ltar[u] = ta;
+      dtar[row + u] = ta;
+    }
+    __syncthreads();
+    if (u < W) {
+      const int x = u - s.arg;
+      const bool ok = (x >= 0) && (abs(s.arg - ltar[x < 0 ? 0 : x]) <= tau);
+      dref[row + u] = s.arg;
+      dsub[row + u] = parabola(s.arg, s.best, s.am, s.ap, D);
+      valid[row + u] = ok ? 1 : 0;
+      if (top2) {
+        top2[row + u] = s.best;
+        top2[plane + row + u] = s.second;
+      }
     }
   }
 }

@@ -5,8 +5,8 @@
 //     c = sum_i (n l_i - S_l) r_i / (e_l e_r)
 // which is Eq. 3 rewritten with the left block centred (the centred values sum to
 // zero, so mu_r drops out).  For uint8 images n l_i - S_l is an exact integer.
-// Any per-entry constant k may be subtracted from the r_i without changing the
-// sum; subtracting the left block mean keeps the FP32 products small.
+// Any constant may be subtracted from the r_i without changing the sum (the cost
+// tile subtracts 128), which keeps the FP32 products small.
 #pragma once
 
 #include "rsv_internal.hpp"
@@ -23,13 +23,12 @@ __device__ __forceinline__ float inv_block_norm(double n, double S, double Q, fl
 }
 
 // Left block of width K = 2R+1 read from a row-major tile: produces the centred
-// values n*l - S (FP32), the shift constant S/n and 1/e_l.
+// values n*l - S (FP32) and 1/e_l.
 template <int R>
 struct LeftBlock {
   static constexpr int K = 2 * R + 1;
   static constexpr int N = K * K;
   float c[K][K];
-  float shift;
   float inv;
 
   __device__ __forceinline__ void load(const float* tile, int stride, float sigma_min) {
@@ -44,7 +43,6 @@ struct LeftBlock {
         Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
       }
     inv = inv_block_norm(static_cast<double>(N), S, Q, sigma_min);
-    shift = static_cast<float>(S / N);
 #pragma unroll
     for (int j = 0; j < K; ++j)
 #pragma unroll
