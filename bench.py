@@ -46,6 +46,11 @@ def parse():
     return ap.parse_args()
 
 
+def mde_per_s(W: int, H: int, D: int, seconds: float) -> float:
+    """Eq. 13: millions of disparity evaluations per second."""
+    return W * H * D / seconds * 1e-6
+
+
 def source_sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
@@ -257,7 +262,7 @@ def main():
     stage_ms = {s: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / a.steps
                 for k, s in enumerate(stages)}
 
-    mde = W * H * D / (ms_step * 1e-3) * 1e-6
+    mde = mde_per_s(W, H, D, ms_step * 1e-3)
     t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
     kernels = kernel_rooflines(stage_ms, W, H, D, prm)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])

@@ -24,6 +24,9 @@ SMALL = [
     (52, 141, 40, 4, 3, 15, "u8", 0.0),
     (24, 70, 1, 3, 2, 16, "u8", 0.0),
     (9, 9, 5, 4, 6, 17, "u8", 0.0),
+    (10, 20, 512, 3, 2, 18, "u8", 0.0),        # the largest D the library accepts
+    (12, 40, 300, 4, 3, 19, "f32", 0.002),
+    (5, 2100, 6, 1, 1, 20, "u8", 0.0),          # selection walks three 1024-column chunks
 ]
 
 

@@ -1,0 +1,26 @@
+"""The benchmark's throughput metric is Eq. 13 (Mde/s = u_max v_max d_max / t * 1e-6);
+pinned against the numbers the paper prints (tests/golden/paper_speed.json)."""
+import json
+import os
+
+import bench
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_speed.json")
+
+
+def test_eq13_reproduces_the_printed_throughput():
+    g = json.load(open(GOLD))
+    t = 1.0 / g["fps"]
+    # d_max that makes Eq. 13 reproduce the printed Mde/s at the printed frame rate
+    d_max = g["mde_per_s"] * 1e6 * t / (g["u_max"] * g["v_max"])
+    assert abs(d_max - 30.0) < 0.01
+    assert abs(bench.mde_per_s(g["u_max"], g["v_max"], 30, t) - g["mde_per_s"]) < 0.1
+
+
+def test_kernel_roofline_bytes():
+    st = {"cost_volume": 0.1, "aggregate_ref": 0.2, "aggregate_tar": 0.2, "select_subpixel": 0.05}
+    k = bench.kernel_rooflines(st, 1280, 720, 64, None)
+    n = 1280 * 720 * 64
+    assert k["aggregate"]["bytes_per_launch"] == 8 * n
+    assert abs(k["select_subpixel"]["achieved"] - 8 * n / 0.05e-3 / 1e9) < 1.0
+    assert k["cost_volume"]["bound"] == "hbm"
