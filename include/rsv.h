@@ -138,7 +138,7 @@ int rsv_aggregate(const float* cost, rsv_image guide, const rsv_params* p, float
  *   disp_ref, disp_tar  out, int32 [H][W];  disp_sub out, float32 [H][W]
  *   valid    out, uint8 [H][W] (1 = passes the check)
  *   top2     out, float32 [2][H][W]: best and second-best agg_ref value, or NULL
- * Errors: RSV_E_NULL, RSV_E_SHAPE (W > 16384), RSV_E_PARAM, RSV_E_ALIGN. */
+ * Errors: RSV_E_NULL, RSV_E_SHAPE, RSV_E_PARAM, RSV_E_ALIGN. */
 int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t height,
                         int32_t width, const rsv_params* p, int32_t* disp_ref,
                         int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,

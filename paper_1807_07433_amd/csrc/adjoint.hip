@@ -38,11 +38,11 @@ __global__ void adjoint_zero_kernel(float* __restrict__ a, float* __restrict__ b
   if (i == 0 && loss) *loss = 0.0;
 }
 
-// 1 / sum of the Eq. 9-10 weights of each pixel's window (same order as the
-// aggregation kernel, so the same float).
+// 1 / sum of the Eq. 9-10 weights of each pixel's window, with the aggregation
+// kernel's weight function (summed in window order).
 template <int A>
 __global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, int64_t gpitch, int H,
-                                                   int W, float igd2, float igr2,
+                                                   int W, BilateralK bk,
                                                    float* __restrict__ zinv) {
   constexpr int K = 2 * A + 1;
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, 
       const int y = v + j - A, x = u + k - A;
       float wt = 0.f;
       if (x >= 0 && x < W && y >= 0 && y < H)
-        wt = bilateral_weight(pixel(g, gpitch, y, x), gp, j - A, k - A, igd2, igr2);
+        wt = bilateral_weight(pixel(g, gpitch, y, x), gp, j - A, k - A, bk);
       z += wt;
     }
   zinv[static_cast<int64_t>(v) * W + u] = 1.f / z;
@@ -101,7 +101,7 @@ __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
 template <int R, int A>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
     const float* __restrict__ left, int64_t lpitch, const float* __restrict__ right, int64_t rpitch,
-    int H, int W, int D, rsv_plane pl, float igd2, float igr2, float sigma_min,
+    int H, int W, int D, rsv_plane pl, BilateralK bk, float sigma_min,
     const float* __restrict__ cost, const float* __restrict__ agg, const int32_t* __restrict__ disp,
     const uint8_t* __restrict__ mask, const float* __restrict__ zinv, float* __restrict__ gleft,
     float* __restrict__ gright, double* __restrict__ gplane, double* __restrict__ loss) {
@@ -183,9 +183,9 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
         const int Y = qy + j - A, X = qx + k - A;
         if (X >= 0 && X < W && Y >= 0 && Y < H) {
           const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
-          const float w = bilateral_weight(gx, gq, j - A, k - A, igd2, igr2);
+          const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
           const float c = cost[my_d * plane + static_cast<int64_t>(Y) * W + X];
-          const float t = (c - Aq) * zi * bilateral_weight_dgq(w, gx, gq, igr2);
+          const float t = (c - Aq) * zi * bilateral_weight_dgq(w, gx, gq, bk);
           atomicAdd(&gl[(Y - ly0) * Ly.ltw + X - lx0], t);
           s += t;
         }
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
           const int dp = dt[zi];
           if (dp >= d0 && dp < d0 + kAdjDChunk) {
             const float gx = lt[(qy + j - A - ly0) * Ly.ltw + qx + k - A - lx0];
-            const float w = bilateral_weight(gx, gq, j - A, k - A, igd2, igr2);
+            const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
             col[(dp - d0) * kAdjThreads + tid] += w * zt[zi];
           }
         }
@@ -298,13 +298,12 @@ int launch_adjoint(const rsv_image& l, const rsv_image& r, rsv_plane pl, const r
                    const float* cost, const float* agg, const int32_t* disp, const uint8_t* mask,
                    float* gl, float* gr, double* gp, double* loss, float* zinv, hipStream_t st) {
   const int H = l.height, W = l.width, D = p->D;
-  const float igd2 = 1.f / (p->gamma_d * p->gamma_d);
-  const float igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
   const int64_t n = static_cast<int64_t>(H) * W;
   adjoint_zero_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st>>>(gl, gr, n, gp, loss);
   if (int s = check_launch()) return s;
   zinv_kernel<A><<<dim3((W + 255) / 256, H), dim3(256), 0, st>>>(
-      static_cast<const float*>(l.data), l.pitch, H, W, igd2, igr2, zinv);
+      static_cast<const float*>(l.data), l.pitch, H, W, bk, zinv);
   if (int s = check_launch()) return s;
   const AdjLayout Ly = adj_layout(R, A, D);
   auto kern = adjoint_kernel<R, A>;
@@ -320,7 +319,7 @@ int launch_adjoint(const rsv_image& l, const rsv_image& r, rsv_plane pl, const r
   const dim3 grid((W + kAdjTX - 1) / kAdjTX, (H + kAdjTY - 1) / kAdjTY);
   kern<<<grid, dim3(kAdjThreads), Ly.bytes, st>>>(
       static_cast<const float*>(l.data), l.pitch, static_cast<const float*>(r.data), r.pitch, H, W, D,
-      pl, igd2, igr2, p->sigma_min, cost, agg, disp, mask, zinv, gl, gr, gp, loss);
+      pl, bk, p->sigma_min, cost, agg, disp, mask, zinv, gl, gr, gp, loss);
   return check_launch();
 }
 

@@ -2,11 +2,16 @@
 // the matrix cores, shared by the plain aggregation kernel and the batch kernel.
 // NT threads (1024 or 512): wave w owns patches w, w + NT/64, ... of the 16 patches,
 // patch k sitting at (k / 4, k % 4); every patch runs the same MFMA sequence
-// whatever NT is, so both forms give the same floats.  The cost tile plus halo for 16
-// disparities at a time is staged in LDS as fp16 hi / lo planes (double-buffered,
-// next tile's global loads in flight during the current tile's MFMAs).  For every
-// disparity tile t the sink receives, per lane, the aggregated values of pixels
-// (patch row g = lane / 16, columns 0..3) at disparity 16 t + lane % 16.
+// whatever NT is, so both forms give the same floats.
+//
+// Per disparity tile t of 16: the cost tile plus halo is staged in LDS as fp16 hi /
+// lo planes, each thread moving 4-column chunks (two float2 loads, one 8-byte LDS
+// store per plane).  The MFMA results, scaled by 1/Z, are transposed through an LDS
+// output tile out[dd * OST + y * 16 + x] = A[16 t + dd][by + y][bx + x], which the
+// sink reads after a barrier: sink(t, out) is called by every thread.  Staging and
+// output tiles are both double-buffered, so one barrier per disparity tile orders
+//     loads of t+1 issued -> MFMAs of t -> output t -> staging t+1 -> barrier -> sink t
+// and the sink's global stores drain while the next tile's MFMAs run.
 #pragma once
 
 #include "aggregate_mfma.hpp"
@@ -16,64 +21,95 @@ namespace rsv {
 template <int A>
 __host__ __device__ inline size_t agg_tile_lds_bytes() {
   using G = AggGeo<A>;
-  return sizeof(float) * G::GT * G::GT + 2 /*hi,lo*/ * 2 /*buffers*/ * 16 * G::PLANE * sizeof(_Float16);
+  return sizeof(float) * (2 * 16 * G::OST + G::RAW + G::SKN) +
+         (2 /*hi,lo*/ * 2 /*buffers*/ * 16 * G::PLANE + 4 * 64 /*dummy*/) * sizeof(_Float16);
 }
 
 // guide_at(Y, X): guide intensity at in-image (Y, X).
-// sink(t, pp, lane, vals): vals[e] = A[16 t + lane % 16][by + 4 pp.pr + lane / 16][bx + 4 pp.pc + e]
-// (values for disparities >= D or pixels outside the image are meaningless).
+// Values for disparities >= D or pixels outside the image are meaningless.
 template <int A, int NT, typename GuideAt, typename Sink>
-__device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, int W, int D, float igd2,
-                                         float igr2, int by, int bx, GuideAt guide_at, Sink& sink,
-                                         unsigned char* smem) {
+__device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, int W, int D,
+                                         const BilateralK& bk, int by, int bx, GuideAt guide_at,
+                                         Sink& sink, unsigned char* smem) {
   using G = AggGeo<A>;
-  constexpr int NW = NT / 64;               // waves
-  constexpr int PPW = 16 / NW;              // patches per wave
-  constexpr int SPT = (G::RAW + NT - 1) / NT;  // staged tile positions per thread
-  float* gt = reinterpret_cast<float*>(smem);
-  _Float16* hi = reinterpret_cast<_Float16*>(smem + sizeof(float) * G::GT * G::GT);
+  constexpr int NW = NT / 64;                    // waves
+  constexpr int PPW = 16 / NW;                   // patches per wave
+  constexpr int NITEM = 16 * G::NCH;             // (disparity, chunk) items per tile
+  constexpr int SPT = (NITEM + NT - 1) / NT;     // items per thread
+  float* out = reinterpret_cast<float*>(smem);  // two output tiles
+  float* gt = out + 2 * 16 * G::OST;
+  float* skt = gt + G::RAW;
+  _Float16* hi = reinterpret_cast<_Float16*>(skt + G::SKN);
   _Float16* lo = hi + 2 * 16 * G::PLANE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  _Float16* dummy = lo + 2 * 16 * G::PLANE + 4 * lane;  // store target of surplus items
   const int64_t plane = static_cast<int64_t>(H) * W;
+  const int x0 = bx - A - G::PAD;  // image column of tile column 0 (even)
 
-  for (int i = tid; i < G::GT * G::GT; i += NT) {
-    const int r = i / G::GT, c = i - r * G::GT;
-    const int Y = by - A + r, X = bx - A + c;
-    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_at(Y, X) : 0.f;
+  for (int i = tid; i < G::RAW; i += NT) {
+    const int r = i / G::TC, c = i - r * G::TC;
+    const int Y = by - A + r, X = x0 + c;
+    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_at(Y, X) : INFINITY;
+  }
+  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
+    const int a = i / G::SKC, b = i - a * G::SKC;
+    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
+    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
   }
 
-  // Thread tid owns tile positions tid, tid + NT, ... (< RAW) and moves their 16
-  // disparities of one tile: global -> registers -> LDS hi / lo planes.
-  const float* src[SPT];
-  bool sok[SPT];
+  // Item q of this thread: disparity dd of the tile, chunk k = 4 columns of one row.
+  // meta = dd | in-image column mask << 4 (bit e: column X + e); off = Y * W + X.
+  const bool pairs_aligned = (W & 1) == 0;  // then every chunk start is 8-byte aligned
+  int off[SPT], ldso[SPT];
+  unsigned meta[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
-    const int i = tid + q * NT;
-    const int sr = i / G::TC, sc = i - sr * G::TC;
-    const int sY = by - A + sr, sX = bx - A + sc;
-    sok[q] = i < G::RAW && sY >= 0 && sY < H && sX >= 0 && sX < W;
-    src[q] = cost + (sok[q] ? static_cast<int64_t>(sY) * W + sX : 0);
+    const int it = tid + q * NT;
+    const int dd = it / G::NCH, k = it - dd * G::NCH;
+    const int row = k / G::CPR, c4 = 4 * (k - row * G::CPR);
+    const int Y = by - A + row, X = x0 + c4;
+    unsigned m = 0;
+    if (it < NITEM && Y >= 0 && Y < H)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) m |= (X + e >= 0 && X + e < W) ? (1u << e) : 0u;
+    meta[q] = static_cast<unsigned>(dd) | (m << 4);
+    off[q] = m ? Y * W + X : 0;
+    ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
-  float pre[SPT][16];
+  float4_t pre[SPT];
+  // The load form is chosen per wave (uniform branch): whole 4-column chunks as one
+  // 16-byte load when every lane has one, else per-column predicated loads.  No
+  // register is then written on one path while the other path's loads are pending.
   auto fetch = [&](int t) {
 #pragma unroll
-    for (int q = 0; q < SPT; ++q)
+    for (int q = 0; q < SPT; ++q) {
+      float4_t v = {0.f, 0.f, 0.f, 0.f};
+      const unsigned m = meta[q] >> 4;
+      const int d = 16 * t + static_cast<int>(meta[q] & 15u);
+      const unsigned mm = d < D ? m : 0u;
+      const float* p = cost + d * plane + off[q];
+      if (__all(mm == 0xFu && pairs_aligned)) {
+        const float2 a = *reinterpret_cast<const float2*>(p);
+        const float2 b = *reinterpret_cast<const float2*>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+      } else {
 #pragma unroll
-      for (int dd = 0; dd < 16; ++dd) {
-        const int d = 16 * t + dd;
-        pre[q][dd] = (sok[q] && d < D) ? src[q][d * plane] : 0.f;
+        for (int e = 0; e < 4; ++e)
+          if (mm & (1u << e)) v[e] = p[e];
       }
+      pre[q] = v;
+    }
   };
+  // Every thread stores every item (surplus ones to the dummy slot), so all loads of
+  // the fetch are consumed on every path.
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-      const int i = tid + q * NT;
-      if (i < G::RAW) {
-        _Float16* h = hi + buf * 16 * G::PLANE + i;
-        _Float16* l = lo + buf * 16 * G::PLANE + i;
-#pragma unroll
-        for (int dd = 0; dd < 16; ++dd) split_store(pre[q][dd], h, l, dd * G::PLANE);
-      }
+      half4_t h, l;
+      split4(pre[q], h, l);
+      const bool real = ldso[q] >= 0;
+      *reinterpret_cast<half4_t*>(real ? hi + buf * 16 * G::PLANE + ldso[q] : dummy) = h;
+      *reinterpret_cast<half4_t*>(real ? lo + buf * 16 * G::PLANE + ldso[q] : dummy) = l;
     }
   };
 
@@ -88,14 +124,16 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   for (int k = 0; k < PPW; ++k) {
     const int patch = wave + k * NW;
     pp[k] = PatchPos{patch >> 2, patch & 3};
-    iz[k] = patch_weights<A>(whi[k], wlo[k], pp[k], lane, by, bx, H, W, igd2, igr2,
-                             [&](int r, int c) { return gt[r * G::GT + c]; });
+    const int i = lane & 15;
+    const bool pin = by + 4 * pp[k].pr + (i >> 2) < H && bx + 4 * pp[k].pc + (i & 3) < W;
+    iz[k] = patch_weights<A>(whi[k], wlo[k], pp[k], lane, pin, gt, skt, bk.kr);
   }
 
   const int ndt = (D + 15) >> 4;
   for (int t = 0; t < ndt; ++t) {
     const int buf = t & 1;
-    if (t + 1 < ndt) fetch(t + 1);
+    float* o = out + buf * 16 * G::OST;
+    fetch(t + 1);  // past the last tile it loads nothing
 #pragma unroll
     for (int k = 0; k < PPW; ++k) {
       const float4_t acc =
@@ -103,10 +141,18 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
       float4_t vals;
 #pragma unroll
       for (int e = 0; e < 4; ++e) vals[e] = acc[e] * iz[k][e];
-      sink(t, pp[k], lane, vals);
+      *reinterpret_cast<float4_t*>(o + (lane & 15) * G::OST + (4 * pp[k].pr + (lane >> 4)) * 16 +
+                                   4 * pp[k].pc) = vals;
     }
-    if (t + 1 < ndt) store(buf ^ 1);
+    // Keep the staging store (which waits for the loads) after the MFMAs: without
+    // this fence the scheduler moves its conversions into the MFMA chain and the
+    // loads' latency is no longer hidden.
+    __builtin_amdgcn_sched_barrier(0);
+    // staging buffer buf ^ 1 was last read by the MFMAs of tile t - 1 and output
+    // tile buf by the sink of tile t - 2, both before the previous barrier
+    store(buf ^ 1);
     __syncthreads();
+    sink(t, static_cast<const float*>(o));
   }
 }
 

@@ -4,7 +4,7 @@
 // aggregation of a 4 x 4 patch over 16 disparities is a small matrix product with a
 // banded weight matrix, run on the matrix cores (agg_tile.hpp, aggregate_mfma.hpp).
 // Each 1024-thread block owns a 16 x 16 output tile and writes its aggregated
-// values plane by plane.  Blocks are numbered so that the tiles handled by one XCD
+// values plane by plane, one 16-disparity tile at a time.  Blocks are numbered so that the tiles handled by one XCD
 // form a contiguous band of the image, keeping halo re-reads inside that XCD's L2.
 #include "agg_tile.hpp"
 
@@ -20,19 +20,30 @@ __device__ __forceinline__ int xcd_band_tile(int b, int ntiles) {
   return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
-// agg_tile sink that stores the aggregated values into the output volume.
+// agg_tile sink that writes each 16-disparity tile into the output volume: thread i
+// moves 4 consecutive pixels of one row of one plane (a wave covers a 16 x 16 plane
+// tile, 64-byte row segments), as one float4 store when rows are 16-byte aligned.
+template <int NT>
 struct VolumeSink {
   float* agg;
   int H, W, D, by, bx;
+  bool vec4;
 
-  __device__ __forceinline__ void operator()(int t, const PatchPos& pp, int lane, const float4_t& vals) {
-    const int d = 16 * t + (lane & 15);
-    const int Y = by + 4 * pp.pr + (lane >> 4), X0 = bx + 4 * pp.pc;
-    if (d < D && Y < H) {
-      float* o = agg + d * (static_cast<int64_t>(H) * W) + static_cast<int64_t>(Y) * W + X0;
+  __device__ __forceinline__ void operator()(int t, const float* o) {
+    for (int i = threadIdx.x; i < 1024; i += NT) {
+      const int dd = i >> 6, row = (i >> 2) & 15, c4 = (i & 3) << 2;
+      const int d = 16 * t + dd, Y = by + row, X = bx + c4;
+      if (d < D && Y < H && X < W) {
+        const float4_t v = *reinterpret_cast<const float4_t*>(o + dd * kAggOutStride + row * 16 + c4);
+        float* p = agg + d * (static_cast<int64_t>(H) * W) + static_cast<int64_t>(Y) * W + X;
+        if (vec4 && X + 3 < W) {
+          *reinterpret_cast<float4_t*>(p) = v;
+        } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (X0 + e < W) o[e] = vals[e];
+          for (int e = 0; e < 4; ++e)
+            if (X + e < W) p[e] = v[e];
+        }
+      }
     }
   }
 };
@@ -40,22 +51,22 @@ struct VolumeSink {
 template <int A, typename TG>
 __global__ __launch_bounds__(kAggThreads) void aggregate_kernel(
     const float* __restrict__ cost, const TG* __restrict__ guide, int64_t gpitch, int H, int W,
-    int D, float igd2, float igr2, float* __restrict__ agg) {
+    int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
   const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
-  VolumeSink sink{agg, H, W, D, by, bx};
-  agg_tile<A, kAggThreads>(cost, H, W, D, igd2, igr2, by, bx, guide_at, sink, smem);
+  VolumeSink<kAggThreads> sink{agg, H, W, D, by, bx, vec4};
+  agg_tile<A, kAggThreads>(cost, H, W, D, bk, by, bx, guide_at, sink, smem);
 }
 
 template <int A, typename TG>
 int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
                hipStream_t st) {
   const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
-  const float igd2 = 1.f / (p->gamma_d * p->gamma_d);
-  const float igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+  const bool vec4 = (g.width % 4) == 0 && aligned(agg, 16);
   const size_t lds = agg_tile_lds_bytes<A>();
   auto kern = aggregate_kernel<A, TG>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -65,7 +76,7 @@ int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float
     return RSV_E_HIP;
   }
   kern<<<dim3(tiles), dim3(kAggThreads), lds, st>>>(cost, static_cast<const TG*>(g.data), g.pitch,
-                                                      g.height, g.width, p->D, igd2, igr2, agg);
+                                                      g.height, g.width, p->D, bk, vec4, agg);
   return check_launch();
 }
 

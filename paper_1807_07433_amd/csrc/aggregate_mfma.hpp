@@ -2,12 +2,12 @@
 // matrix cores.  For a 4 x 4 patch of output pixels p and 16 disparities d:
 //     A[d][p] = (sum_q w(p, q) C[d][q]) / Z(p),   Z(p) = sum_q w(p, q)
 // where q runs over the union of the 16 windows: (4 + 2A) rows x 16 columns (the
-// columns beyond 4 + 2A carry zero weight).  One v_mfma_f32_16x16x32_f16 consumes
-// two union rows (K = 32): M = 16 pixels, N = 16 disparities.  Weights and costs are
-// each split into fp16 hi + lo parts (x = hi + lo to about 2^-22 relative, |C| <= 1,
-// 0 <= w <= 1), and hi*hi + hi*lo + lo*hi is accumulated in fp32, so the result
-// matches an fp32 weighted sum to ~1e-7.  The weights are computed once per patch
-// and stay in registers for every disparity tile.
+// columns outside a pixel's window carry zero weight).  One v_mfma_f32_16x16x32_f16
+// consumes two union rows (K = 32): M = 16 pixels, N = 16 disparities.  Weights and
+// costs are each split into fp16 hi + lo parts (x = hi + lo to about 2^-22
+// relative, |C| <= 1, 0 <= w <= 1), and hi*hi + hi*lo + lo*hi is accumulated in
+// fp32, so the result matches an fp32 weighted sum to ~1e-7.  The weights are
+// computed once per patch and stay in registers for every disparity tile.
 //
 // Lane layout of v_mfma_f32_16x16x32_f16 (wave64; l = lane, i = l % 16, g = l / 16):
 //   A operand: A[i][8g + e], e = 0..7      B operand: B[8g + e][l % 16]
@@ -23,18 +23,33 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-// Geometry of the LDS cost tile of a 16 x 16 output block.
+// Floats per disparity in the LDS output tile of a 16 x 16 block (256 + 4: the
+// planes written by consecutive lanes start on distinct 4-bank groups).
+constexpr int kAggOutStride = 260;
+
+// Geometry of the LDS tiles of a 16 x 16 output block at (by, bx).  The staged
+// cost and guide tiles start at row by - A and column bx - A - PAD; PAD makes that
+// column even, so four consecutive tile columns are one 8-byte aligned pair of
+// float2 loads whenever the image width is even.  Union column c of patch column pc
+// is tile column 4 pc + c.
 template <int A>
 struct AggGeo {
+  static constexpr int PAD = A & 1;
   static constexpr int UR = 4 + 2 * A;       // union rows of one patch
   static constexpr int KS = UR / 2;          // K-steps of 32
   static constexpr int TR = 16 + 2 * A;      // tile rows
   static constexpr int TC = 28;              // tile columns: patch 3's union ends at 12 + 16
   static constexpr int RAW = TR * TC;
-  // halves per disparity plane; PLANE % 16 == 8 keeps the 16 planes read by one
-  // group of 16 lanes on distinct 4-bank groups
-  static constexpr int PLANE = RAW + ((8 - RAW % 16) + 16) % 16;
-  static constexpr int GT = 16 + 2 * A;      // guide tile side
+  static constexpr int CPR = TC / 4;         // 4-column chunks per tile row
+  static constexpr int NCH = TR * CPR;       // chunks per disparity plane
+  // halves per disparity plane; PLANE % 8 == 4 (an odd number of dword pairs) puts
+  // the 16 planes read by one group of 16 lanes on distinct bank pairs
+  static constexpr int PLANE = RAW + ((4 - RAW % 8) + 8) % 8;
+  // spatial exponent table, indexed by (union row - py + 3, union column - px + 3)
+  static constexpr int SKR = UR + 3, SKC = 19;
+  static constexpr int SKN = (SKR * SKC + 3) & ~3;
+  static constexpr int OST = kAggOutStride;
+  static_assert(2 * A + PAD <= 12, "a pixel's window must fit the 16 union columns");
 };
 
 struct PatchPos {
@@ -42,31 +57,25 @@ struct PatchPos {
 };
 
 // Weights w of one lane for one patch, split into hi / lo fp16 parts (w <= 1).
-// Returns 1 / Z for the four output pixels this lane receives from the MFMA
-// (patch row g = lane / 16, columns 0..3), Z = sum of the pixel's weights in fp32.
-template <int A, typename GuideAt>
+// gt: guide tile (+inf outside the image); skt: spatial exponent table (+inf
+// outside the window).  Returns 1 / Z for the four output pixels this lane
+// receives from the MFMA (patch row g = lane / 16, columns 0..3).
+template <int A>
 __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, const PatchPos& pp,
-                                                  int lane, int by, int bx, int H, int W,
-                                                  float igd2, float igr2, GuideAt guide_at) {
+                                                  int lane, bool pin, const float* gt, const float* skt,
+                                                  float kr) {
   using G = AggGeo<A>;
   const int i = lane & 15, g = lane >> 4;
   const int py = i >> 2, px = i & 3;
-  const int Yp = by + 4 * pp.pr + py, Xp = bx + 4 * pp.pc + px;
-  const bool pin = Yp < H && Xp < W;
-  const float gp = pin ? guide_at(4 * pp.pr + py + A, 4 * pp.pc + px + A) : 0.f;
+  const float gp = pin ? gt[(4 * pp.pr + py + A) * G::TC + 4 * pp.pc + px + A + G::PAD] : 0.f;
+  const float* gq = gt + (4 * pp.pr + (g >> 1)) * G::TC + 4 * pp.pc + 8 * (g & 1);
+  const float* sk = skt + ((g >> 1) - py + 3) * G::SKC + 8 * (g & 1) - px + 3;
   float z = 0.f;
 #pragma unroll
   for (int s = 0; s < G::KS; ++s)
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int r = 2 * s + (g >> 1), c = 8 * (g & 1) + e;
-      const int dy = r - A - py, dx = c - A - px;
-      float wt = 0.f;
-      if (pin && dy >= -A && dy <= A && dx >= -A && dx <= A) {
-        const int Y = Yp + dy, X = Xp + dx;
-        if (Y >= 0 && Y < H && X >= 0 && X < W)
-          wt = bilateral_weight(guide_at(4 * pp.pr + r, 4 * pp.pc + c), gp, dy, dx, igd2, igr2);
-      }
+      const float wt = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e], kr);
       const _Float16 h = static_cast<_Float16>(wt);
       whi[s][e] = h;
       wlo[s][e] = static_cast<_Float16>(wt - static_cast<float>(h));
@@ -116,10 +125,14 @@ __device__ __forceinline__ float4_t patch_mfma(const half8_t* whi, const half8_t
   return acc;
 }
 
-__device__ __forceinline__ void split_store(float c, _Float16* hi, _Float16* lo, int idx) {
-  const _Float16 h = static_cast<_Float16>(c);
-  hi[idx] = h;
-  lo[idx] = static_cast<_Float16>(c - static_cast<float>(h));
+// fp16 hi / lo split of four costs: c = hi + lo to about 2^-22 relative.
+__device__ __forceinline__ void split4(const float4_t& c, half4_t& hi, half4_t& lo) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const _Float16 h = static_cast<_Float16>(c[e]);
+    hi[e] = h;
+    lo[e] = static_cast<_Float16>(c[e] - static_cast<float>(h));
+  }
 }
 
 }  // namespace rsv

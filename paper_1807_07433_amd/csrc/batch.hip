@@ -10,9 +10,9 @@
 //       of rsv_warp / rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
 //   aggregation items (pair, 16 x 16 tile, ref | tar): bilateral aggregation on the
 //       matrix cores with the arithmetic of rsv_aggregate (shared agg_tile) and
-//       winner-take-all folded in: per pixel the running best, second best and the
-//       winner's neighbours, updated disparity tile by disparity tile exactly as a
-//       scan over d in increasing order would (ties keep the lowest d).  No
+//       winner-take-all folded in: each 16-disparity tile of aggregated values is
+//       fed, from LDS, through the select kernel's own scan step (running best,
+//       second best and the winner's neighbours, ties keep the lowest d).  No
 //       aggregated volume is written.
 // The tail applies the left-right check (Eq. 11), the parabola (Eq. 12),
 // post-processing and triangulation per pixel, with the plain path's functions.
@@ -64,92 +64,35 @@ struct BatchArgs {
   const int4* items;  // {pair, kind, a, b}
   int n_items;
   int* head;
-  float igd2, igr2, sigma_min;
+  BilateralK bk;
+  float sigma_min;
 };
 
-// Running WTA state of the 256 pixels of one AGG tile, in LDS.
-struct WtaState {
-  float best[256], second[256], am[256], ap[256], last[256];
-  int arg[256], need_ap[256];
-};
-
-__device__ __forceinline__ void argmax16(float& v, int& j) {
-  // max over the 16 lanes of a lane group; ties -> lowest j
-#pragma unroll
-  for (int m = 1; m < 16; m <<= 1) {
-    const float ov = __shfl_xor(v, m);
-    const int oj = __shfl_xor(j, m);
-    if (ov > v || (ov == v && oj < j)) {
-      v = ov;
-      j = oj;
-    }
-  }
-}
-
-__device__ __forceinline__ float max16(float v) {
-#pragma unroll
-  for (int m = 1; m < 16; m <<= 1) v = fmaxf(v, __shfl_xor(v, m));
-  return v;
-}
-
-// Sink for agg_tile: folds each 16-disparity tile into the per-pixel scan state.
+// agg_tile sink that runs the select kernel's scan over d for the tile's 256
+// pixels, 16 disparities at a time: thread p < 256 owns pixel p (row p / 16,
+// column p % 16) and keeps its state in registers across the disparity tiles.
 struct WtaSink {
-  WtaState* st;
   int D;
-  bool full;  // reference volume: keep second best and neighbours; target: argmax only
+  bool full;  // reference volume: best, second best and neighbours; target: argmax only
+  Scan s;
+  bool need_next;
+  float prev;
 
-  __device__ __forceinline__ void operator()(int t, const PatchPos& pp, int lane, const float4_t& vals) {
-    const int j = lane & 15, g = lane >> 4;
-    const int base = lane & ~15;
-    const int d = 16 * t + j;
-    const int jl = min(15, D - 1 - 16 * t);  // last valid lane of this tile
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float v = d < D ? vals[e] : -INFINITY;
-      float m = v;
-      int jm = j;
-      argmax16(m, jm);
-      const int pix = (4 * pp.pr + g) * 16 + 4 * pp.pc + e;
-      const float v_first = __shfl(v, base);
-      const float v_last = __shfl(v, base + jl);
-      float sec = 0.f, vm1 = 0.f, vp1 = 0.f;
+  __device__ __forceinline__ void operator()(int t, const float* o) {
+    const int p = threadIdx.x;
+    if (p >= 256) return;
+    const int n = min(16, D - 16 * t);
+    for (int dd = 0; dd < n; ++dd) {
+      const float a = o[dd * kAggOutStride + p];
+      const int d = 16 * t + dd;
       if (full) {
-        sec = max16(j == jm ? -INFINITY : v);
-        vm1 = __shfl(v, base + (jm > 0 ? jm - 1 : 0));
-        vp1 = __shfl(v, base + (jm < 15 ? jm + 1 : 15));
-      }
-      if (j == 0) {
-        if (t == 0) {
-          st->best[pix] = -INFINITY;
-          st->second[pix] = -INFINITY;
-          st->arg[pix] = -1;
-          st->am[pix] = 0.f;
-          st->ap[pix] = 0.f;
-          st->need_ap[pix] = 0;
-          st->last[pix] = 0.f;
-        }
-        float best = st->best[pix];
-        if (full && st->need_ap[pix]) {
-          st->ap[pix] = v_first;
-          st->need_ap[pix] = 0;
-        }
-        if (m > best) {
-          if (full) {
-            st->second[pix] = fmaxf(best, sec);
-            st->am[pix] = jm > 0 ? vm1 : st->last[pix];
-            if (jm < jl) {
-              st->ap[pix] = vp1;
-              st->need_ap[pix] = 0;
-            } else {
-              st->need_ap[pix] = 1;
-            }
-          }
-          st->best[pix] = m;
-          st->arg[pix] = 16 * t + jm;
-        } else if (full) {
-          st->second[pix] = fmaxf(st->second[pix], m);
-        }
-        st->last[pix] = v_last;
+        if (d == 0)
+          scan_init(s, need_next, prev, a);
+        else
+          scan_step(s, need_next, prev, a, d);
+      } else if (d == 0 || a > s.best) {
+        s.best = a;
+        s.arg = d;
       }
     }
   }
@@ -189,38 +132,35 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args
 
 template <int A>
 __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsigned char* smem) {
-  WtaState* st = reinterpret_cast<WtaState*>(smem);
-  unsigned char* work = smem + ((sizeof(WtaState) + 15) & ~size_t(15));
   const PairDev* pd = args.pairs + w.x;
   const int H = pd->H, W = pd->W, D = pd->D;
   const int by = 16 * w.z, bx = 16 * w.w;
   const bool full = w.y == kItemAggRef;
-  WtaSink sink{st, D, full};
+  WtaSink sink{D, full};
   if (full) {
     const uint8_t* left = pd->left;
     const int64_t lpitch = pd->lpitch;
     auto guide = [&](int Y, int X) { return pixel(left, lpitch, Y, X); };
-    agg_tile<A, kAggItemThreads>(pd->cref, H, W, D, args.igd2, args.igr2, by, bx, guide, sink, work);
+    agg_tile<A, kAggItemThreads>(pd->cref, H, W, D, args.bk, by, bx, guide, sink, smem);
   } else {
     const uint8_t* right = pd->right;
     const int64_t rpitch = pd->rpitch;
     const rsv_plane pl = pd->plane;
     auto guide = [&](int Y, int X) { return warp_sample(right, rpitch, W, pl, X, Y); };
-    agg_tile<A, kAggItemThreads>(pd->ctar, H, W, D, args.igd2, args.igr2, by, bx, guide, sink, work);
+    agg_tile<A, kAggItemThreads>(pd->ctar, H, W, D, args.bk, by, bx, guide, sink, smem);
   }
-  // agg_tile ends with a barrier: the state of all 256 pixels is complete
   if (threadIdx.x < 256) {
     const int q = threadIdx.x;
     const int Y = by + (q >> 4), X = bx + (q & 15);
     if (Y < H && X < W) {
       const int64_t i = static_cast<int64_t>(Y) * W + X;
       if (full) {
-        pd->ref_arg[i] = st->arg[q];
-        pd->ref_best[i] = st->best[q];
-        pd->ref_am[i] = st->am[q];
-        pd->ref_ap[i] = st->ap[q];
+        pd->ref_arg[i] = sink.s.arg;
+        pd->ref_best[i] = sink.s.best;
+        pd->ref_am[i] = sink.s.am;
+        pd->ref_ap[i] = sink.s.ap;
       } else {
-        pd->tar_arg[i] = st->arg[q];
+        pd->tar_arg[i] = sink.s.arg;
       }
     }
   }
@@ -311,7 +251,7 @@ const void* pick_agg_kernel(int A, size_t* lds) {
     case 6: t = agg_tile_lds_bytes<6>(); k = agg_kernel_ptr<6>(); break;
     default: return nullptr;
   }
-  *lds = ((sizeof(WtaState) + 15) & ~size_t(15)) + t;
+  *lds = t;
   return k;
 }
 
@@ -344,9 +284,11 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   if (!pairs || !p || !out) return RSV_E_NULL;
   *out = nullptr;
   if (n < 1) return RSV_E_SHAPE;
-  if (int s = validate_cost_params(p)) return s;
-  if (int s = validate_agg_params(p)) return s;
-  if (int s = validate_select_params(p)) return s;
+  rsv_params pc = *p;  // D comes from each pair; validate the shared parameters only
+  pc.D = 1;
+  if (int s = validate_cost_params(&pc)) return s;
+  if (int s = validate_agg_params(&pc)) return s;
+  if (int s = validate_select_params(&pc)) return s;
   const int R = p->block_radius, A = p->agg_radius, K = 2 * R + 1;
   rsv_tuning tn;
   rsv_tuning_default(&tn);
@@ -508,8 +450,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   ca.n_items = plan->n_cost_items;
   ca.head = plan->d_heads;
   ca.sigma_min = p->sigma_min;
-  ca.igd2 = 1.f / (p->gamma_d * p->gamma_d);
-  ca.igr2 = 1.f / (p->gamma_r * p->gamma_r);
+  ca.bk = bilateral_constants(p->gamma_d, p->gamma_r);
   BatchArgs& aa = plan->agg_args;
   aa = ca;
   aa.items = reinterpret_cast<const int4*>(base + o_ai);

@@ -1,24 +1,46 @@
 // Bilateral weight of Eq. 9-10, shared by the aggregation, batch and adjoint kernels
-// so all of them use the same float for the same pixel pair:
+// so all of them use the same float for the same pixel pair.  In base 2:
 //   w = exp(-(dx^2 + dy^2) / gamma_d^2 - ((g_q - g_p) / 255)^2 / gamma_r^2)
-// (the product of the two exponentials written as one).
+//     = 2^-(s + (g_q - g_p)^2 kr),   s = (dx^2 + dy^2) kd,
+//   kd = log2(e) / gamma_d^2,   kr = log2(e) / (255 gamma_r)^2,
+// evaluated with the hardware base-2 exponential.  The spatial exponent s of a
+// window offset is a constant the kernels may tabulate; s = +inf (outside the
+// window) or g_q = +inf (outside the image) gives w = 0.
 #pragma once
 
 #include "rsv_internal.hpp"
 
 namespace rsv {
 
-__device__ __forceinline__ float bilateral_weight(float gq, float gp, int dy, int dx, float inv_gd2,
-                                                  float inv_gr2) {
-  const float dg = (gq - gp) * (1.f / 255.f);
-  const float r2 = static_cast<float>(dy * dy + dx * dx);
-  return expf(-(r2 * inv_gd2 + dg * dg * inv_gr2));
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr float kLn2f = 0.693147180559945309f;
+
+struct BilateralK {
+  float kd, kr;
+};
+
+inline BilateralK bilateral_constants(float gamma_d, float gamma_r) {
+  const double gd = gamma_d, gr = 255.0 * static_cast<double>(gamma_r);
+  return BilateralK{static_cast<float>(kLog2e / (gd * gd)), static_cast<float>(kLog2e / (gr * gr))};
 }
 
-// d w / d g_q for the same weight (and -that for g_p).
-__device__ __forceinline__ float bilateral_weight_dgq(float w, float gq, float gp, float inv_gr2) {
-  const float dg = (gq - gp) * (1.f / 255.f);
-  return w * (-2.f * dg * inv_gr2 * (1.f / 255.f));
+__device__ __forceinline__ float spatial_exponent(int dy, int dx, float kd) {
+  return static_cast<float>(dy * dy + dx * dx) * kd;
+}
+
+// w from the spatial exponent s of the offset.
+__device__ __forceinline__ float bilateral_weight_s(float gq, float gp, float s, float kr) {
+  const float dg = gq - gp;
+  return __builtin_amdgcn_exp2f(-fmaf(dg * dg, kr, s));
+}
+
+__device__ __forceinline__ float bilateral_weight(float gq, float gp, int dy, int dx, const BilateralK& k) {
+  return bilateral_weight_s(gq, gp, spatial_exponent(dy, dx, k.kd), k.kr);
+}
+
+// d w / d g_q for the same weight (and -that for g_p): w ln2 (-2 (g_q - g_p) kr).
+__device__ __forceinline__ float bilateral_weight_dgq(float w, float gq, float gp, const BilateralK& k) {
+  return w * (-2.f * kLn2f * k.kr * (gq - gp));
 }
 
 }  // namespace rsv

@@ -27,6 +27,8 @@ inline int validate_image(const rsv_image& im) {
   if (!im.data) return RSV_E_NULL;
   if (im.dtype != RSV_U8 && im.dtype != RSV_F32) return RSV_E_DTYPE;
   if (im.height < 1 || im.width < 1 || im.pitch < im.width) return RSV_E_SHAPE;
+  // pixel indices within one plane are 32-bit in the kernels
+  if (static_cast<int64_t>(im.height) * im.width > INT32_MAX) return RSV_E_SHAPE;
   if (im.dtype == RSV_F32 && !aligned(im.data, 4)) return RSV_E_ALIGN;
   return RSV_OK;
 }

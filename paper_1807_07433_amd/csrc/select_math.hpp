@@ -9,11 +9,56 @@
 
 namespace rsv {
 
+// Running state of the reference-volume scan over d = 0, 1, ... of one pixel: the
+// best value and its d, the second best, and the best's neighbours.  Ties keep the
+// lowest d: a later d replaces the best only when strictly greater.
+struct Scan {
+  float best, second, am, ap;
+  int arg;
+};
+
+// The scan after d = 0 with value a.  need_next: the next value is the best's right
+// neighbour; prev: the value at the previous d.
+__device__ __forceinline__ void scan_init(Scan& s, bool& need_next, float& prev, float a) {
+  s.best = a;
+  s.second = -INFINITY;
+  s.am = 0.f;
+  s.ap = 0.f;
+  s.arg = 0;
+  need_next = true;
+  prev = a;
+}
+
+// One step of the scan at disparity d >= 1 with value a.
+__device__ __forceinline__ void scan_step(Scan& s, bool& need_next, float& prev, float a, int d) {
+  if (need_next) {
+    s.ap = a;
+    need_next = false;
+  }
+  if (a > s.best) {
+    s.second = s.best;
+    s.best = a;
+    s.arg = d;
+    s.am = prev;
+    need_next = true;
+  } else if (a > s.second) {
+    s.second = a;
+  }
+  prev = a;
+}
+
 // Eq. 12: d + (a(d-1) - a(d+1)) / (2a(d-1) + 2a(d+1) - 4a(d)); ends of the range unrefined.
 __device__ __forceinline__ float parabola(int arg, float best, float am, float ap, int D) {
   if (arg <= 0 || arg >= D - 1) return static_cast<float>(arg);
-  const float den = 2.f * am + 2.f * ap - 4.f * best;
-  return static_cast<float>(arg) + (am - ap) / den;
+  // Eq. 12 written with the gaps below the peak, x = c(d) - c(d-1) and
+  // y = c(d) - c(d+1): the offset (x - y) / (2 (x + y)) equals
+  // (c(d-1) - c(d+1)) / (2c(d-1) + 2c(d+1) - 4c(d)), and since x, y >= 0 at a
+  // maximum the rounded quotient stays within [-1/2, 1/2] (the direct form's
+  // denominator can round to 0 when a neighbour is within an ulp of the peak).
+  const float x = best - am, y = best - ap;
+  const float s = x + y;
+  if (!(s > 0.f)) return static_cast<float>(arg);
+  return static_cast<float>(arg) + (x - y) / (2.f * s);
 }
 
 // d_f = d_s + s(u - d_s, v); xyz = (x, y, z) or NaN when invalid or d_f <= 0.  FP64, one rounding.

@@ -61,3 +61,14 @@ def check_subpixel(name, gpu_sub, ref_sub, agree, den, agg_err=AGG_TOL):
         bad = err[small] > bound
         assert not bad.any(), f"{name}: {bad.sum()} small-denominator pixels beyond 6e/|den|"
     return worst, int(small.sum())
+
+
+def check_subpixel_range(name, gpu_sub, gpu_disp):
+    """Eq. 12 at a discrete maximum puts the parabola's vertex within half a pixel of
+    the winner, at every pixel and at any size: the refined map is finite and
+    |d_s - d| <= 1/2."""
+    sub = np.asarray(gpu_sub, np.float64)
+    d = np.asarray(gpu_disp, np.float64)
+    assert np.isfinite(sub).all(), f"{name}: {int((~np.isfinite(sub)).sum())} non-finite values"
+    off = np.abs(sub - d)
+    assert off.max(initial=0.0) <= 0.5, f"{name}: |d_s - d| reaches {off.max():.6g}"

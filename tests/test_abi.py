@@ -104,7 +104,7 @@ def test_select_validation(lib):
     p = _params()
     ok = [FAKE] * 6
     assert lib.rsv_select_subpixel(FAKE, FAKE, 0, 10, C.byref(p), *ok, None) == -2
-    assert lib.rsv_select_subpixel(FAKE, FAKE, 10, 16385, C.byref(p), *ok, None) == -2
+    assert lib.rsv_select_subpixel(FAKE, FAKE, 70000, 70000, C.byref(p), *ok, None) == -2  # H*W > 2^31-1
     assert lib.rsv_select_subpixel(None, FAKE, 10, 10, C.byref(p), *ok, None) == -1
     bad = _params(lr_threshold=-1)
     assert lib.rsv_select_subpixel(FAKE, FAKE, 10, 10, C.byref(bad), *ok, None) == -3

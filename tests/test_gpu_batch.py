@@ -22,7 +22,8 @@ def _say(msg):
 def _cases(shapes, seed0):
     out = []
     for k, (H, W, D) in enumerate(shapes):
-        c = synth.small_case(H, W, D, 3, 5, seed0 + k, plane_a=0.07, plane_b=4.0 + k)
+        c = synth.small_case(H, W, D, 3, 5, seed0 + k, plane_a=0.07, plane_b=4.0 + k,
+                             gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
         out.append(c)
     return out
 
@@ -42,12 +43,17 @@ def _plain(rsv, pair, D):
     return rsv.reconstruct(left, right, plane, cam, prm)
 
 
+def _same(x, y):
+    """Bitwise equality that also matches NaN with NaN."""
+    if x.is_floating_point():
+        return torch.equal(torch.isnan(x), torch.isnan(y)) and torch.equal(x.nan_to_num(), y.nan_to_num())
+    return torch.equal(x, y)
+
+
 def _check_equal(tag, a, b):
-    for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final"):
-        assert torch.equal(a[k], b[k]), f"{tag}: {k} differs"
-    xa, xb = a["xyz"], b["xyz"]
-    assert torch.equal(torch.isnan(xa), torch.isnan(xb)), f"{tag}: xyz NaN pattern"
-    assert torch.equal(xa.nan_to_num(), xb.nan_to_num()), f"{tag}: xyz differs"
+    for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
+        assert _same(a[k], b[k]), f"{tag}: {k} differs"
+    P.check_subpixel_range(f"{tag} disp_sub", a["disp_sub"].cpu().numpy(), a["disp_ref"].cpu().numpy())
 
 
 SHAPES = [(37, 150, 31), (70, 201, 64), (52, 141, 40), (24, 70, 8), (96, 128, 17), (45, 64, 1)]

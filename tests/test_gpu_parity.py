@@ -65,6 +65,7 @@ def _check_selection(tag, sel, ref, AL, AR, agg_err):
     dtar = P.to_np(sel["disp_tar"]).astype(np.int64)
     P.check_disparity(f"{tag} disp_ref", dref, ref["disp_ref"], AL[dref, v, u], AL.max(0))
     P.check_disparity(f"{tag} disp_tar", dtar, ref["disp_tar"], AR[dtar, v, u], AR.max(0))
+    P.check_subpixel_range(f"{tag} disp_sub", P.to_np(sel["disp_sub"]), dref)
     agree = dref == ref["disp_ref"]
     interior = (ref["disp_ref"] > 0) & (ref["disp_ref"] < D - 1)
     P.check_subpixel(f"{tag} disp_sub", P.to_np(sel["disp_sub"]), ref["disp_sub"], agree & interior,
@@ -97,7 +98,7 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
     cref_n, ctar_n = P.to_np(cref), P.to_np(ctar)
     P.check_close("cost_ref", cref_n, ref["cost_ref"], P.COST_TOL)
     P.check_close("cost_tar", ctar_n, ref["cost_tar"], P.COST_TOL)
-    for d in range(D):  # identity stated after Eq. 5, bit for bit
+    for d in range(min(D, W)):  # identity stated after Eq. 5, bit for bit
         assert np.array_equal(ctar_n[d, :, :W - d], cref_n[d, :, d:])
 
     _say("  rsv_aggregate x2")
@@ -258,6 +259,7 @@ def _sampled_full(rsv, case, n_cost, n_agg, n_pix, seed):
     sub = ref_d + (cm - cp) / np.where(inner, 2 * cm + 2 * cp - 4 * c0, 1.0)
     P.check_subpixel("disp_sub", P.to_np(out["disp_sub"][v, u]), sub, inner,
                      np.where(inner, 2 * cm + 2 * cp - 4 * c0, -1.0), max(e_agg, 1e-7))
+    P.check_subpixel_range("disp_sub (whole frame)", P.to_np(out["disp_sub"]), P.to_np(out["disp_ref"]))
     return out
 
 
