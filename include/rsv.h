@@ -123,8 +123,8 @@ int rsv_cost_volume(rsv_image left, const float* warped, const rsv_params* p,
  * once per volume: guide = left image for cost_ref, warped image for cost_tar.
  *   cost   float32 [D][H][W];  guide  u8 or f32 image of the same H, W
  *   agg    out, float32 [D][H][W] (must not alias cost)
- * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE, RSV_E_PARAM (agg_radius, gammas),
- * RSV_E_ALIGN. */
+ * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE (also H*W > 2^26), RSV_E_PARAM
+ * (agg_radius, gammas), RSV_E_ALIGN. */
 int rsv_aggregate(const float* cost, rsv_image guide, const rsv_params* p, float* agg,
                   void* stream);
 

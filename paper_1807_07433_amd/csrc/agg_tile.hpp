@@ -1,8 +1,8 @@
-// One 16 x 16 output tile of the bilateral aggregation (Sec. II-B.2, Eq. 8-10) on
-// the matrix cores, shared by the plain aggregation kernel and the batch kernel.
-// NT threads (1024 or 512): wave w owns patches w, w + NT/64, ... of the 16 patches,
-// patch k sitting at (k / 4, k % 4); every patch runs the same MFMA sequence
-// whatever NT is, so both forms give the same floats.
+// One TY x 16 output tile (TY = 16 or 8) of the bilateral aggregation (Sec. II-B.2,
+// Eq. 8-10) on the matrix cores, shared by the plain aggregation kernel and the
+// batch kernel.  64 * TY threads: wave w owns patch w, sitting at (w / 4, w % 4);
+// every patch runs the same MFMA sequence whatever the tile height, so all forms
+// give the same floats.
 //
 // Per disparity tile t of 16: the cost tile plus halo is staged in LDS as fp16 hi /
 // lo planes, each thread moving 4-column chunks (two float2 loads, one 8-byte LDS
@@ -18,26 +18,27 @@
 
 namespace rsv {
 
-template <int A>
+template <int A, int TY>
 __host__ __device__ inline size_t agg_tile_lds_bytes() {
-  using G = AggGeo<A>;
-  return sizeof(float) * (2 * 16 * G::OST + G::RAW + G::SKN) +
+  using G = AggGeo<A, TY>;
+  return sizeof(float) * (G::NOB * 16 * G::OST + G::RAW + G::SKN) +
          (2 /*hi,lo*/ * 2 /*buffers*/ * 16 * G::PLANE + 4 * 64 /*dummy*/) * sizeof(_Float16);
 }
 
 // guide_at(Y, X): guide intensity at in-image (Y, X).
 // Values for disparities >= D or pixels outside the image are meaningless.
-template <int A, int NT, typename GuideAt, typename Sink>
+template <int A, int TY, typename GuideAt, typename Sink>
 __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, int W, int D,
                                          const BilateralK& bk, int by, int bx, GuideAt guide_at,
                                          Sink& sink, unsigned char* smem) {
-  using G = AggGeo<A>;
+  using G = AggGeo<A, TY>;
+  constexpr int NT = G::NT;
   constexpr int NW = NT / 64;                    // waves
-  constexpr int PPW = 16 / NW;                   // patches per wave
+  constexpr int PPW = G::NP / NW;                // patches per wave
   constexpr int NITEM = 16 * G::NCH;             // (disparity, chunk) items per tile
   constexpr int SPT = (NITEM + NT - 1) / NT;     // items per thread
-  float* out = reinterpret_cast<float*>(smem);  // two output tiles
-  float* gt = out + 2 * 16 * G::OST;
+  float* out = reinterpret_cast<float*>(smem);  // NOB output tiles
+  float* gt = out + G::NOB * 16 * G::OST;
   float* skt = gt + G::RAW;
   _Float16* hi = reinterpret_cast<_Float16*>(skt + G::SKN);
   _Float16* lo = hi + 2 * 16 * G::PLANE;
@@ -58,9 +59,11 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   }
 
   // Item q of this thread: disparity dd of the tile, chunk k = 4 columns of one row.
-  // meta = dd | in-image column mask << 4 (bit e: column X + e); off = Y * W + X.
+  // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * H * W +
+  // Y * W + X, the element offset from the tile's first disparity plane (32-bit for
+  // H * W <= 2^26), added to a per-tile uniform base.
   const bool pairs_aligned = (W & 1) == 0;  // then every chunk start is 8-byte aligned
-  int off[SPT], ldso[SPT];
+  int eoff[SPT], ldso[SPT];
   unsigned meta[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
@@ -73,21 +76,22 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
 #pragma unroll
       for (int e = 0; e < 4; ++e) m |= (X + e >= 0 && X + e < W) ? (1u << e) : 0u;
     meta[q] = static_cast<unsigned>(dd) | (m << 4);
-    off[q] = m ? Y * W + X : 0;
+    eoff[q] = m ? dd * static_cast<int>(plane) + Y * W + X : 0;
     ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
   float4_t pre[SPT];
   // The load form is chosen per wave (uniform branch): whole 4-column chunks as one
   // 16-byte load when every lane has one, else per-column predicated loads.  No
   // register is then written on one path while the other path's loads are pending.
+  // Past the last disparity tile nothing is loaded.
   auto fetch = [&](int t) {
+    const float* base = cost + static_cast<int64_t>(16 * t) * plane;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       float4_t v = {0.f, 0.f, 0.f, 0.f};
       const unsigned m = meta[q] >> 4;
-      const int d = 16 * t + static_cast<int>(meta[q] & 15u);
-      const unsigned mm = d < D ? m : 0u;
-      const float* p = cost + d * plane + off[q];
+      const unsigned mm = 16 * t + static_cast<int>(meta[q] & 15u) < D ? m : 0u;
+      const float* p = base + eoff[q];  // column X of the chunk (X may be < 0 at the border)
       if (__all(mm == 0xFu && pairs_aligned)) {
         const float2 a = *reinterpret_cast<const float2*>(p);
         const float2 b = *reinterpret_cast<const float2*>(p + 2);
@@ -100,7 +104,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
       pre[q] = v;
     }
   };
-  // Every thread stores every item (surplus ones to the dummy slot), so all loads of
+  // Every thread stores every item (surplus ones to its dummy slot), so all loads of
   // the fetch are consumed on every path.
   auto store = [&](int buf) {
 #pragma unroll
@@ -116,6 +120,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   fetch(0);
   store(0);
   __syncthreads();
+  fetch(1);  // in flight while the weights are computed
 
   PatchPos pp[PPW];
   half8_t whi[PPW][G::KS], wlo[PPW][G::KS];
@@ -126,33 +131,38 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
     pp[k] = PatchPos{patch >> 2, patch & 3};
     const int i = lane & 15;
     const bool pin = by + 4 * pp[k].pr + (i >> 2) < H && bx + 4 * pp[k].pc + (i & 3) < W;
-    iz[k] = patch_weights<A>(whi[k], wlo[k], pp[k], lane, pin, gt, skt, bk.kr);
+    iz[k] = patch_weights<A, TY>(whi[k], wlo[k], pp[k], lane, pin, gt, skt, bk.kr);
   }
 
   const int ndt = (D + 15) >> 4;
   for (int t = 0; t < ndt; ++t) {
     const int buf = t & 1;
-    float* o = out + buf * 16 * G::OST;
-    fetch(t + 1);  // past the last tile it loads nothing
+    float* o = out + (G::NOB == 2 ? buf : 0) * 16 * G::OST;
+    float4_t vals[PPW];
 #pragma unroll
     for (int k = 0; k < PPW; ++k) {
-      const float4_t acc =
-          patch_mfma<A>(whi[k], wlo[k], hi + buf * 16 * G::PLANE, lo + buf * 16 * G::PLANE, pp[k], lane);
-      float4_t vals;
+      const float4_t acc = patch_mfma<A, TY>(whi[k], wlo[k], hi + buf * 16 * G::PLANE,
+                                             lo + buf * 16 * G::PLANE, pp[k], lane);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) vals[e] = acc[e] * iz[k][e];
-      *reinterpret_cast<float4_t*>(o + (lane & 15) * G::OST + (4 * pp[k].pr + (lane >> 4)) * 16 +
-                                   4 * pp[k].pc) = vals;
+      for (int e = 0; e < 4; ++e) vals[k][e] = acc[e] * iz[k][e];
     }
+    // a single output tile was read by the sink of tile t - 1 after the last barrier
+    if (G::NOB == 1) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPW; ++k)
+      *reinterpret_cast<float4_t*>(o + (lane & 15) * G::OST + (4 * pp[k].pr + (lane >> 4)) * 16 +
+                                   4 * pp[k].pc) = vals[k];
     // Keep the staging store (which waits for the loads) after the MFMAs: without
     // this fence the scheduler moves its conversions into the MFMA chain and the
     // loads' latency is no longer hidden.
     __builtin_amdgcn_sched_barrier(0);
-    // staging buffer buf ^ 1 was last read by the MFMAs of tile t - 1 and output
-    // tile buf by the sink of tile t - 2, both before the previous barrier
+    // staging buffer buf ^ 1 was last read by the MFMAs of tile t - 1 and (double
+    // buffering) output tile buf by the sink of tile t - 2, both before the previous
+    // barrier
     store(buf ^ 1);
     __syncthreads();
     sink(t, static_cast<const float*>(o));
+    fetch(t + 2);  // in flight during the next tile's MFMAs
   }
 }
 

@@ -19,25 +19,26 @@
 
 namespace rsv {
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-// Floats per disparity in the LDS output tile of a 16 x 16 block (256 + 4: the
-// planes written by consecutive lanes start on distinct 4-bank groups).
-constexpr int kAggOutStride = 260;
-
-// Geometry of the LDS tiles of a 16 x 16 output block at (by, bx).  The staged
-// cost and guide tiles start at row by - A and column bx - A - PAD; PAD makes that
-// column even, so four consecutive tile columns are one 8-byte aligned pair of
-// float2 loads whenever the image width is even.  Union column c of patch column pc
-// is tile column 4 pc + c.
-template <int A>
+// Geometry of the LDS tiles of a TY x 16 output block at (by, bx) (TY = 16 or 8
+// rows: TY / 4 x 4 patches).  The staged cost and guide tiles start at row by - A
+// and column bx - A - PAD; PAD makes that column even, so four consecutive tile
+// columns are one 8-byte aligned pair of float2 loads whenever the image width is
+// even.  Union column c of patch column pc is tile column 4 pc + c.
+template <int A, int TY>
 struct AggGeo {
+  static_assert(TY == 16 || TY == 8, "tile height");
   static constexpr int PAD = A & 1;
+  static constexpr int NP = TY;              // patches (TY / 4 rows of 4)
+  static constexpr int NT = 64 * NP;         // threads: one wave per patch
   static constexpr int UR = 4 + 2 * A;       // union rows of one patch
   static constexpr int KS = UR / 2;          // K-steps of 32
-  static constexpr int TR = 16 + 2 * A;      // tile rows
+  static constexpr int TR = TY + 2 * A;      // tile rows
   static constexpr int TC = 28;              // tile columns: patch 3's union ends at 12 + 16
   static constexpr int RAW = TR * TC;
   static constexpr int CPR = TC / 4;         // 4-column chunks per tile row
@@ -48,9 +49,25 @@ struct AggGeo {
   // spatial exponent table, indexed by (union row - py + 3, union column - px + 3)
   static constexpr int SKR = UR + 3, SKC = 19;
   static constexpr int SKN = (SKR * SKC + 3) & ~3;
-  static constexpr int OST = kAggOutStride;
+  // output tile: floats per disparity (TY * 16 + 4: the planes written by
+  // consecutive lanes start on distinct 4-bank groups); double-buffered for TY = 16,
+  // single for TY = 8 so that two blocks fit one CU's LDS
+  static constexpr int OST = TY * 16 + 4;
+  static constexpr int NOB = TY == 16 ? 2 : 1;
   static_assert(2 * A + PAD <= 12, "a pixel's window must fit the 16 union columns");
 };
+
+// Largest H * W the aggregation tile accepts: its loads address 16 disparity planes
+// from one base with 32-bit offsets.
+constexpr int64_t kAggMaxPixels = int64_t(1) << 26;
+
+// fp16 hi / lo split of two floats (x = hi + lo to about 2^-22 relative), as packed
+// conversions.
+__device__ __forceinline__ void split2(float a, float b, half2_t& hi, half2_t& lo) {
+  const float2_t x = {a, b};
+  hi = __builtin_convertvector(x, half2_t);
+  lo = __builtin_convertvector(x - __builtin_convertvector(hi, float2_t), half2_t);
+}
 
 struct PatchPos {
   int pr, pc;  // patch row / column inside the 16 x 16 block (0..3)
@@ -60,11 +77,11 @@ struct PatchPos {
 // gt: guide tile (+inf outside the image); skt: spatial exponent table (+inf
 // outside the window).  Returns 1 / Z for the four output pixels this lane
 // receives from the MFMA (patch row g = lane / 16, columns 0..3).
-template <int A>
+template <int A, int TY>
 __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, const PatchPos& pp,
                                                   int lane, bool pin, const float* gt, const float* skt,
                                                   float kr) {
-  using G = AggGeo<A>;
+  using G = AggGeo<A, TY>;
   const int i = lane & 15, g = lane >> 4;
   const int py = i >> 2, px = i & 3;
   const float gp = pin ? gt[(4 * pp.pr + py + A) * G::TC + 4 * pp.pc + px + A + G::PAD] : 0.f;
@@ -72,15 +89,23 @@ __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, co
   const float* sk = skt + ((g >> 1) - py + 3) * G::SKC + 8 * (g & 1) - px + 3;
   float z = 0.f;
 #pragma unroll
-  for (int s = 0; s < G::KS; ++s)
+  for (int s = 0; s < G::KS; ++s) {
+    float wt[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float wt = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e], kr);
-      const _Float16 h = static_cast<_Float16>(wt);
-      whi[s][e] = h;
-      wlo[s][e] = static_cast<_Float16>(wt - static_cast<float>(h));
-      z += wt;
+      wt[e] = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e], kr);
+      z += wt[e];
     }
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      half2_t h, l;
+      split2(wt[e], wt[e + 1], h, l);
+      whi[s][e] = h[0];
+      whi[s][e + 1] = h[1];
+      wlo[s][e] = l[0];
+      wlo[s][e + 1] = l[1];
+    }
+  }
   // the four lanes holding pixel i cover disjoint K ranges: sum them
   z += __shfl_xor(z, 16);
   z += __shfl_xor(z, 32);
@@ -105,11 +130,11 @@ __device__ __forceinline__ half8_t lds_load8(const _Float16* p) {
 
 // acc += W' x C over all K-steps for one patch and one 16-disparity tile held in
 // LDS as hi / lo planes.
-template <int A>
+template <int A, int TY>
 __device__ __forceinline__ float4_t patch_mfma(const half8_t* whi, const half8_t* wlo,
                                                const _Float16* hi, const _Float16* lo,
                                                const PatchPos& pp, int lane) {
-  using G = AggGeo<A>;
+  using G = AggGeo<A, TY>;
   const int j = lane & 15, g = lane >> 4;
   const int base = j * G::PLANE + (4 * pp.pr + (g >> 1)) * G::TC + 4 * pp.pc + 8 * (g & 1);
   float4_t acc = {0.f, 0.f, 0.f, 0.f};
@@ -127,12 +152,11 @@ __device__ __forceinline__ float4_t patch_mfma(const half8_t* whi, const half8_t
 
 // fp16 hi / lo split of four costs: c = hi + lo to about 2^-22 relative.
 __device__ __forceinline__ void split4(const float4_t& c, half4_t& hi, half4_t& lo) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const _Float16 h = static_cast<_Float16>(c[e]);
-    hi[e] = h;
-    lo[e] = static_cast<_Float16>(c[e] - static_cast<float>(h));
-  }
+  half2_t h0, l0, h1, l1;
+  split2(c[0], c[1], h0, l0);
+  split2(c[2], c[3], h1, l1);
+  hi[0] = h0[0]; hi[1] = h0[1]; hi[2] = h1[0]; hi[3] = h1[1];
+  lo[0] = l0[0]; lo[1] = l0[1]; lo[2] = l1[0]; lo[3] = l1[1];
 }
 
 }  // namespace rsv

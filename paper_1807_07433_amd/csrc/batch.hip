@@ -83,7 +83,7 @@ struct WtaSink {
     if (p >= 256) return;
     const int n = min(16, D - 16 * t);
     for (int dd = 0; dd < n; ++dd) {
-      const float a = o[dd * kAggOutStride + p];
+      const float a = o[dd * AggGeo<1, 16>::OST + p];
       const int d = 16 * t + dd;
       if (full) {
         if (d == 0)
@@ -132,23 +132,23 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args
 
 template <int A>
 __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsigned char* smem) {
-  const PairDev* pd = args.pairs + w.x;
-  const int H = pd->H, W = pd->W, D = pd->D;
-  const int by = 16 * w.z, bx = 16 * w.w;
-  const bool full = w.y == kItemAggRef;
+  // the item and the pair's fields are the same for the whole workgroup
+  const PairDev* pd = uniform(args.pairs + uniform(w.x));
+  const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
+  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
+  const bool full = uniform(w.y) == kItemAggRef;
   WtaSink sink{D, full};
-  if (full) {
-    const uint8_t* left = pd->left;
-    const int64_t lpitch = pd->lpitch;
-    auto guide = [&](int Y, int X) { return pixel(left, lpitch, Y, X); };
-    agg_tile<A, kAggItemThreads>(pd->cref, H, W, D, args.bk, by, bx, guide, sink, smem);
-  } else {
-    const uint8_t* right = pd->right;
-    const int64_t rpitch = pd->rpitch;
-    const rsv_plane pl = pd->plane;
-    auto guide = [&](int Y, int X) { return warp_sample(right, rpitch, W, pl, X, Y); };
-    agg_tile<A, kAggItemThreads>(pd->ctar, H, W, D, args.bk, by, bx, guide, sink, smem);
-  }
+  // reference: guided by the left image; target: by the warped right image, sampled
+  // with rsv_warp's arithmetic (one branch per guide pixel, uniform per item)
+  const uint8_t* left = uniform(pd->left);
+  const uint8_t* right = uniform(pd->right);
+  const int64_t lpitch = uniform(pd->lpitch), rpitch = uniform(pd->rpitch);
+  const rsv_plane pl = pd->plane;
+  const float* cost = uniform(full ? pd->cref : pd->ctar);
+  auto guide = [&](int Y, int X) {
+    return full ? pixel(left, lpitch, Y, X) : warp_sample(right, rpitch, W, pl, X, Y);
+  };
+  agg_tile<A, 16>(cost, H, W, D, args.bk, by, bx, guide, sink, smem);
   if (threadIdx.x < 256) {
     const int q = threadIdx.x;
     const int Y = by + (q >> 4), X = bx + (q & 15);
@@ -243,12 +243,12 @@ const void* pick_agg_kernel(int A, size_t* lds) {
   size_t t = 0;
   const void* k = nullptr;
   switch (A) {
-    case 1: t = agg_tile_lds_bytes<1>(); k = agg_kernel_ptr<1>(); break;
-    case 2: t = agg_tile_lds_bytes<2>(); k = agg_kernel_ptr<2>(); break;
-    case 3: t = agg_tile_lds_bytes<3>(); k = agg_kernel_ptr<3>(); break;
-    case 4: t = agg_tile_lds_bytes<4>(); k = agg_kernel_ptr<4>(); break;
-    case 5: t = agg_tile_lds_bytes<5>(); k = agg_kernel_ptr<5>(); break;
-    case 6: t = agg_tile_lds_bytes<6>(); k = agg_kernel_ptr<6>(); break;
+    case 1: t = agg_tile_lds_bytes<1, 16>(); k = agg_kernel_ptr<1>(); break;
+    case 2: t = agg_tile_lds_bytes<2, 16>(); k = agg_kernel_ptr<2>(); break;
+    case 3: t = agg_tile_lds_bytes<3, 16>(); k = agg_kernel_ptr<3>(); break;
+    case 4: t = agg_tile_lds_bytes<4, 16>(); k = agg_kernel_ptr<4>(); break;
+    case 5: t = agg_tile_lds_bytes<5, 16>(); k = agg_kernel_ptr<5>(); break;
+    case 6: t = agg_tile_lds_bytes<6, 16>(); k = agg_kernel_ptr<6>(); break;
     default: return nullptr;
   }
   *lds = t;
@@ -261,6 +261,7 @@ int validate_pair(const rsv_pair_desc& pd, int K) {
   if (pd.left.dtype != RSV_U8 || pd.right.dtype != RSV_U8) return RSV_E_DTYPE;
   if (pd.left.height != pd.right.height || pd.left.width != pd.right.width) return RSV_E_SHAPE;
   if (pd.left.height < K || pd.left.width < K) return RSV_E_SHAPE;
+  if (static_cast<int64_t>(pd.left.height) * pd.left.width > kAggMaxPixels) return RSV_E_SHAPE;
   if (pd.D < 1 || pd.D > RSV_MAX_D) return RSV_E_SHAPE;
   if (!pd.disp_sub || !pd.valid) return RSV_E_NULL;
   if (!(pd.camera.f > 0.0) || !(pd.camera.baseline > 0.0)) return RSV_E_PARAM;
