@@ -42,7 +42,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   float* skt = gt + G::RAW;
   _Float16* hi = reinterpret_cast<_Float16*>(skt + G::SKN);
   _Float16* lo = hi + 2 * 16 * G::PLANE;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
   _Float16* dummy = lo + 2 * 16 * G::PLANE + 4 * lane;  // store target of surplus items
   const int64_t plane = static_cast<int64_t>(H) * W;
   const int x0 = bx - A - G::PAD;  // image column of tile column 0 (even)

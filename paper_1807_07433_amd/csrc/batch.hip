@@ -1,23 +1,28 @@
 // Batched form: many stereo pairs of uneven size and disparity range in one
 // hipGraph launch of persistent work-queue kernels.
 //
-// A plan holds, per pair, the two cost volumes and the WTA state, plus two work
-// lists, and captures the graph
-//     reset counters -> cost kernel -> aggregate+WTA kernel -> tail kernel.
+// A plan holds, per pair, the warped right image, the two cost volumes and the WTA
+// state, plus the work lists, and captures the graph
+//     reset counters -> warp -> cost kernel -> aggregate+WTA kernel -> tail kernel.
 // The persistent kernels pull items from atomic counters, so pairs of any size and
 // D share the GPU without per-pair launches:
-//   cost items (pair, band of 4 rows, 64 centres): warp + ZNCC with the arithmetic
-//       of rsv_warp / rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
+//   warp: every pixel of every pair, with rsv_warp's arithmetic;
+//   cost items (pair, band of 4 rows, 64-centre column tiles): ZNCC with the
+//       arithmetic of rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
 //   aggregation items (pair, 16 x 16 tile, ref | tar): bilateral aggregation on the
 //       matrix cores with the arithmetic of rsv_aggregate (shared agg_tile) and
 //       winner-take-all folded in: each 16-disparity tile of aggregated values is
 //       fed, from LDS, through the select kernel's own scan step (running best,
 //       second best and the winner's neighbours, ties keep the lowest d).  No
-//       aggregated volume is written.
-// The tail applies the left-right check (Eq. 11), the parabola (Eq. 12),
-// post-processing and triangulation per pixel, with the plain path's functions.
-// Every output therefore equals the plain path's bit for bit.  The kernel boundary
-// between cost and aggregation replaces any cross-workgroup wait.
+//       aggregated volume is written.  The aggregation list is cut into 8 contiguous
+//       stretches, one queue per XCD (workgroups are dealt to the XCDs round-robin),
+//       so neighbouring tiles share an L2; a workgroup whose queue is empty takes
+//       items from the next queues.
+// Workgroups claim items in chunks of 4 neighbours, one atomic per chunk.  The tail
+// applies the left-right check (Eq. 11), the
+// parabola (Eq. 12), post-processing and triangulation per pixel, with the plain
+// path's functions.  Every output therefore equals the plain path's bit for bit.
+// The kernel boundaries replace any cross-workgroup wait.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +39,7 @@ namespace rsv {
 constexpr int kCostThreads = 256;
 constexpr int kBandRows = kCostThreads / kCostTW;  // 4
 constexpr int kAggItemThreads = 1024;
+constexpr int kAggQueues = 8;  // one per XCD
 
 enum : int { kItemCost = 0, kItemAggRef = 1, kItemAggTar = 2 };
 
@@ -44,6 +50,7 @@ struct PairDev {
   int H, W, D, nbands, ncol_tiles, tiles_x;
   rsv_plane plane;
   rsv_camera cam;
+  float* warped;
   float* cref;
   float* ctar;
   int32_t* ref_arg;
@@ -59,28 +66,50 @@ struct PairDev {
   float* xyz;
 };
 
+// Work queues over one item list: queue q holds items [qbeg[q], qbeg[q + 1]) and
+// head[q] counts the items taken from it.
 struct BatchArgs {
   const PairDev* pairs;
   const int4* items;  // {pair, kind, a, b}
-  int n_items;
-  int* head;
+  const int* qbeg;    // nq + 1 entries
+  int nq;
+  int* head;          // nq counters
   BilateralK bk;
   float sigma_min;
 };
 
+// Scan state of the 256 pixels of one aggregation item, in LDS between disparity
+// tiles (kept out of registers, which the tile needs).
+struct WtaState {
+  float best[256], second[256], am[256], ap[256], prev[256];
+  int arg[256], need_next[256];
+};
+
 // agg_tile sink that runs the select kernel's scan over d for the tile's 256
 // pixels, 16 disparities at a time: thread p < 256 owns pixel p (row p / 16,
-// column p % 16) and keeps its state in registers across the disparity tiles.
+// column p % 16).
 struct WtaSink {
+  WtaState* st;
   int D;
   bool full;  // reference volume: best, second best and neighbours; target: argmax only
-  Scan s;
-  bool need_next;
-  float prev;
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
     const int p = threadIdx.x;
     if (p >= 256) return;
+    Scan s;
+    bool need_next = false;
+    float prev = 0.f;
+    if (t > 0) {
+      s.best = st->best[p];
+      s.arg = st->arg[p];
+      if (full) {
+        s.second = st->second[p];
+        s.am = st->am[p];
+        s.ap = st->ap[p];
+        prev = st->prev[p];
+        need_next = st->need_next[p] != 0;
+      }
+    }
     const int n = min(16, D - 16 * t);
     for (int dd = 0; dd < n; ++dd) {
       const float a = o[dd * AggGeo<1, 16>::OST + p];
@@ -95,39 +124,102 @@ struct WtaSink {
         s.arg = d;
       }
     }
+    st->best[p] = s.best;
+    st->arg[p] = s.arg;
+    if (full) {
+      st->second[p] = s.second;
+      st->am[p] = s.am;
+      st->ap[p] = s.ap;
+      st->prev[p] = prev;
+      st->need_next[p] = need_next ? 1 : 0;
+    }
   }
 };
 
-// Next item of a work list for the whole workgroup (uniform), or -1 when done.
-__device__ __forceinline__ int next_item(int* head, int n_items, int* slot) {
-  if (threadIdx.x == 0) *slot = atomicAdd(head, 1);
-  __syncthreads();
-  const int it = __builtin_amdgcn_readfirstlane(*slot);
-  __syncthreads();
-  return it < n_items ? it : -1;
+// Items are claimed in chunks of kChunk consecutive list entries: one atomic per
+// chunk, and a chunk's items are neighbours (they share halo data in L2).
+constexpr int kChunk = 4;
+
+// First item of a chunk from queue q, or -1 when the queue is exhausted (the
+// counter still advances).
+__device__ __forceinline__ int take(const BatchArgs& a, int q) {
+  const int it = a.qbeg[q] + kChunk * atomicAdd(&a.head[q], 1);
+  return it < a.qbeg[q + 1] ? it : -1;
+}
+
+// A chunk for the workgroup: from the home queue, else from the following queues.
+__device__ int claim(const BatchArgs& a, int home, int* end) {
+  for (int k = 0; k < a.nq; ++k) {
+    const int q = (home + k) % a.nq;
+    const int it = take(a, q);
+    if (it >= 0) {
+      *end = min(it + kChunk, a.qbeg[q + 1]);
+      return it;
+    }
+  }
+  return -1;
+}
+
+// Runs body(item) for every item this workgroup obtains.
+template <typename Body>
+__device__ __forceinline__ void for_each_item(const BatchArgs& a, int home, int* slot, Body body) {
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int end = 0;
+      slot[0] = claim(a, home, &end);
+      slot[1] = end;
+    }
+    __syncthreads();
+    const int first = __builtin_amdgcn_readfirstlane(slot[0]);
+    const int end = __builtin_amdgcn_readfirstlane(slot[1]);
+    __syncthreads();
+    if (first < 0) return;
+    for (int it = first; it < end; ++it) {
+      body(it);
+      __syncthreads();  // the item's LDS is free for the next one
+    }
+  }
+}
+
+// The warped right image of every pair (rsv_warp's arithmetic); grid (x, pair).
+__global__ __launch_bounds__(256) void batch_warp_kernel(const PairDev* pairs) {
+  const PairDev* pd = pairs + blockIdx.y;
+  const int W = pd->W;
+  const int64_t n = static_cast<int64_t>(pd->H) * W;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * 256) {
+    const int v = static_cast<int>(i / W), u = static_cast<int>(i - static_cast<int64_t>(v) * W);
+    pd->warped[i] = warp_sample(pd->right, pd->rpitch, W, pd->plane, u, v);
+  }
 }
 
 // Cost item {pair, tiles << 8, band, first column tile}: `tiles` consecutive tiles of
 // 64 centres x kBandRows rows.
 template <int R>
+__device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, float* cwork) {
+  const PairDev* pd = uniform(args.pairs + uniform(w.x));
+  const float* warped = uniform(pd->warped);
+  const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
+  auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
+  const int c0 = uniform(w.w);
+  const int last = min(c0 + (uniform(w.y) >> 8), uniform(pd->ncol_tiles));
+  const int v0 = uniform(w.z) * kBandRows;
+  const uint8_t* left = uniform(pd->left);
+  const int64_t lpitch = uniform(pd->lpitch);
+  float* cref = uniform(pd->cref);
+  float* ctar = uniform(pd->ctar);
+  for (int ct = c0; ct < last; ++ct) {
+    if (ct > c0) __syncthreads();  // LDS is reused by the next tile
+    cost_tile<R, kBandRows>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0, cref,
+                            ctar, cwork);
+  }
+}
+
+template <int R>
 __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args) {
   extern __shared__ __align__(16) float cwork[];
-  __shared__ int s_item;
-  for (int it; (it = next_item(args.head, args.n_items, &s_item)) >= 0;) {
-    const int4 w = args.items[it];
-    const PairDev* pd = args.pairs + w.x;
-    const uint8_t* right = pd->right;
-    const int64_t rpitch = pd->rpitch;
-    const int W = pd->W;
-    const rsv_plane pl = pd->plane;
-    auto warped_at = [&](int y, int x) { return warp_sample(right, rpitch, W, pl, x, y); };
-    const int last = min(w.w + (w.y >> 8), pd->ncol_tiles);
-    for (int ct = w.w; ct < last; ++ct) {
-      cost_tile<R, kBandRows>(pd->left, pd->lpitch, warped_at, pd->H, W, pd->D, args.sigma_min,
-                              ct * kCostTW, w.z * kBandRows, pd->cref, pd->ctar, cwork);
-      __syncthreads();  // LDS is reused by the next tile
-    }
-  }
+  __shared__ int s_item[2];
+  for_each_item(args, 0, s_item, [&](int it) { batch_cost_item<R>(args, args.items[it], cwork); });
 }
 
 template <int A>
@@ -137,30 +229,31 @@ __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsig
   const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
   const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
   const bool full = uniform(w.y) == kItemAggRef;
-  WtaSink sink{D, full};
-  // reference: guided by the left image; target: by the warped right image, sampled
-  // with rsv_warp's arithmetic (one branch per guide pixel, uniform per item)
+  WtaState* st = reinterpret_cast<WtaState*>(smem + agg_tile_lds_bytes<A, 16>());
+  WtaSink sink{st, D, full};
+  // reference: guided by the left image; target: by the warped right image (one
+  // branch per guide pixel, uniform per item)
   const uint8_t* left = uniform(pd->left);
-  const uint8_t* right = uniform(pd->right);
-  const int64_t lpitch = uniform(pd->lpitch), rpitch = uniform(pd->rpitch);
-  const rsv_plane pl = pd->plane;
+  const float* warped = uniform(pd->warped);
+  const int64_t lpitch = uniform(pd->lpitch);
   const float* cost = uniform(full ? pd->cref : pd->ctar);
   auto guide = [&](int Y, int X) {
-    return full ? pixel(left, lpitch, Y, X) : warp_sample(right, rpitch, W, pl, X, Y);
+    return full ? pixel(left, lpitch, Y, X) : warped[static_cast<int64_t>(Y) * W + X];
   };
   agg_tile<A, 16>(cost, H, W, D, args.bk, by, bx, guide, sink, smem);
+  // each thread < 256 wrote its own pixel's state in the last sink call
   if (threadIdx.x < 256) {
     const int q = threadIdx.x;
     const int Y = by + (q >> 4), X = bx + (q & 15);
     if (Y < H && X < W) {
       const int64_t i = static_cast<int64_t>(Y) * W + X;
       if (full) {
-        pd->ref_arg[i] = sink.s.arg;
-        pd->ref_best[i] = sink.s.best;
-        pd->ref_am[i] = sink.s.am;
-        pd->ref_ap[i] = sink.s.ap;
+        uniform(pd->ref_arg)[i] = st->arg[q];
+        uniform(pd->ref_best)[i] = st->best[q];
+        uniform(pd->ref_am)[i] = st->am[q];
+        uniform(pd->ref_ap)[i] = st->ap[q];
       } else {
-        pd->tar_arg[i] = sink.s.arg;
+        uniform(pd->tar_arg)[i] = st->arg[q];
       }
     }
   }
@@ -169,11 +262,9 @@ __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsig
 template <int A>
 __global__ __launch_bounds__(kAggItemThreads) void batch_agg_kernel(BatchArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_item;
-  for (int it; (it = next_item(args.head, args.n_items, &s_item)) >= 0;) {
-    batch_agg_item<A>(args, args.items[it], smem);
-    __syncthreads();  // LDS is reused by the next item
-  }
+  __shared__ int s_item[2];
+  const int home = static_cast<int>(blockIdx.x % static_cast<unsigned>(args.nq));
+  for_each_item(args, home, s_item, [&](int it) { batch_agg_item<A>(args, args.items[it], smem); });
 }
 
 // Left-right check, Eq. 12, post-processing and 3-D points for every pixel of every pair.
@@ -196,8 +287,8 @@ __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, i
   }
 }
 
-__global__ void batch_reset_kernel(int* heads) {
-  if (threadIdx.x < 2) heads[threadIdx.x] = 0;
+__global__ void batch_reset_kernel(int* heads, int n) {
+  if (static_cast<int>(threadIdx.x) < n) heads[threadIdx.x] = 0;
 }
 
 }  // namespace rsv
@@ -208,7 +299,7 @@ struct rsv_batch_plan {
   rsv_tuning tuning{};
   void* dev_mem = nullptr;  // one allocation: pair table, item lists, counters, workspace
   rsv::PairDev* d_pairs = nullptr;
-  int* d_heads = nullptr;   // [cost, aggregation]
+  int* d_heads = nullptr;   // [cost, aggregation queues]
   rsv::BatchArgs cost_args{}, agg_args{};
   int n_cost_items = 0, n_agg_items = 0;
   int cost_grid = 0, agg_grid = 0;
@@ -251,7 +342,7 @@ const void* pick_agg_kernel(int A, size_t* lds) {
     case 6: t = agg_tile_lds_bytes<6, 16>(); k = agg_kernel_ptr<6>(); break;
     default: return nullptr;
   }
-  *lds = t;
+  *lds = t + sizeof(WtaState);
   return k;
 }
 
@@ -328,7 +419,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     off_ctar[i] = ws_bytes;
     ws_bytes = align(ws_bytes + sizeof(float) * N * D);
     off_maps[i] = ws_bytes;
-    ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float) * 3));
+    ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float) * 4));  // + warped image
     max_pixels = std::max<int>(max_pixels, static_cast<int>(N));
     PairDev& P = pd[i];
     P.left = static_cast<const uint8_t*>(q.left.data);
@@ -350,17 +441,24 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.disp_final = q.disp_final;
     P.xyz = q.xyz;
   }
+  // agg items: per pair, the reference tiles then the target tiles, row-major, so
+  // each queue's stretch of the list is a band of neighbouring tiles of one volume
   for (int i : order) {
     const PairDev& P = pd[i];
     for (int b = 0; b < P.nbands; ++b)
       for (int ct = 0; ct < P.ncol_tiles; ct += tn.cost_tiles_per_item)
         cost_items.push_back(make_int4(i, kItemCost | (tn.cost_tiles_per_item << 8), b, ct));
-    for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
-      for (int tx = 0; tx < P.tiles_x; ++tx) {
-        agg_items.push_back(make_int4(i, kItemAggRef, ty, tx));
-        agg_items.push_back(make_int4(i, kItemAggTar, ty, tx));
-      }
+    for (int kind : {kItemAggRef, kItemAggTar})
+      for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
+        for (int tx = 0; tx < P.tiles_x; ++tx) agg_items.push_back(make_int4(i, kind, ty, tx));
   }
+  // queue boundaries: [0, n_cost) for the cost kernel; 8 equal stretches of the agg list
+  std::vector<int> qbeg(2 + kAggQueues + 1);
+  qbeg[0] = 0;
+  qbeg[1] = static_cast<int>(cost_items.size());
+  const int na = static_cast<int>(agg_items.size());
+  for (int q = 0; q <= kAggQueues; ++q)
+    qbeg[2 + q] = static_cast<int>((static_cast<int64_t>(na) * q) / kAggQueues);
 
   rsv_batch_plan* plan = new (std::nothrow) rsv_batch_plan();
   if (!plan) return RSV_E_NOMEM;
@@ -377,7 +475,9 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   const size_t o_ai = off;
   off = align(off + sizeof(int4) * agg_items.size());
   const size_t o_heads = off;
-  off = align(off + sizeof(int) * 2);
+  off = align(off + sizeof(int) * (1 + kAggQueues));
+  const size_t o_qbeg = off;
+  off = align(off + sizeof(int) * qbeg.size());
   const size_t o_ws = off;
   off += ws_bytes;
   hipError_t e = hipMalloc(&plan->dev_mem, off);
@@ -400,6 +500,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.ref_best = reinterpret_cast<float*>(P.tar_arg + N);
     P.ref_am = P.ref_best + N;
     P.ref_ap = P.ref_am + N;
+    P.warped = P.ref_ap + N;
   }
   auto fail = [&](hipError_t err) {
     set_hip_error(err);
@@ -413,6 +514,9 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     return fail(e);
   if ((e = hipMemcpy(base + o_ai, agg_items.data(), sizeof(int4) * agg_items.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMemcpy(base + o_qbeg, qbeg.data(), sizeof(int) * qbeg.size(), hipMemcpyHostToDevice)) !=
+      hipSuccess)
     return fail(e);
 
   const void* ck = pick_cost_kernel(R);
@@ -445,29 +549,33 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   plan->cost_grid = std::min(cus * cpc, std::max(1, plan->n_cost_items));
   plan->agg_grid = std::min(cus * apc, std::max(1, plan->n_agg_items));
 
+  const int* d_qbeg = reinterpret_cast<const int*>(base + o_qbeg);
   BatchArgs& ca = plan->cost_args;
   ca.pairs = plan->d_pairs;
   ca.items = reinterpret_cast<const int4*>(base + o_ci);
-  ca.n_items = plan->n_cost_items;
+  ca.qbeg = d_qbeg;
+  ca.nq = 1;
   ca.head = plan->d_heads;
   ca.sigma_min = p->sigma_min;
   ca.bk = bilateral_constants(p->gamma_d, p->gamma_r);
   BatchArgs& aa = plan->agg_args;
   aa = ca;
   aa.items = reinterpret_cast<const int4*>(base + o_ai);
-  aa.n_items = plan->n_agg_items;
+  aa.qbeg = d_qbeg + 2;
+  aa.nq = kAggQueues;
   aa.head = plan->d_heads + 1;
 
-  // graph: reset counters -> cost kernel -> aggregation + WTA kernel -> tail
+  // graph: reset counters -> warp -> cost kernel -> aggregation + WTA kernel -> tail
   if ((e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
-  batch_reset_kernel<<<1, 64, 0, plan->capture_stream>>>(plan->d_heads);
+  batch_reset_kernel<<<1, 64, 0, plan->capture_stream>>>(plan->d_heads, 1 + kAggQueues);
+  const int tail_x = std::min(1024, (max_pixels + 255) / 256);
+  batch_warp_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs);
   void* cargs[] = {&plan->cost_args};
   hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
   void* aargs[] = {&plan->agg_args};
   hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
-  const int tail_x = std::min(1024, (max_pixels + 255) / 256);
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
   e = hipStreamEndCapture(plan->capture_stream, &plan->graph);

@@ -34,7 +34,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
                                           float* smem) {
   constexpr int K = 2 * R + 1;
   constexpr int NT = kCostTW * TH;
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int tx = tid % kCostTW, ty = tid / kCostTW;
   constexpr int wtw = kWarpStride;          // warped tile row stride
   const int rows = TH + 2 * R;

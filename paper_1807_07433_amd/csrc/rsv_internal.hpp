@@ -83,6 +83,16 @@ __device__ __forceinline__ T* uniform(T* p) {
   return reinterpret_cast<T*>(uniform(static_cast<int64_t>(reinterpret_cast<uintptr_t>(p))));
 }
 
+// threadIdx.x as a value the compiler cannot see through.  A tile function called
+// once per work item of a persistent loop derives its per-thread indices from it,
+// so they are recomputed per item instead of being hoisted out of the loop and kept
+// live (which costs registers and occupancy).
+__device__ __forceinline__ int opaque_tid() {
+  int t = static_cast<int>(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 template <typename T>
