@@ -51,39 +51,77 @@ def mde_per_s(W: int, H: int, D: int, seconds: float) -> float:
     return W * H * D / seconds * 1e-6
 
 
-def source_sha(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_sha(paths):
+    """sha256 (16 hex digits) over the sources that define a kernel, in order."""
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel_src: str, kernel: str, workload: str):
+CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
+KERNEL_SOURCES = {
+    "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
+    "aggregate": ["aggregate.hip", "agg_tile.hpp", "aggregate_mfma.hpp", "bilateral_math.hpp",
+                  "rsv_internal.hpp"],
+    "select_subpixel": ["select.hip", "select_math.hpp", "rsv_internal.hpp"],
+}
+
+
+def kernel_sha(kernel):
+    return source_sha([os.path.join(CSRC, f) for f in KERNEL_SOURCES[kernel]])
+
+
+def recorded_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel sources; else None."""
     f = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
     if not os.path.exists(f):
         return None
     txt = open(f).read()
     sha = re.search(r"source_sha:\s*([0-9a-f]+)", txt)
     tb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not sha or not tb or sha.group(1) != source_sha(kernel_src):
+    if not sha or not tb or sha.group(1) != kernel_sha(kernel):
         return None
     return float(tb.group(1))
 
 
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 matrix, published
+
+
 def kernel_rooflines(stage_ms, W, H, D, prm):
-    """Algorithmic HBM bytes per launch / average launch time for the three volume
-    kernels (all HBM-bound at these sizes):
-      cost_volume: writes C_ref and C_tar, 8 B per entry (image reads are O(1/D));
-      aggregate:   reads one volume and writes one, 8 B per entry (per launch);
-      select:      reads both aggregated volumes, 8 B per entry."""
+    """Per-launch algorithmic work / average launch time for the three volume kernels,
+    each against the resource that bounds it at these sizes:
+      cost_volume: HBM, writes C_ref and C_tar, 8 B per entry (image reads are O(1/D));
+      aggregate:   FP32 arithmetic, 2m + 2 FLOP per entry (m = (2 rho + 1)^2 weighted
+                   terms, weight sum and normalisation), against the FP32 vector peak.
+                   Also reported: its HBM rate (8 B per entry) and the matrix-core work
+                   it issues (3 split-fp16 MFMAs per K-step, padded window union)
+                   against the fp16 matrix peak;
+      select:      HBM, reads both aggregated volumes, 8 B per entry."""
     n = W * H * D
-    per = {"cost_volume": (stage_ms["cost_volume"], 8 * n),
-           "aggregate": (0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]), 8 * n),
-           "select_subpixel": (stage_ms["select_subpixel"], 8 * n)}
+    m = (2 * prm.agg_radius + 1) ** 2
     out = {}
-    for k, (ms, b) in per.items():
-        gbs = b / (ms * 1e-3) / 1e9
+    for k, key in (("cost_volume", "cost_volume"), ("select_subpixel", "select_subpixel")):
+        ms = stage_ms[key]
+        gbs = 8 * n / (ms * 1e-3) / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": b, "ms": round(ms, 5)}
+                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": 8 * n, "ms": round(ms, 5)}
+    ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
+    flops = (2 * m + 2) * n
+    tf = flops / (ms * 1e-3) / 1e12
+    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    issued = tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
+    itf = issued / (ms * 1e-3) / 1e12
+    gbs = 8 * n / (ms * 1e-3) / 1e9
+    out["aggregate"] = {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                        "flops_per_launch": flops, "ms": round(ms, 5),
+                        "hbm_view": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)},
+                        "mfma_view": {"issued_flops_per_launch": issued, "achieved_tflops": round(itf, 1),
+                                      "peak": PEAK_FP16_MFMA_TFLOPS,
+                                      "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)}}
     return out
 
 
@@ -266,11 +304,8 @@ def main():
     t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
     kernels = kernel_rooflines(stage_ms, W, H, D, prm)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    roof = dict(kernels[dom])
-    src = {"cost_volume": "cost_tile.hpp", "aggregate": "agg_tile.hpp",
-           "select_subpixel": "select.hip"}[dom]
-    roof["traffic"] = recorded_traffic(os.path.join(ROOT, "paper_1807_07433_amd", "csrc", src),
-                                       dom, a.workload)
+    roof = {k: v for k, v in kernels[dom].items() if k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof["traffic"] = recorded_traffic(dom, a.workload)
     roof = {"kernel": dom, **roof}
 
     out = {

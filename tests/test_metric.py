@@ -17,10 +17,26 @@ def test_eq13_reproduces_the_printed_throughput():
     assert abs(bench.mde_per_s(g["u_max"], g["v_max"], 30, t) - g["mde_per_s"]) < 0.1
 
 
-def test_kernel_roofline_bytes():
+def test_kernel_roofline_units():
+    """Cost and select against HBM at 8 B per entry; the aggregation against the FP32
+    arithmetic peak at 2m + 2 FLOP per entry, m = (2 rho + 1)^2."""
+    class P:
+        agg_radius = 5
     st = {"cost_volume": 0.1, "aggregate_ref": 0.2, "aggregate_tar": 0.2, "select_subpixel": 0.05}
-    k = bench.kernel_rooflines(st, 1280, 720, 64, None)
+    k = bench.kernel_rooflines(st, 1280, 720, 64, P)
     n = 1280 * 720 * 64
-    assert k["aggregate"]["bytes_per_launch"] == 8 * n
+    assert k["cost_volume"]["bound"] == "hbm" and k["cost_volume"]["bytes_per_launch"] == 8 * n
     assert abs(k["select_subpixel"]["achieved"] - 8 * n / 0.05e-3 / 1e9) < 1.0
-    assert k["cost_volume"]["bound"] == "hbm"
+    agg = k["aggregate"]
+    assert agg["bound"] == "alu" and agg["flops_per_launch"] == (2 * 121 + 2) * n
+    assert abs(agg["achieved"] - (2 * 121 + 2) * n / 0.2e-3 / 1e12) < 0.01
+    assert abs(agg["frac"] - agg["achieved"] / 157.3) < 1e-3
+    # issued matrix work: 80 x 45 tiles, 4 disparity tiles, 16 patches, 7 K-steps, 3 MFMAs
+    assert agg["mfma_view"]["issued_flops_per_launch"] == 80 * 45 * 4 * 16 * 7 * 3 * 16384
+
+
+def test_kernel_sha_covers_every_source():
+    for kernel, files in bench.KERNEL_SOURCES.items():
+        for f in files:
+            assert os.path.exists(os.path.join(bench.CSRC, f)), (kernel, f)
+        assert len(bench.kernel_sha(kernel)) == 16
