@@ -10,7 +10,7 @@ namespace rsv {
 constexpr int kCostTH = 4;
 
 template <int R, typename TL>
-__global__ __launch_bounds__(kCostTW* kCostTH) void cost_volume_kernel(
+__global__ __launch_bounds__(kCostTW* kCostTH, R <= 3 ? 4 : 1) void cost_volume_kernel(
     const TL* __restrict__ left, int64_t lpitch, const float* __restrict__ warped, int H, int W,
     int D, float sigma_min, float* __restrict__ cost_ref, float* __restrict__ cost_tar) {
   extern __shared__ float smem[];

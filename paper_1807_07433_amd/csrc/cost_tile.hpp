@@ -69,7 +69,12 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   const int v = v0 + ty;
   const bool row_ok = v < H;
   const int64_t plane = static_cast<int64_t>(H) * W;
-  const int64_t rowoff = static_cast<int64_t>(v) * W;
+  // Stores go to a per-disparity base that is the same for the whole workgroup plus
+  // this thread's element offset v * W + u, for both volumes: C_tar's base is moved
+  // back by d so that column u - d has the same offset.
+  const uint32_t toff = static_cast<uint32_t>(v) * static_cast<uint32_t>(W) + static_cast<uint32_t>(u);
+  const bool ref_ok = row_ok && u < W;
+  const bool tar_ok = row_ok && cost_tar != nullptr;
   const float* wrow = wt + ty * wtw + tx + (D - 1);  // window column k at step d: wrow[k - d]
   const float* irow = ir + ty * nt + tx + (D - 1);   // 1/e_r of centre u - d: irow[-d]
 
@@ -99,11 +104,9 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
 #pragma unroll
         for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
       const float c = (num * lb.inv) * irow[-d];
-      if (row_ok) {
-        if (u < W) cost_ref[d * plane + rowoff + u] = c;
-        const int x = u - d;
-        if (cost_tar && x >= 0 && x < W) cost_tar[d * plane + rowoff + x] = c;
-      }
+      const int64_t pd = d * plane;
+      if (ref_ok) (cost_ref + pd)[toff] = c;
+      if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) (cost_tar + (pd - d))[toff] = c;
     }
   }
 }
