@@ -1,0 +1,210 @@
+// The aggregation tile of agg_tile.hpp with the cost tiles brought into LDS by
+// direct global-to-LDS loads (global_load_lds_dwordx4), two disparity tiles ahead.
+// Same weights, same fp16 split of the same floats, same MFMA sequence per patch,
+// so it produces the same aggregated floats as agg_tile.
+//
+// Register staging holds only one tile in flight, and at the aggregation's rate a
+// disparity tile's loads take longer than its MFMAs; these loads need no registers,
+// so three buffers rotate in LDS:
+//     raw[2]   fp32 cost tiles as loaded (16 B per 4-column chunk, item order)
+//     hi / lo  fp16 planes of the tile the MFMAs read
+//     out      the transposed output tile
+// Iteration t:
+//     MFMAs(t) -> barrier -> output(t), wait for tile t+1's loads, convert
+//     raw(t+1) -> hi / lo -> barrier -> sink(t), issue tile t+3's loads into the
+//     raw buffer just converted
+// so the loads of tiles t+2 and t+3 are in flight during tile t+1's MFMAs.
+//
+// The loads are issued with inline assembly and waited for by hand: the waits are
+// "at most n vector-memory operations outstanding", where n is the number of loads
+// this wave issues per tile, so everything older (the previous tile's loads and the
+// sink's stores) has completed.  Loads complete in order, and every wave issues the
+// same number of loads for every tile: lanes whose chunk has no data (rows outside
+// the image, disparities >= D) load a valid address anyway and are masked when
+// converting; lanes past the item list are masked identically for every tile.
+// Border chunks load the in-row chunk [Xc, Xc + 3], Xc = clamp(X, 0, W - 4), and
+// the conversion picks their columns from it.  Needs W >= 4.
+#pragma once
+
+#include "agg_tile.hpp"
+
+namespace rsv {
+
+template <int A>
+__host__ __device__ constexpr size_t agg_tile_dma_lds_bytes() {
+  using G = AggGeo<A, 16>;
+  return sizeof(float) * (16 * G::OST + G::RAW + G::SKN) + 2 /*raw*/ * 16 * G::NCH * 16 /*B per chunk*/ +
+         2 /*hi,lo*/ * 16 * G::PLANE * sizeof(_Float16);
+}
+
+// One 16-byte-per-lane global-to-LDS load: lane l's 16 bytes at src go to LDS byte
+// address lds_wave + 16 l (lds_wave is the wave's destination base, uniform).
+__device__ __forceinline__ void lds_dma16(const float* src, uint32_t lds_wave) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_wave)
+               : "memory", "m0");
+}
+
+// s_waitcnt vmcnt(n); the memory clobber keeps LDS reads of the loaded data after it.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// LDS byte address of a pointer into the workgroup's LDS.
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+  typedef const __attribute__((address_space(3))) char* lds_ptr;
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr)p));
+}
+
+template <int A, typename GuideAt, typename Sink>
+__device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int H, int W, int D,
+                                             const BilateralK& bk, int by, int bx, GuideAt guide_at,
+                                             Sink& sink, unsigned char* smem) {
+  using G = AggGeo<A, 16>;
+  constexpr int NT = G::NT;                      // 1024
+  constexpr int NITEM = 16 * G::NCH;             // (disparity, chunk) items per tile
+  constexpr int SPT = (NITEM + NT - 1) / NT;     // items per thread
+  static_assert(SPT <= 3, "wait counts below assume at most 3 loads per wave and tile");
+  float* out = reinterpret_cast<float*>(smem);
+  float* gt = out + 16 * G::OST;
+  float* skt = gt + G::RAW;
+  float* raw0 = skt + G::SKN;                    // 16 B aligned: all sizes above are multiples of 4
+  float* raw1 = raw0 + 4 * NITEM;
+  _Float16* hi = reinterpret_cast<_Float16*>(raw1 + 4 * NITEM);
+  _Float16* lo = hi + 16 * G::PLANE;
+  const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
+  const int64_t plane = static_cast<int64_t>(H) * W;
+  const int x0 = bx - A - G::PAD;
+
+  for (int i = tid; i < G::RAW; i += NT) {
+    const int r = i / G::TC, c = i - r * G::TC;
+    const int Y = by - A + r, X = x0 + c;
+    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_at(Y, X) : INFINITY;
+  }
+  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
+    const int a = i / G::SKC, b = i - a * G::SKC;
+    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
+    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
+  }
+
+  // Item q of this thread: chunk k (4 columns of one row) of disparity dd.
+  // meta = dd | in-image column mask << 4 | (X - Xc + 3) << 8; eoff = element offset
+  // of the loaded chunk [Xc, Xc + 3] from the tile's first plane (0 for rows outside).
+  int eoff[SPT], ldso[SPT];
+  unsigned meta[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int it = tid + q * NT;
+    const int dd = it / G::NCH, k = it - dd * G::NCH;
+    const int row = k / G::CPR, c4 = 4 * (k - row * G::CPR);
+    const int Y = by - A + row, X = x0 + c4;
+    const bool yok = it < NITEM && Y >= 0 && Y < H;
+    unsigned m = 0;
+    if (yok)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) m |= (X + e >= 0 && X + e < W) ? (1u << e) : 0u;
+    const int Xc = X < 0 ? 0 : (X > W - 4 ? W - 4 : X);
+    // every in-image column of the chunk lies in [Xc, Xc + 3], so |X - Xc| <= 3 when
+    // m != 0; chunks wholly outside keep shift 0
+    const int sh = m ? X - Xc : 0;
+    meta[q] = static_cast<unsigned>(dd) | (m << 4) | (static_cast<unsigned>(sh + 3) << 8);
+    eoff[q] = yok ? dd * static_cast<int>(plane) + Y * W + Xc : 0;
+    ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
+  }
+  // loads this wave issues per tile (items with at least one lane in the list)
+  const int nq = __builtin_amdgcn_readfirstlane((NITEM - 64 * wave + NT - 1) / NT);
+
+  auto issue = [&](int t, float* raw) {
+    const float* base = cost + static_cast<int64_t>(16 * t) * plane;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (q * NT + 64 * wave < NITEM) {  // uniform per wave
+        const int d = 16 * t + static_cast<int>(meta[q] & 15u);
+        const bool ok = (meta[q] >> 4 & 15u) != 0 && d < D;
+        const float* src = ok ? base + eoff[q] : cost;  // a valid address either way
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_address(raw + 4 * (q * NT + 64 * wave)));
+        if (tid + q * NT < NITEM) lds_dma16(src, dst);
+      }
+    }
+  };
+  // every wave: at most nq loads outstanding, i.e. all but the newest tile's loads done
+  auto wait_older = [&]() {
+    if (nq >= 3)
+      wait_vm<3>();
+    else if (nq == 2)
+      wait_vm<2>();
+    else
+      wait_vm<1>();
+  };
+  auto convert = [&](int t, const float* raw) {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (ldso[q] < 0) continue;
+      const int it = tid + q * NT;
+      float4_t v = *reinterpret_cast<const float4_t*>(raw + 4 * it);
+      const unsigned m = (16 * t + static_cast<int>(meta[q] & 15u) < D) ? (meta[q] >> 4 & 15u) : 0u;
+      const int sh = static_cast<int>(meta[q] >> 8) - 3;  // column X + e is loaded element e + sh
+      if (m != 0xFu || sh != 0) {
+        float4_t w = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int s = e + sh;
+          float x = 0.f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (s == j) x = v[j];
+          w[e] = (m >> e & 1u) ? x : 0.f;
+        }
+        v = w;
+      }
+      half4_t h, l;
+      split4(v, h, l);
+      *reinterpret_cast<half4_t*>(hi + ldso[q]) = h;
+      *reinterpret_cast<half4_t*>(lo + ldso[q]) = l;
+    }
+  };
+
+  const int ndt = (D + 15) >> 4;
+  issue(0, raw0);
+  if (ndt > 1) {
+    issue(1, raw1);
+    wait_older();
+  } else {
+    wait_vm<0>();
+  }
+  convert(0, raw0);
+  __syncthreads();  // hi / lo of tile 0 ready; raw0 is free
+  if (ndt > 2) issue(2, raw0);
+
+  PatchPos pp;
+  half8_t whi[G::KS], wlo[G::KS];
+  pp = PatchPos{wave >> 2, wave & 3};
+  const int i16 = lane & 15;
+  const bool pin = by + 4 * pp.pr + (i16 >> 2) < H && bx + 4 * pp.pc + (i16 & 3) < W;
+  const float4_t iz = patch_weights<A, 16>(whi, wlo, pp, lane, pin, gt, skt, bk.kr);
+
+  for (int t = 0; t < ndt; ++t) {
+    const float4_t acc = patch_mfma<A, 16>(whi, wlo, hi, lo, pp, lane);
+    float4_t vals;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) vals[e] = acc[e] * iz[e];
+    __syncthreads();  // hi / lo of tile t and the output tile (sink t - 1) are free
+    *reinterpret_cast<float4_t*>(out + (lane & 15) * G::OST + (4 * pp.pr + (lane >> 4)) * 16 + 4 * pp.pc) =
+        vals;
+    if (t + 1 < ndt) {
+      // tile t+1's loads were issued two iterations ago, tile t+2's one ago
+      if (t + 2 < ndt)
+        wait_older();
+      else
+        wait_vm<0>();
+      convert(t + 1, (t + 1) & 1 ? raw1 : raw0);
+    }
+    __syncthreads();  // output t and hi / lo of tile t+1 ready
+    sink(t, static_cast<const float*>(out));
+    if (t + 3 < ndt) issue(t + 3, (t + 1) & 1 ? raw1 : raw0);
+  }
+  wait_vm<0>();  // nothing may be in flight into LDS when the block's LDS is reused
+}
+
+}  // namespace rsv

@@ -5,7 +5,7 @@
 // banded weight matrix, run on the matrix cores (agg_tile.hpp, aggregate_mfma.hpp).
 // Each block owns a kAggTileRows x 16 output tile and writes its aggregated values
 // plane by plane, one 16-disparity tile at a time.
-#include "agg_tile.hpp"
+#include "agg_tile_dma.hpp"
 
 namespace rsv {
 
@@ -69,9 +69,52 @@ __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
   agg_tile<A, TY>(cost, H, W, D, bk, by, bx, guide_at, sink, smem);
 }
 
+// The same tile with its cost tiles loaded straight into LDS two disparity tiles
+// ahead (agg_tile_dma.hpp): used when its buffers fit one CU's LDS (rho <= 5) and
+// W >= 4.
+template <int A, typename TG>
+__global__ __launch_bounds__(1024) void aggregate_dma_kernel(
+    const float* __restrict__ cost, const TG* __restrict__ guide, int64_t gpitch, int H, int W,
+    int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
+  auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
+  VolumeSink<16> sink{agg, H, W, D, by, bx, vec4};
+  agg_tile_dma<A>(cost, H, W, D, bk, by, bx, guide_at, sink, smem);
+}
+
+template <int A>
+constexpr bool agg_dma_fits() {
+  return agg_tile_dma_lds_bytes<A>() <= 160 * 1024;
+}
+
+template <int A, typename TG>
+int launch_agg_dma(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
+                   hipStream_t st) {
+  const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
+  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+  const bool vec4 = (g.width % 4) == 0 && aligned(agg, 16);
+  const size_t lds = agg_tile_dma_lds_bytes<A>();
+  auto kern = aggregate_dma_kernel<A, TG>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RSV_E_HIP;
+  }
+  kern<<<dim3(tiles), dim3(1024), lds, st>>>(cost, static_cast<const TG*>(g.data), g.pitch, g.height,
+                                             g.width, p->D, bk, vec4, agg);
+  return check_launch();
+}
+
 template <int A, typename TG>
 int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
                hipStream_t st) {
+  if constexpr (agg_dma_fits<A>()) {
+    if (g.width >= 4) return launch_agg_dma<A, TG>(cost, g, p, agg, st);
+  }
   constexpr int TY = kAggTileRows;
   const int tiles = ((g.width + 15) / 16) * ((g.height + TY - 1) / TY);
   const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);

@@ -26,7 +26,9 @@ SMALL = [
     (9, 9, 5, 4, 6, 17, "u8", 0.0),
     (10, 20, 512, 3, 2, 18, "u8", 0.0),        # the largest D the library accepts
     (12, 40, 300, 4, 3, 19, "f32", 0.002),
-    (5, 2100, 6, 1, 1, 20, "u8", 0.0),          # selection walks three 1024-column chunks
+    (5, 2100, 6, 1, 1, 20, "u8", 0.0),          # a long ragged row
+    (13, 5, 6, 1, 2, 21, "u8", 0.0),            # narrowest widths: every aggregation chunk
+    (11, 7, 9, 3, 5, 22, "f32", 0.0),           # is a border chunk
 ]
 
 
