@@ -47,17 +47,6 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   const int64_t plane = static_cast<int64_t>(H) * W;
   const int x0 = bx - A - G::PAD;  // image column of tile column 0 (even)
 
-  for (int i = tid; i < G::RAW; i += NT) {
-    const int r = i / G::TC, c = i - r * G::TC;
-    const int Y = by - A + r, X = x0 + c;
-    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_at(Y, X) : INFINITY;
-  }
-  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
-    const int a = i / G::SKC, b = i - a * G::SKC;
-    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
-    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
-  }
-
   // Item q of this thread: disparity dd of the tile, chunk k = 4 columns of one row.
   // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * H * W +
   // Y * W + X, the element offset from the tile's first disparity plane (32-bit for
@@ -118,6 +107,17 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   };
 
   fetch(0);
+  // the guide and spatial tables are staged while tile 0 loads
+  for (int i = tid; i < G::RAW; i += NT) {
+    const int r = i / G::TC, c = i - r * G::TC;
+    const int Y = by - A + r, X = x0 + c;
+    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_scaled(guide_at(Y, X), bk) : INFINITY;
+  }
+  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
+    const int a = i / G::SKC, b = i - a * G::SKC;
+    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
+    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
+  }
   store(0);
   __syncthreads();
   fetch(1);  // in flight while the weights are computed
@@ -131,7 +131,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
     pp[k] = PatchPos{patch >> 2, patch & 3};
     const int i = lane & 15;
     const bool pin = by + 4 * pp[k].pr + (i >> 2) < H && bx + 4 * pp[k].pc + (i & 3) < W;
-    iz[k] = patch_weights<A, TY>(whi[k], wlo[k], pp[k], lane, pin, gt, skt, bk.kr);
+    iz[k] = patch_weights<A, TY>(whi[k], wlo[k], pp[k], lane, pin, gt, skt);
   }
 
   const int ndt = (D + 15) >> 4;

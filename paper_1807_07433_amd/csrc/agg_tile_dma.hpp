@@ -77,17 +77,6 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   const int64_t plane = static_cast<int64_t>(H) * W;
   const int x0 = bx - A - G::PAD;
 
-  for (int i = tid; i < G::RAW; i += NT) {
-    const int r = i / G::TC, c = i - r * G::TC;
-    const int Y = by - A + r, X = x0 + c;
-    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_at(Y, X) : INFINITY;
-  }
-  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
-    const int a = i / G::SKC, b = i - a * G::SKC;
-    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
-    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
-  }
-
   // Item q of this thread: chunk k (4 columns of one row) of disparity dd.
   // meta = dd | in-image column mask << 4 | (X - Xc + 3) << 8; eoff = element offset
   // of the loaded chunk [Xc, Xc + 3] from the tile's first plane (0 for rows outside).
@@ -167,12 +156,23 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
 
   const int ndt = (D + 15) >> 4;
   issue(0, raw0);
-  if (ndt > 1) {
-    issue(1, raw1);
-    wait_older();
-  } else {
-    wait_vm<0>();
+  if (ndt > 1) issue(1, raw1);
+  // The guide and spatial tables are staged while the first tiles load (the wait
+  // for the guide loads may also wait for those tiles).
+  for (int i = tid; i < G::RAW; i += NT) {
+    const int r = i / G::TC, c = i - r * G::TC;
+    const int Y = by - A + r, X = x0 + c;
+    gt[i] = (Y >= 0 && Y < H && X >= 0 && X < W) ? guide_scaled(guide_at(Y, X), bk) : INFINITY;
   }
+  for (int i = tid; i < G::SKR * G::SKC; i += NT) {
+    const int a = i / G::SKC, b = i - a * G::SKC;
+    const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
+    skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
+  }
+  if (ndt > 1)
+    wait_older();
+  else
+    wait_vm<0>();
   convert(0, raw0);
   __syncthreads();  // hi / lo of tile 0 ready; raw0 is free
   if (ndt > 2) issue(2, raw0);
@@ -182,7 +182,7 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   pp = PatchPos{wave >> 2, wave & 3};
   const int i16 = lane & 15;
   const bool pin = by + 4 * pp.pr + (i16 >> 2) < H && bx + 4 * pp.pc + (i16 & 3) < W;
-  const float4_t iz = patch_weights<A, 16>(whi, wlo, pp, lane, pin, gt, skt, bk.kr);
+  const float4_t iz = patch_weights<A, 16>(whi, wlo, pp, lane, pin, gt, skt);
 
   for (int t = 0; t < ndt; ++t) {
     const float4_t acc = patch_mfma<A, 16>(whi, wlo, hi, lo, pp, lane);

@@ -63,10 +63,17 @@ constexpr int64_t kAggMaxPixels = int64_t(1) << 26;
 
 // fp16 hi / lo split of two floats (x = hi + lo to about 2^-22 relative), as packed
 // conversions.
+// fp16 hi / lo split of two floats: hi = x rounded to fp16, lo = (x - hi) rounded,
+// x = hi + lo to about 2^-22 relative.  The residuals are taken by mixed-precision
+// FMAs straight from the packed halves (-hi * 1 + x, exact since hi is x rounded to
+// 11 bits), which saves the two conversions back to fp32.
 __device__ __forceinline__ void split2(float a, float b, half2_t& hi, half2_t& lo) {
   const float2_t x = {a, b};
   hi = __builtin_convertvector(x, half2_t);
-  lo = __builtin_convertvector(x - __builtin_convertvector(hi, float2_t), half2_t);
+  float ra, rb;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(ra) : "v"(hi), "v"(a));
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(rb) : "v"(hi), "v"(b));
+  lo = __builtin_convertvector(float2_t{ra, rb}, half2_t);
 }
 
 struct PatchPos {
@@ -74,13 +81,12 @@ struct PatchPos {
 };
 
 // Weights w of one lane for one patch, split into hi / lo fp16 parts (w <= 1).
-// gt: guide tile (+inf outside the image); skt: spatial exponent table (+inf
-// outside the window).  Returns 1 / Z for the four output pixels this lane
+// gt: guide tile of scaled guides h = g sr (+inf outside the image); skt: spatial
+// exponent table (+inf outside the window).  Returns 1 / Z for the four output pixels this lane
 // receives from the MFMA (patch row g = lane / 16, columns 0..3).
 template <int A, int TY>
 __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, const PatchPos& pp,
-                                                  int lane, bool pin, const float* gt, const float* skt,
-                                                  float kr) {
+                                                  int lane, bool pin, const float* gt, const float* skt) {
   using G = AggGeo<A, TY>;
   const int i = lane & 15, g = lane >> 4;
   const int py = i >> 2, px = i & 3;
@@ -93,7 +99,7 @@ __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, co
     float wt[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      wt[e] = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e], kr);
+      wt[e] = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e]);
       z += wt[e];
     }
 #pragma unroll
