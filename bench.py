@@ -99,7 +99,9 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 matrix, published
 def kernel_rooflines(stage_ms, W, H, D, prm):
     """Per-launch algorithmic work / average launch time for the three volume kernels,
     each against the resource that bounds it at these sizes:
-      cost_volume: HBM, writes C_ref and C_tar, 8 B per entry (image reads are O(1/D));
+      cost_volume: HBM, writes the joint volume that holds C_ref and C_tar (the
+                   identity after Eq. 5): every distinct cost value once, 4 B each,
+                   H (D W + D (D - 1) / 2) values (image reads are O(1/D));
       aggregate:   FP32 arithmetic, 2m + 2 FLOP per entry (m = (2 rho + 1)^2 weighted
                    terms, weight sum and normalisation), against the FP32 vector peak.
                    Also reported: its HBM rate (8 B per entry) and the matrix-core work
@@ -109,11 +111,12 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
     n = W * H * D
     m = (2 * prm.agg_radius + 1) ** 2
     out = {}
-    for k, key in (("cost_volume", "cost_volume"), ("select_subpixel", "select_subpixel")):
-        ms = stage_ms[key]
-        gbs = 8 * n / (ms * 1e-3) / 1e9
+    joint_bytes = 4 * H * (D * W + D * (D - 1) // 2)
+    for k, nbytes in (("cost_volume", joint_bytes), ("select_subpixel", 8 * n)):
+        ms = stage_ms[k]
+        gbs = nbytes / (ms * 1e-3) / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": 8 * n, "ms": round(ms, 5)}
+                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes, "ms": round(ms, 5)}
     ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
     flops = (2 * m + 2) * n
     tf = flops / (ms * 1e-3) / 1e12
@@ -163,7 +166,10 @@ def bench_batch(a, rsv, torch):
     # 64 sequential plain calls, buffers sized for the largest pair and reused
     f32 = dict(dtype=torch.float32, device=dev)
     mx = max(c.pair.left.size * c.params.D for c in cases)
-    vols = [torch.empty(mx, **f32) for _ in range(4)]
+    vols = [torch.empty(mx, **f32) for _ in range(2)]
+    mxj = max(c.params.D * c.pair.left.shape[0] * rsv.joint_row_stride(c.pair.left.shape[1], c.params.D)
+              for c in cases)
+    jbuf = torch.empty(mxj, **f32)
     outs = []
     for c in cases:
         H, W = c.pair.left.shape
@@ -174,13 +180,15 @@ def bench_batch(a, rsv, torch):
                               "disp_sub": torch.empty((H, W), **f32),
                               "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)},
                          dfin=torch.empty((H, W), **f32), xyz=torch.empty((H, W, 3), **f32),
-                         v=[t[:D * H * W].view(D, H, W) for t in vols]))
+                         v=[t[:D * H * W].view(D, H, W) for t in vols],
+                         j=jbuf[:D * H * rsv.joint_row_stride(W, D)].view(D, H, rsv.joint_row_stride(W, D))))
 
     def plain_all():
         for (left, right, plane, cam, D), c, o in zip(pairs, cases, outs):
-            cr, ct, ar, at = o["v"]
+            ar, at = o["v"]
             rsv.warp(right, plane, out=o["wp"])
-            rsv.cost_volume(left, o["wp"], c.params, out_ref=cr, out_tar=ct)
+            rsv.cost_volume_joint(left, o["wp"], c.params, out=o["j"])
+            cr, ct = rsv.joint_views(o["j"], left.shape[1])
             rsv.aggregate(cr, left, c.params, out=ar)
             rsv.aggregate(ct, o["wp"], c.params, out=at)
             rsv.select_subpixel(ar, at, c.params, out=o["sel"])
@@ -315,8 +323,8 @@ def main():
 
     f32 = dict(dtype=torch.float32, device=dev)
     wp = torch.empty((H, W), **f32)
-    cref = torch.empty((D, H, W), **f32)
-    ctar = torch.empty((D, H, W), **f32)
+    joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
+    cref, ctar = rsv.joint_views(joint, W)  # both cost volumes, views of the joint one
     aref = torch.empty((D, H, W), **f32)
     atar = torch.empty((D, H, W), **f32)
     sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
@@ -335,7 +343,7 @@ def main():
         mark(0)
         rsv.warp(R, case.plane, out=wp)
         mark(1)
-        rsv.cost_volume(L, wp, prm, out_ref=cref, out_tar=ctar)
+        rsv.cost_volume_joint(L, wp, prm, out=joint)
         mark(2)
         rsv.aggregate(cref, L, prm, out=aref)
         mark(3)

@@ -116,6 +116,22 @@ int rsv_warp(rsv_image right, rsv_plane plane, float* warped, void* stream);
 int rsv_cost_volume(rsv_image left, const float* warped, const rsv_params* p,
                     float* cost_ref, float* cost_tar, void* stream);
 
+/* Both ZNCC volumes of rsv_cost_volume as one joint volume (Sec. II-B.1, Eq. 3-5 and
+ * the identity stated after Eq. 5):
+ *   joint[d][v][u] = zncc(B_left(u, v), B_warped(u - d, v)),  u = 0 .. W + D - 2
+ * (left blocks clamp-to-edge past column W - 1).  The two volumes are its views:
+ *   cost_ref[d][v][u] = joint[d*(H*row_stride)     + v*row_stride + u]
+ *   cost_tar[d][v][x] = joint[d*(H*row_stride + 1) + v*row_stride + x]   (= joint[d][v][x + d])
+ * bit for bit equal to rsv_cost_volume's outputs, with 4 B written per entry instead
+ * of 8.  Aggregate the views with rsv_aggregate_strided.
+ *   joint       out, float32 [D][H][row_stride]; columns >= W + D - 1 are not written
+ *   row_stride  elements, >= W + D - 1; a multiple of 64 keeps every 64-centre row
+ *               segment 256-byte aligned
+ * Errors: as rsv_cost_volume; RSV_E_SHAPE also for row_stride < W + D - 1 or
+ * H*row_stride > 2^31 - 1. */
+int rsv_cost_volume_joint(rsv_image left, const float* warped, const rsv_params* p,
+                          float* joint, int64_t row_stride, void* stream);
+
 /* Bilateral cost aggregation (Sec. II-B.2, Eq. 8-10) of one volume:
  *   agg[d][v][u] = sum_q w(p, q) cost[d][q] / sum_q w(p, q),  p = (u, v),
  *   w = exp(-|q - p|^2 / gamma_d^2) * exp(-((g(q) - g(p)) / 255)^2 / gamma_r^2)
@@ -127,6 +143,16 @@ int rsv_cost_volume(rsv_image left, const float* warped, const rsv_params* p,
  * (agg_radius, gammas), RSV_E_ALIGN. */
 int rsv_aggregate(const float* cost, rsv_image guide, const rsv_params* p, float* agg,
                   void* stream);
+
+/* rsv_aggregate on a strided view of a cost volume (Sec. II-B.2, Eq. 8-10):
+ *   cost(d, v, u) = cost[d*plane_stride + v*row_stride + u],  d < D, v < H, u < W,
+ * e.g. the reference and target views of rsv_cost_volume_joint's volume.  Only the
+ * view's elements are read; views may overlap themselves (the target view does).
+ *   agg    out, float32 [D][H][W] dense, outside the view
+ * Errors: as rsv_aggregate; RSV_E_SHAPE also for row_stride < W, plane_stride < 1,
+ * plane_stride > 2^26 or (H-1)*row_stride + W > 2^26. */
+int rsv_aggregate_strided(const float* cost, int64_t plane_stride, int64_t row_stride,
+                          rsv_image guide, const rsv_params* p, float* agg, void* stream);
 
 /* Disparity selection and refinement (Sec. II-B.3 and II-B.4):
  *   disp_ref = argmax_d agg_ref, disp_tar = argmax_d agg_tar (ties -> lowest d);

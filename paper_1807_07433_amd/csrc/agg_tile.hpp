@@ -25,10 +25,12 @@ __host__ __device__ inline size_t agg_tile_lds_bytes() {
          (2 /*hi,lo*/ * 2 /*buffers*/ * 16 * G::PLANE + 4 * 64 /*dummy*/) * sizeof(_Float16);
 }
 
+// cost(d, Y, X) = cost[d * cps + Y * crs + X] (a dense volume: cps = H W, crs = W).
 // guide_at(Y, X): guide intensity at in-image (Y, X).
 // Values for disparities >= D or pixels outside the image are meaningless.
 template <int A, int TY, typename GuideAt, typename Sink>
-__device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, int W, int D,
+__device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t cps, int crs, int H,
+                                         int W, int D,
                                          const BilateralK& bk, int by, int bx, GuideAt guide_at,
                                          Sink& sink, unsigned char* smem) {
   using G = AggGeo<A, TY>;
@@ -44,14 +46,13 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   _Float16* lo = hi + 2 * 16 * G::PLANE;
   const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
   _Float16* dummy = lo + 2 * 16 * G::PLANE + 4 * lane;  // store target of surplus items
-  const int64_t plane = static_cast<int64_t>(H) * W;
   const int x0 = bx - A - G::PAD;  // image column of tile column 0 (even)
 
   // Item q of this thread: disparity dd of the tile, chunk k = 4 columns of one row.
-  // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * H * W +
-  // Y * W + X, the element offset from the tile's first disparity plane (32-bit for
-  // H * W <= 2^26), added to a per-tile uniform base.
-  const bool pairs_aligned = (W & 1) == 0;  // then every chunk start is 8-byte aligned
+  // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * cps +
+  // Y * crs + X, the element offset from the tile's first disparity plane (32-bit
+  // for cps and H * crs <= 2^26), added to a per-tile uniform base.
+  const bool pairs_aligned = ((cps | crs) & 1) == 0;  // then every chunk start is 8-byte aligned
   int eoff[SPT], ldso[SPT];
   unsigned meta[SPT];
 #pragma unroll
@@ -65,7 +66,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
 #pragma unroll
       for (int e = 0; e < 4; ++e) m |= (X + e >= 0 && X + e < W) ? (1u << e) : 0u;
     meta[q] = static_cast<unsigned>(dd) | (m << 4);
-    eoff[q] = m ? dd * static_cast<int>(plane) + Y * W + X : 0;
+    eoff[q] = m ? dd * static_cast<int>(cps) + Y * crs + X : 0;
     ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
   float4_t pre[SPT];
@@ -74,7 +75,7 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int H, 
   // register is then written on one path while the other path's loads are pending.
   // Past the last disparity tile nothing is loaded.
   auto fetch = [&](int t) {
-    const float* base = cost + static_cast<int64_t>(16 * t) * plane;
+    const float* base = cost + static_cast<int64_t>(16 * t) * cps;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       float4_t v = {0.f, 0.f, 0.f, 0.f};

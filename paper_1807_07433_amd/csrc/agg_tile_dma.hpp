@@ -23,7 +23,8 @@
 // the image, disparities >= D) load a valid address anyway and are masked when
 // converting; lanes past the item list are masked identically for every tile.
 // Border chunks load the in-row chunk [Xc, Xc + 3], Xc = clamp(X, 0, W - 4), and
-// the conversion picks their columns from it.  Needs W >= 4.
+// the conversion picks their columns from it.  Needs W >= 4.  The cost volume is
+// read as cost[d * cps + Y * crs + X], as in agg_tile.
 #pragma once
 
 #include "agg_tile.hpp"
@@ -58,7 +59,8 @@ __device__ __forceinline__ uint32_t lds_address(const void* p) {
 }
 
 template <int A, typename GuideAt, typename Sink>
-__device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int H, int W, int D,
+__device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int64_t cps, int crs, int H,
+                                             int W, int D,
                                              const BilateralK& bk, int by, int bx, GuideAt guide_at,
                                              Sink& sink, unsigned char* smem) {
   using G = AggGeo<A, 16>;
@@ -74,7 +76,6 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   _Float16* hi = reinterpret_cast<_Float16*>(raw1 + 4 * NITEM);
   _Float16* lo = hi + 16 * G::PLANE;
   const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
-  const int64_t plane = static_cast<int64_t>(H) * W;
   const int x0 = bx - A - G::PAD;
 
   // Item q of this thread: chunk k (4 columns of one row) of disparity dd.
@@ -98,14 +99,14 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
     // m != 0; chunks wholly outside keep shift 0
     const int sh = m ? X - Xc : 0;
     meta[q] = static_cast<unsigned>(dd) | (m << 4) | (static_cast<unsigned>(sh + 3) << 8);
-    eoff[q] = yok ? dd * static_cast<int>(plane) + Y * W + Xc : 0;
+    eoff[q] = yok ? dd * static_cast<int>(cps) + Y * crs + Xc : 0;
     ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
   // loads this wave issues per tile (items with at least one lane in the list)
   const int nq = __builtin_amdgcn_readfirstlane((NITEM - 64 * wave + NT - 1) / NT);
 
   auto issue = [&](int t, float* raw) {
-    const float* base = cost + static_cast<int64_t>(16 * t) * plane;
+    const float* base = cost + static_cast<int64_t>(16 * t) * cps;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       if (q * NT + 64 * wave < NITEM) {  // uniform per wave

@@ -58,15 +58,15 @@ struct VolumeSink {
 
 template <int A, int TY, typename TG>
 __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
-    const float* __restrict__ cost, const TG* __restrict__ guide, int64_t gpitch, int H, int W,
-    int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
+    const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
+    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + TY - 1) / TY;
   const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * TY, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
   VolumeSink<TY> sink{agg, H, W, D, by, bx, vec4};
-  agg_tile<A, TY>(cost, H, W, D, bk, by, bx, guide_at, sink, smem);
+  agg_tile<A, TY>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
 }
 
 // The same tile with its cost tiles loaded straight into LDS two disparity tiles
@@ -74,15 +74,15 @@ __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
 // W >= 4.
 template <int A, typename TG>
 __global__ __launch_bounds__(1024) void aggregate_dma_kernel(
-    const float* __restrict__ cost, const TG* __restrict__ guide, int64_t gpitch, int H, int W,
-    int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
+    const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
+    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
   const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
   VolumeSink<16> sink{agg, H, W, D, by, bx, vec4};
-  agg_tile_dma<A>(cost, H, W, D, bk, by, bx, guide_at, sink, smem);
+  agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
 }
 
 template <int A>
@@ -91,8 +91,8 @@ constexpr bool agg_dma_fits() {
 }
 
 template <int A, typename TG>
-int launch_agg_dma(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
-                   hipStream_t st) {
+int launch_agg_dma(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                   float* agg, hipStream_t st) {
   const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
   const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
   const bool vec4 = (g.width % 4) == 0 && aligned(agg, 16);
@@ -104,16 +104,16 @@ int launch_agg_dma(const float* cost, const rsv_image& g, const rsv_params* p, f
     set_hip_error(e);
     return RSV_E_HIP;
   }
-  kern<<<dim3(tiles), dim3(1024), lds, st>>>(cost, static_cast<const TG*>(g.data), g.pitch, g.height,
-                                             g.width, p->D, bk, vec4, agg);
+  kern<<<dim3(tiles), dim3(1024), lds, st>>>(cost, cps, crs, static_cast<const TG*>(g.data), g.pitch,
+                                             g.height, g.width, p->D, bk, vec4, agg);
   return check_launch();
 }
 
 template <int A, typename TG>
-int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
-               hipStream_t st) {
+int launch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+               float* agg, hipStream_t st) {
   if constexpr (agg_dma_fits<A>()) {
-    if (g.width >= 4) return launch_agg_dma<A, TG>(cost, g, p, agg, st);
+    if (g.width >= 4) return launch_agg_dma<A, TG>(cost, cps, crs, g, p, agg, st);
   }
   constexpr int TY = kAggTileRows;
   const int tiles = ((g.width + 15) / 16) * ((g.height + TY - 1) / TY);
@@ -127,23 +127,39 @@ int launch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float
     set_hip_error(e);
     return RSV_E_HIP;
   }
-  kern<<<dim3(tiles), dim3(64 * TY), lds, st>>>(cost, static_cast<const TG*>(g.data), g.pitch,
-                                                          g.height, g.width, p->D, bk, vec4, agg);
+  kern<<<dim3(tiles), dim3(64 * TY), lds, st>>>(cost, cps, crs, static_cast<const TG*>(g.data), g.pitch,
+                                                g.height, g.width, p->D, bk, vec4, agg);
   return check_launch();
 }
 
 template <typename TG>
-int dispatch_agg(const float* cost, const rsv_image& g, const rsv_params* p, float* agg,
-                 hipStream_t st) {
+int dispatch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                 float* agg, hipStream_t st) {
   switch (p->agg_radius) {
-    case 1: return launch_agg<1, TG>(cost, g, p, agg, st);
-    case 2: return launch_agg<2, TG>(cost, g, p, agg, st);
-    case 3: return launch_agg<3, TG>(cost, g, p, agg, st);
-    case 4: return launch_agg<4, TG>(cost, g, p, agg, st);
-    case 5: return launch_agg<5, TG>(cost, g, p, agg, st);
-    case 6: return launch_agg<6, TG>(cost, g, p, agg, st);
+    case 1: return launch_agg<1, TG>(cost, cps, crs, g, p, agg, st);
+    case 2: return launch_agg<2, TG>(cost, cps, crs, g, p, agg, st);
+    case 3: return launch_agg<3, TG>(cost, cps, crs, g, p, agg, st);
+    case 4: return launch_agg<4, TG>(cost, cps, crs, g, p, agg, st);
+    case 5: return launch_agg<5, TG>(cost, cps, crs, g, p, agg, st);
+    case 6: return launch_agg<6, TG>(cost, cps, crs, g, p, agg, st);
     default: return RSV_E_PARAM;
   }
+}
+
+int run_agg(const float* cost, int64_t cps, int64_t crs, const rsv_image& guide, const rsv_params* p,
+            float* agg, void* stream) {
+  if (int s = validate_image(guide)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (!cost || !agg) return RSV_E_NULL;
+  if (!aligned(cost, 4) || !aligned(agg, 4)) return RSV_E_ALIGN;
+  if (cost == agg) return RSV_E_PARAM;
+  // element offsets inside 16 disparity planes stay below 2^31
+  if (crs < guide.width || cps < 1 || cps > kAggMaxPixels ||
+      static_cast<int64_t>(guide.height - 1) * crs + guide.width > kAggMaxPixels)
+    return RSV_E_SHAPE;
+  hipStream_t st = as_stream(stream);
+  if (guide.dtype == RSV_U8) return dispatch_agg<uint8_t>(cost, cps, static_cast<int>(crs), guide, p, agg, st);
+  return dispatch_agg<float>(cost, cps, static_cast<int>(crs), guide, p, agg, st);
 }
 
 }  // namespace rsv
@@ -152,12 +168,10 @@ extern "C" int rsv_aggregate(const float* cost, rsv_image guide, const rsv_param
                              void* stream) {
   using namespace rsv;
   if (int s = validate_image(guide)) return s;
-  if (int s = validate_agg_params(p)) return s;
-  if (static_cast<int64_t>(guide.height) * guide.width > kAggMaxPixels) return RSV_E_SHAPE;
-  if (!cost || !agg) return RSV_E_NULL;
-  if (!aligned(cost, 4) || !aligned(agg, 4)) return RSV_E_ALIGN;
-  if (cost == agg) return RSV_E_PARAM;
-  hipStream_t st = as_stream(stream);
-  if (guide.dtype == RSV_U8) return dispatch_agg<uint8_t>(cost, guide, p, agg, st);
-  return dispatch_agg<float>(cost, guide, p, agg, st);
+  return run_agg(cost, static_cast<int64_t>(guide.height) * guide.width, guide.width, guide, p, agg, stream);
+}
+
+extern "C" int rsv_aggregate_strided(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                     rsv_image guide, const rsv_params* p, float* agg, void* stream) {
+  return rsv::run_agg(cost, plane_stride, row_stride, guide, p, agg, stream);
 }

@@ -210,8 +210,8 @@ __device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, f
   float* ctar = uniform(pd->ctar);
   for (int ct = c0; ct < last; ++ct) {
     if (ct > c0) __syncthreads();  // LDS is reused by the next tile
-    cost_tile<R, kBandRows>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0, cref,
-                            ctar, cwork);
+    cost_tile<R, kBandRows>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
+                            cost_out_dual(cref, ctar, H, W), cwork);
   }
 }
 
@@ -240,7 +240,7 @@ __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsig
   auto guide = [&](int Y, int X) {
     return full ? pixel(left, lpitch, Y, X) : warped[static_cast<int64_t>(Y) * W + X];
   };
-  agg_tile<A, 16>(cost, H, W, D, args.bk, by, bx, guide, sink, smem);
+  agg_tile<A, 16>(cost, static_cast<int64_t>(H) * W, W, H, W, D, args.bk, by, bx, guide, sink, smem);
   // each thread < 256 wrote its own pixel's state in the last sink call
   if (threadIdx.x < 256) {
     const int q = threadIdx.x;

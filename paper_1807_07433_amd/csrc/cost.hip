@@ -1,4 +1,5 @@
-// rsv_cost_volume: ZNCC reference and target cost volumes (Sec. II-B.1, Eq. 3-5).
+// rsv_cost_volume, rsv_cost_volume_joint: ZNCC reference and target cost volumes
+// (Sec. II-B.1, Eq. 3-5), as two dense volumes or as one joint volume.
 // One block per tile of 64 left-block centres x 4 rows (cost_tile.hpp); the grid
 // spans centres u = 0 .. W + D - 2 so that the target volume is filled where
 // x + d leaves the image.  LDS holds the left tile (64 + 2R columns), the warped
@@ -12,16 +13,16 @@ constexpr int kCostTH = 4;
 template <int R, typename TL>
 __global__ __launch_bounds__(kCostTW* kCostTH, R <= 3 ? 4 : 1) void cost_volume_kernel(
     const TL* __restrict__ left, int64_t lpitch, const float* __restrict__ warped, int H, int W,
-    int D, float sigma_min, float* __restrict__ cost_ref, float* __restrict__ cost_tar) {
+    int D, float sigma_min, CostOut out) {
   extern __shared__ float smem[];
   auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
   cost_tile<R, kCostTH>(left, lpitch, warped_at, H, W, D, sigma_min, blockIdx.x * kCostTW,
-                        blockIdx.y * kCostTH, cost_ref, cost_tar, smem);
+                        blockIdx.y * kCostTH, out, smem);
 }
 
 template <int R, typename TL>
-int launch_cost(const rsv_image& left, const float* warped, const rsv_params* p, float* cref,
-                float* ctar, hipStream_t st) {
+int launch_cost(const rsv_image& left, const float* warped, const rsv_params* p, const CostOut& out,
+                hipStream_t st) {
   const int H = left.height, W = left.width, D = p->D;
   const size_t lds = sizeof(float) * cost_tile_lds_floats(D, R, kCostTH);
   const dim3 block(kCostTW * kCostTH);
@@ -37,20 +38,27 @@ int launch_cost(const rsv_image& left, const float* warped, const rsv_params* p,
     }
   }
   kern<<<grid, block, lds, st>>>(static_cast<const TL*>(left.data), left.pitch, warped, H, W, D,
-                                 p->sigma_min, cref, ctar);
+                                 p->sigma_min, out);
   return check_launch();
 }
 
 template <typename TL>
-int dispatch_cost(const rsv_image& left, const float* warped, const rsv_params* p, float* cref,
-                  float* ctar, hipStream_t st) {
+int dispatch_cost(const rsv_image& left, const float* warped, const rsv_params* p, const CostOut& out,
+                  hipStream_t st) {
   switch (p->block_radius) {
-    case 1: return launch_cost<1, TL>(left, warped, p, cref, ctar, st);
-    case 2: return launch_cost<2, TL>(left, warped, p, cref, ctar, st);
-    case 3: return launch_cost<3, TL>(left, warped, p, cref, ctar, st);
-    case 4: return launch_cost<4, TL>(left, warped, p, cref, ctar, st);
+    case 1: return launch_cost<1, TL>(left, warped, p, out, st);
+    case 2: return launch_cost<2, TL>(left, warped, p, out, st);
+    case 3: return launch_cost<3, TL>(left, warped, p, out, st);
+    case 4: return launch_cost<4, TL>(left, warped, p, out, st);
     default: return RSV_E_PARAM;
   }
+}
+
+int run_cost(const rsv_image& left, const float* warped, const rsv_params* p, const CostOut& out,
+             void* stream) {
+  hipStream_t st = as_stream(stream);
+  if (left.dtype == RSV_U8) return dispatch_cost<uint8_t>(left, warped, p, out, st);
+  return dispatch_cost<float>(left, warped, p, out, st);
 }
 
 }  // namespace rsv
@@ -65,7 +73,20 @@ extern "C" int rsv_cost_volume(rsv_image left, const float* warped, const rsv_pa
     return RSV_E_ALIGN;
   const int K = 2 * p->block_radius + 1;
   if (left.height < K || left.width < K) return RSV_E_SHAPE;
-  hipStream_t st = as_stream(stream);
-  if (left.dtype == RSV_U8) return dispatch_cost<uint8_t>(left, warped, p, cost_ref, cost_tar, st);
-  return dispatch_cost<float>(left, warped, p, cost_ref, cost_tar, st);
+  return run_cost(left, warped, p, cost_out_dual(cost_ref, cost_tar, left.height, left.width), stream);
+}
+
+extern "C" int rsv_cost_volume_joint(rsv_image left, const float* warped, const rsv_params* p,
+                                     float* joint, int64_t row_stride, void* stream) {
+  using namespace rsv;
+  if (int s = validate_image(left)) return s;
+  if (int s = validate_cost_params(p)) return s;
+  if (!warped || !joint) return RSV_E_NULL;
+  if (!aligned(warped, 4) || !aligned(joint, 4)) return RSV_E_ALIGN;
+  const int K = 2 * p->block_radius + 1;
+  if (left.height < K || left.width < K) return RSV_E_SHAPE;
+  if (row_stride < static_cast<int64_t>(left.width) + p->D - 1 ||
+      static_cast<int64_t>(left.height) * row_stride > INT32_MAX)
+    return RSV_E_SHAPE;
+  return run_cost(left, warped, p, cost_out_joint(joint, row_stride, left.height, left.width, p->D), stream);
 }

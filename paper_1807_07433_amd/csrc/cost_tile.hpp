@@ -6,8 +6,10 @@
 // and walks d = 0 .. D-1: its centred left block stays in registers and the target
 // block slides one column left per step through a register ring, so a step reads
 // one new column of 2R+1 values from LDS and spends (2R+1)^2 FMAs.  The value for
-// (u, v, d) is written to cost_ref[d][v][u] (u < W) and cost_tar[d][v][u - d]
-// (0 <= u - d < W): the identity stated after Eq. 5.
+// (u, v, d) is written to ref[d * ref_plane + v * ref_row + u] (u < ref_cols) and,
+// for the dual layout, to tar[d][v][u - d] (0 <= u - d < W): the identity stated
+// after Eq. 5.  The joint layout (ref_cols = W + D - 1, no tar) holds both volumes
+// in one: the target one is its view with plane stride ref_plane + 1.
 // The warped tile is stored minus 128 (kWarpShift): the centred left values sum to
 // zero, so the dot product is unchanged while its FP32 terms stay small.  Its row
 // stride is a compile-time constant so the column reads use immediate offsets.
@@ -21,6 +23,25 @@ constexpr int kCostTW = 64;
 constexpr int kWarpStride = kCostTW + RSV_MAX_D - 1 + 2 * RSV_MAX_BLOCK_RADIUS + 1;  // 584
 constexpr float kWarpShift = 128.f;
 
+// Where a cost tile writes its values.
+struct CostOut {
+  float* ref;         // ref[d * ref_plane + v * ref_row + u] for u < ref_cols
+  int64_t ref_plane;
+  uint32_t ref_row;
+  int ref_cols;
+  float* tar;         // dense [D][H][W] target volume, or null
+};
+
+// Both volumes dense [D][H][W] (tar may be null).
+__host__ __device__ inline CostOut cost_out_dual(float* ref, float* tar, int H, int W) {
+  return CostOut{ref, static_cast<int64_t>(H) * W, static_cast<uint32_t>(W), W, tar};
+}
+
+// The joint volume [D][H][row] over centres u = 0 .. W + D - 2.
+__host__ __device__ inline CostOut cost_out_joint(float* joint, int64_t row, int H, int W, int D) {
+  return CostOut{joint, H * row, static_cast<uint32_t>(row), W + D - 1, nullptr};
+}
+
 __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
   const size_t rows = TH + 2 * R;
   return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1);
@@ -30,8 +51,7 @@ __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
 template <int R, int TH, typename TL, typename WarpAt>
 __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t lpitch, WarpAt warped_at,
                                           int H, int W, int D, float sigma_min, int u0, int v0,
-                                          float* __restrict__ cost_ref, float* __restrict__ cost_tar,
-                                          float* smem) {
+                                          const CostOut& out, float* smem) {
   constexpr int K = 2 * R + 1;
   constexpr int NT = kCostTW * TH;
   const int tid = opaque_tid();
@@ -70,10 +90,14 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   const bool row_ok = v < H;
   const int64_t plane = static_cast<int64_t>(H) * W;
   // Stores go to a per-disparity base that is the same for the whole workgroup plus
-  // this thread's element offset v * W + u, for both volumes: C_tar's base is moved
-  // back by d so that column u - d has the same offset.
+  // this thread's element offset: v * ref_row + u, and v * W + u for C_tar, whose
+  // base is moved back by d so that column u - d has that offset.
+  float* const cost_ref = out.ref;
+  float* const cost_tar = out.tar;
+  const int64_t ref_plane = out.ref_plane;
+  const uint32_t roff = static_cast<uint32_t>(v) * out.ref_row + static_cast<uint32_t>(u);
   const uint32_t toff = static_cast<uint32_t>(v) * static_cast<uint32_t>(W) + static_cast<uint32_t>(u);
-  const bool ref_ok = row_ok && u < W;
+  const bool ref_ok = row_ok && u < out.ref_cols;
   const bool tar_ok = row_ok && cost_tar != nullptr;
   const float* wrow = wt + ty * wtw + tx + (D - 1);  // window column k at step d: wrow[k - d]
   const float* irow = ir + ty * nt + tx + (D - 1);   // 1/e_r of centre u - d: irow[-d]
@@ -105,7 +129,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
         for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
       const float c = (num * lb.inv) * irow[-d];
       const int64_t pd = d * plane;
-      if (ref_ok) (cost_ref + pd)[toff] = c;
+      if (ref_ok) (cost_ref + d * ref_plane)[roff] = c;
       if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) (cost_tar + (pd - d))[toff] = c;
     }
   }

@@ -103,18 +103,60 @@ def cost_volume(left: torch.Tensor, warped: torch.Tensor, params, want_tar: bool
     return cref, ctar
 
 
+def joint_row_stride(W: int, D: int) -> int:
+    """Row stride of the joint volume: W + D - 1 rounded up to a multiple of 64."""
+    return (W + D - 1 + 63) // 64 * 64
+
+
+def cost_volume_joint(left: torch.Tensor, warped: torch.Tensor, params,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """Both cost volumes as one [D][H][row_stride] volume (rsv_cost_volume_joint);
+    joint_views gives the reference and target volumes as views of it."""
+    lib = load()
+    H, W = left.shape
+    D = int(params.D)
+    _contig(warped, "warped", torch.float32, (H, W))
+    shp = (D, H, joint_row_stride(W, D))
+    out = out if out is not None else torch.empty(shp, dtype=torch.float32, device=left.device)
+    _contig(out, "joint", torch.float32, shp)
+    p = _params(params)
+    check(lib.rsv_cost_volume_joint(image(left, "left"), warped.data_ptr(), C.byref(p), out.data_ptr(),
+                                    shp[2], _stream(left.device)), "rsv_cost_volume_joint")
+    return out
+
+
+def joint_views(joint: torch.Tensor, W: int) -> tuple[torch.Tensor, torch.Tensor]:
+    """(cost_ref, cost_tar) [D][H][W] as strided views of a joint volume: the target
+    volume's plane stride is one element longer (cost_tar[d][v][x] = joint[d][v][x + d])."""
+    D, H, rs = joint.shape
+    if not joint.is_contiguous() or rs < W + D - 1:
+        raise ValueError("joint must be a contiguous [D][H][row_stride >= W + D - 1] volume")
+    ref = joint.as_strided((D, H, W), (H * rs, rs, 1))
+    tar = joint.as_strided((D, H, W), (H * rs + 1, rs, 1))
+    return ref, tar
+
+
 def aggregate(cost: torch.Tensor, guide: torch.Tensor, params,
               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Bilateral aggregation of a [D][H][W] volume: contiguous (rsv_aggregate) or any
+    view with unit column stride, e.g. from joint_views (rsv_aggregate_strided)."""
     lib = load()
     D, H, W = cost.shape
-    _contig(cost, "cost", torch.float32, (int(params.D), H, W))
+    _dev(cost, "cost", torch.float32, (int(params.D), H, W))
     if tuple(guide.shape) != (H, W):
         raise ValueError("guide must match the volume's H, W")
-    out = out if out is not None else torch.empty_like(cost)
+    out = out if out is not None else torch.empty((D, H, W), dtype=torch.float32, device=cost.device)
     _contig(out, "agg", torch.float32, (D, H, W))
     p = _params(params)
-    check(lib.rsv_aggregate(cost.data_ptr(), image(guide, "guide"), C.byref(p), out.data_ptr(),
-                            _stream(cost.device)), "rsv_aggregate")
+    if cost.is_contiguous():
+        check(lib.rsv_aggregate(cost.data_ptr(), image(guide, "guide"), C.byref(p), out.data_ptr(),
+                                _stream(cost.device)), "rsv_aggregate")
+    else:
+        if cost.stride(2) != 1:
+            raise ValueError("cost views need unit column stride")
+        check(lib.rsv_aggregate_strided(cost.data_ptr(), cost.stride(0), cost.stride(1),
+                                        image(guide, "guide"), C.byref(p), out.data_ptr(),
+                                        _stream(cost.device)), "rsv_aggregate_strided")
     return out
 
 
@@ -212,12 +254,16 @@ def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_re
 
 
 def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
-                want_top2: bool = False) -> dict:
+                want_top2: bool = False, joint: bool = True) -> dict:
     """The plain path, one C-ABI call per stage on the current stream (Fig. 1):
     warp -> both cost volumes -> aggregation of each -> WTA + L-R + subpixel ->
-    post-processing + 3-D points."""
+    post-processing + 3-D points.  With joint=True the two cost volumes are views of
+    one joint volume (rsv_cost_volume_joint); otherwise two dense volumes."""
     wp = warp(right, plane)
-    cref, ctar = cost_volume(left, wp, params)
+    if joint:
+        cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
+    else:
+        cref, ctar = cost_volume(left, wp, params)
     aref = aggregate(cref, left, params)
     atar = aggregate(ctar, wp, params)
     sel = select_subpixel(aref, atar, params, want_top2=want_top2)
@@ -228,5 +274,6 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
     return out
 
 
-__all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "aggregate", "select_subpixel",
+__all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
+           "joint_row_stride", "aggregate", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "cost_adjoint", "image", "load"]

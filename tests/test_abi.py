@@ -143,3 +143,26 @@ def test_adjoint_validation(lib):
     a = list(args)
     a[6] = FAKE + 4                  # grad_plane must be 8-byte aligned
     assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -5
+
+
+@pytest.mark.parametrize("stride", [48 + 32 - 2, 2**31 // 32 + 1])
+def test_cost_joint_validation(lib, stride):
+    """row_stride must hold W + D - 1 centres and H * row_stride must fit 31 bits."""
+    p = _params()
+    assert lib.rsv_cost_volume_joint(_img(), FAKE, C.byref(p), FAKE, stride, None) == -2
+    assert lib.rsv_cost_volume_joint(_img(), FAKE, C.byref(p), None, 128, None) == -1
+    assert lib.rsv_cost_volume_joint(_img(), FAKE, C.byref(_params(D=0)), FAKE, 128, None) == -2
+    assert lib.rsv_cost_volume_joint(_img(), FAKE, C.byref(p), FAKE + 2, 128, None) == -5
+
+
+@pytest.mark.parametrize("ps,rs,status", [
+    (32 * 48, 47, -2),            # row stride shorter than a row
+    (0, 48, -2),                  # no plane stride
+    (2**26 + 1, 48, -2),          # planes too far apart for 32-bit tile offsets
+    (32 * 48, 2**22, -2)])        # rows too far apart
+def test_aggregate_strided_validation(lib, ps, rs, status):
+    p = _params()
+    assert lib.rsv_aggregate_strided(FAKE, ps, rs, _img(), C.byref(p), FAKE + 4096, None) == status
+    assert lib.rsv_aggregate_strided(None, 32 * 48, 48, _img(), C.byref(p), FAKE, None) == -1
+    assert lib.rsv_aggregate_strided(FAKE, 32 * 48, 48, _img(), C.byref(_params(agg_radius=9)),
+                                     FAKE + 4096, None) == -3

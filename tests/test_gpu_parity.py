@@ -103,12 +103,20 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
     for d in range(min(D, W)):  # identity stated after Eq. 5, bit for bit
         assert np.array_equal(ctar_n[d, :, :W - d], cref_n[d, :, d:])
 
+    _say("  rsv_cost_volume_joint")
+    joint = rsv.cost_volume_joint(L, wp, prm)
+    jref, jtar = rsv.joint_views(joint, W)
+    assert torch.equal(jref, cref) and torch.equal(jtar, ctar), "joint views != dual volumes"
+
     _say("  rsv_aggregate x2")
     aref = rsv.aggregate(cref, L, prm)
     atar = rsv.aggregate(ctar, wp, prm)
     e1 = P.check_close("agg_ref", P.to_np(aref), ref["agg_ref"], P.AGG_TOL)
     e2 = P.check_close("agg_tar", P.to_np(atar), ref["agg_tar"], P.AGG_TOL)
     _say(f"  max |agg err| ref {e1:.2e} tar {e2:.2e}")
+    _say("  rsv_aggregate_strided x2 (joint views)")
+    assert torch.equal(rsv.aggregate(jref, L, prm), aref), "strided ref aggregation"
+    assert torch.equal(rsv.aggregate(jtar, wp, prm), atar), "strided tar aggregation"
     # aggregation alone, fed the oracle's volume
     aref_iso = rsv.aggregate(_gpu(ref["cost_ref"].astype(np.float32)), L, prm)
     P.check_close("agg_ref(oracle cost)", P.to_np(aref_iso), ref["agg_ref"], P.AGG_TOL)
@@ -226,9 +234,16 @@ def _sampled_full(rsv, case, n_cost, n_agg, n_pix, seed):
     gi = (torch.from_numpy(d).cuda(), torch.from_numpy(v).cuda(), torch.from_numpy(u).cuda())
     P.check_close("cost_ref", P.to_np(out["cost_ref"][gi]), cl(u, v, d), P.COST_TOL)
     P.check_close("cost_tar", P.to_np(out["cost_tar"][gi]), cr(u, v, d), P.COST_TOL)
+    _say("  joint volume views == the two dense volumes (every entry)")
+    cref, ctar = rsv.cost_volume(L, out["warped"], prm)
+    assert torch.equal(cref, out["cost_ref"]) and torch.equal(ctar, out["cost_tar"])
     _say("  cost identity (every entry)")
     for dd in range(D):
-        assert torch.equal(out["cost_tar"][dd, :, :W - dd], out["cost_ref"][dd, :, dd:])
+        assert torch.equal(ctar[dd, :, :W - dd], cref[dd, :, dd:])
+    _say("  dense-volume aggregation == strided (every entry)")
+    assert torch.equal(rsv.aggregate(cref, L, prm), out["agg_ref"])
+    assert torch.equal(rsv.aggregate(ctar, out["warped"], prm), out["agg_tar"])
+    del cref, ctar
 
     _say(f"  aggregated volumes ({n_agg} sampled entries each)")
     u = rng.integers(0, W, n_agg)

@@ -18,14 +18,17 @@ def test_eq13_reproduces_the_printed_throughput():
 
 
 def test_kernel_roofline_units():
-    """Cost and select against HBM at 8 B per entry; the aggregation against the FP32
-    arithmetic peak at 2m + 2 FLOP per entry, m = (2 rho + 1)^2."""
+    """Cost against HBM at 4 B per distinct cost value (the joint volume), select at
+    8 B per entry; the aggregation against the FP32 arithmetic peak at 2m + 2 FLOP per
+    entry, m = (2 rho + 1)^2."""
     class P:
         agg_radius = 5
     st = {"cost_volume": 0.1, "aggregate_ref": 0.2, "aggregate_tar": 0.2, "select_subpixel": 0.05}
     k = bench.kernel_rooflines(st, 1280, 720, 64, P)
     n = 1280 * 720 * 64
-    assert k["cost_volume"]["bound"] == "hbm" and k["cost_volume"]["bytes_per_launch"] == 8 * n
+    # every (d, v) row holds W reference values plus d target values past the right edge
+    distinct = sum(720 * (1280 + d) for d in range(64))
+    assert k["cost_volume"]["bound"] == "hbm" and k["cost_volume"]["bytes_per_launch"] == 4 * distinct
     assert abs(k["select_subpixel"]["achieved"] - 8 * n / 0.05e-3 / 1e9) < 1.0
     agg = k["aggregate"]
     assert agg["bound"] == "alu" and agg["flops_per_launch"] == (2 * 121 + 2) * n
