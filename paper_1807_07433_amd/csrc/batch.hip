@@ -222,6 +222,21 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args
   for_each_item(args, 0, s_item, [&](int it) { batch_cost_item<R>(args, args.items[it], cwork); });
 }
 
+// The same work with one workgroup per cost item (no queue): without the item loop
+// the kernel keeps the plain cost kernel's register budget and occupancy.
+template <int R>
+__global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) float cwork[];
+  const int4 w = args.items[blockIdx.x];  // one tile: {pair, 1 << 8, band, column tile}
+  const PairDev* pd = uniform(args.pairs + uniform(w.x));
+  const float* warped = uniform(pd->warped);
+  const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
+  auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
+  cost_tile<R, kBandRows>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
+                          uniform(w.w) * kCostTW, uniform(w.z) * kBandRows,
+                          cost_out_dual(uniform(pd->cref), uniform(pd->ctar), H, W), cwork);
+}
+
 template <int A>
 __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsigned char* smem) {
   // the item and the pair's fields are the same for the whole workgroup
@@ -312,20 +327,21 @@ namespace rsv {
 namespace {
 
 template <int R>
-const void* cost_kernel_ptr() {
-  return reinterpret_cast<const void*>(batch_cost_kernel<R>);
+const void* cost_kernel_ptr(bool grid) {
+  return grid ? reinterpret_cast<const void*>(batch_cost_grid_kernel<R>)
+              : reinterpret_cast<const void*>(batch_cost_kernel<R>);
 }
 template <int A>
 const void* agg_kernel_ptr() {
   return reinterpret_cast<const void*>(batch_agg_kernel<A>);
 }
 
-const void* pick_cost_kernel(int R) {
+const void* pick_cost_kernel(int R, bool grid) {
   switch (R) {
-    case 1: return cost_kernel_ptr<1>();
-    case 2: return cost_kernel_ptr<2>();
-    case 3: return cost_kernel_ptr<3>();
-    case 4: return cost_kernel_ptr<4>();
+    case 1: return cost_kernel_ptr<1>(grid);
+    case 2: return cost_kernel_ptr<2>(grid);
+    case 3: return cost_kernel_ptr<3>(grid);
+    case 4: return cost_kernel_ptr<4>(grid);
     default: return nullptr;
   }
 }
@@ -385,7 +401,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   rsv_tuning tn;
   rsv_tuning_default(&tn);
   if (tuning) tn = *tuning;
-  if (tn.cost_tiles_per_item < 1 || tn.cost_tiles_per_item > 16 || tn.cost_blocks_per_cu < 0 ||
+  if (tn.cost_tiles_per_item < 1 || tn.cost_tiles_per_item > 16 || tn.cost_blocks_per_cu < -1 ||
       tn.agg_blocks_per_cu < 0)
     return RSV_E_PARAM;
   int maxD = 0;
@@ -443,11 +459,13 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   }
   // agg items: per pair, the reference tiles then the target tiles, row-major, so
   // each queue's stretch of the list is a band of neighbouring tiles of one volume
+  // (one tile per cost item when the cost kernel runs one workgroup per item)
+  const int cost_tiles = tn.cost_blocks_per_cu < 0 ? 1 : tn.cost_tiles_per_item;
   for (int i : order) {
     const PairDev& P = pd[i];
     for (int b = 0; b < P.nbands; ++b)
-      for (int ct = 0; ct < P.ncol_tiles; ct += tn.cost_tiles_per_item)
-        cost_items.push_back(make_int4(i, kItemCost | (tn.cost_tiles_per_item << 8), b, ct));
+      for (int ct = 0; ct < P.ncol_tiles; ct += cost_tiles)
+        cost_items.push_back(make_int4(i, kItemCost | (cost_tiles << 8), b, ct));
     for (int kind : {kItemAggRef, kItemAggTar})
       for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
         for (int tx = 0; tx < P.tiles_x; ++tx) agg_items.push_back(make_int4(i, kind, ty, tx));
@@ -519,7 +537,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       hipSuccess)
     return fail(e);
 
-  const void* ck = pick_cost_kernel(R);
+  const bool cost_grid_mode = tn.cost_blocks_per_cu < 0;
+  const void* ck = pick_cost_kernel(R, cost_grid_mode);
   size_t agg_lds = 0;
   const void* ak = pick_agg_kernel(A, &agg_lds);
   if (!ck || !ak) {
@@ -546,7 +565,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   }
   const int cpc = tn.cost_blocks_per_cu > 0 ? std::min(tn.cost_blocks_per_cu, cost_fit) : cost_fit;
   const int apc = tn.agg_blocks_per_cu > 0 ? std::min(tn.agg_blocks_per_cu, agg_fit) : agg_fit;
-  plan->cost_grid = std::min(cus * cpc, std::max(1, plan->n_cost_items));
+  plan->cost_grid = cost_grid_mode ? std::max(1, plan->n_cost_items)
+                                   : std::min(cus * cpc, std::max(1, plan->n_cost_items));
   plan->agg_grid = std::min(cus * apc, std::max(1, plan->n_agg_items));
 
   const int* d_qbeg = reinterpret_cast<const int*>(base + o_qbeg);
@@ -639,7 +659,8 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
   int status = RSV_OK;
   for (int lf = 0; lf <= 1; ++lf)
     for (int tiles : {1, 2, 4})
-      for (int cpc : {0, 2}) {
+      for (int cpc : {-1, 0, 2}) {
+        if (cpc < 0 && tiles != 1) continue;  // one tile per item there
         rsv_tuning t;
         rsv_tuning_default(&t);
         t.largest_first = lf;

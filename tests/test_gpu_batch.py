@@ -132,7 +132,7 @@ def test_batch_realistic_sizes_equal_plain(rsv_gpu):
     plan.close()
 
 
-@pytest.mark.parametrize("largest_first,tiles,cpc", [(0, 1, 0), (1, 4, 2), (1, 3, 1)])
+@pytest.mark.parametrize("largest_first,tiles,cpc", [(0, 1, 0), (1, 4, 2), (1, 3, 1), (1, 4, -1)])
 def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc):
     rsv = rsv_gpu
     from paper_1807_07433_amd.batch import BatchPlan, default_tuning
