@@ -213,24 +213,26 @@ typedef struct rsv_batch_plan rsv_batch_plan;
 
 void rsv_tuning_default(rsv_tuning* t);
 
-/* Builds a plan for the whole batch: device workspace for every pair's two cost
- * volumes and selection state, two work lists, and a hipGraph of
- *   [reset queue counters] -> [persistent cost kernel] -> [persistent aggregate +
- *   winner-take-all kernel] -> [per-pixel tail].
- * The persistent kernels pull work items from atomic counters.  The cost kernel
- * runs warp + ZNCC (the arithmetic of rsv_warp and rsv_cost_volume).  The second
- * runs bilateral aggregation (that of rsv_aggregate) with winner-take-all fused in,
- * writing no aggregated volume.  The tail runs the left-right check, Eq. 12,
- * post-processing and triangulation (those of rsv_select_subpixel and
- * rsv_triangulate).  Every output equals the plain path's bit for bit.
+/* Builds a plan for the whole batch: device workspace for every pair's warped image,
+ * joint cost volume (rsv_cost_volume_joint's layout, row stride W + D - 1 rounded up
+ * to 64) and selection state, two work lists, and a hipGraph of
+ *   [reset queue counters] -> [warp every pair] -> [cost kernel] -> [persistent
+ *   aggregate + winner-take-all kernel] -> [per-pixel tail].
+ * The cost kernel runs ZNCC (the arithmetic of rsv_cost_volume_joint), persistent
+ * over a work queue or one workgroup per tile (see rsv_tuning).  The second kernel
+ * pulls work items from atomic counters and runs bilateral aggregation (that of
+ * rsv_aggregate on the two views) with winner-take-all fused in, writing no
+ * aggregated volume.  The tail runs the left-right check, Eq. 12, post-processing
+ * and triangulation (those of rsv_select_subpixel and rsv_triangulate).  Every
+ * output equals the plain path's bit for bit.
  *   pairs, n   the batch (host array, copied)
  *   p          shared parameters (block_radius, agg_radius, gammas, lr_threshold,
  *              sigma_min); p->D is ignored
  *   tuning     launch shape, or NULL for the defaults (see rsv_autotune)
  *   out        host pointer receiving the plan
- * The plan owns its device memory (about 8 * sum(H*W*D) bytes) and graph.
- * Errors: RSV_E_NULL, RSV_E_SHAPE, RSV_E_PARAM, RSV_E_DTYPE (pairs must be uint8),
- * RSV_E_NOMEM, RSV_E_HIP. */
+ * The plan owns its device memory (about 4 * sum(H*(W+D)*D) bytes) and graph.
+ * Errors: RSV_E_NULL, RSV_E_SHAPE (also H * row stride + 1 > 2^26 for a pair),
+ * RSV_E_PARAM, RSV_E_DTYPE (pairs must be uint8), RSV_E_NOMEM, RSV_E_HIP. */
 int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
                           const rsv_tuning* tuning, rsv_batch_plan** out);
 

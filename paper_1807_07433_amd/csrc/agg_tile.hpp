@@ -52,7 +52,6 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
   // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * cps +
   // Y * crs + X, the element offset from the tile's first disparity plane (32-bit
   // for cps and H * crs <= 2^26), added to a per-tile uniform base.
-  const bool pairs_aligned = ((cps | crs) & 1) == 0;  // then every chunk start is 8-byte aligned
   int eoff[SPT], ldso[SPT];
   unsigned meta[SPT];
 #pragma unroll
@@ -73,7 +72,9 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
   // The load form is chosen per wave (uniform branch): whole 4-column chunks as one
   // 16-byte load when every lane has one, else per-column predicated loads.  No
   // register is then written on one path while the other path's loads are pending.
-  // Past the last disparity tile nothing is loaded.
+  // A chunk start is only 4-byte aligned (odd strides, e.g. a target view of a joint
+  // volume, or odd widths); gfx950 serves such 16-byte global loads.  Past the last
+  // disparity tile nothing is loaded.
   auto fetch = [&](int t) {
     const float* base = cost + static_cast<int64_t>(16 * t) * cps;
 #pragma unroll
@@ -82,10 +83,9 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
       const unsigned m = meta[q] >> 4;
       const unsigned mm = 16 * t + static_cast<int>(meta[q] & 15u) < D ? m : 0u;
       const float* p = base + eoff[q];  // column X of the chunk (X may be < 0 at the border)
-      if (__all(mm == 0xFu && pairs_aligned)) {
-        const float2 a = *reinterpret_cast<const float2*>(p);
-        const float2 b = *reinterpret_cast<const float2*>(p + 2);
-        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+      if (__all(mm == 0xFu)) {
+        const float4_a4 a = *reinterpret_cast<const float4_a4*>(p);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)

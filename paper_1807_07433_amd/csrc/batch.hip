@@ -51,8 +51,8 @@ struct PairDev {
   rsv_plane plane;
   rsv_camera cam;
   float* warped;
-  float* cref;
-  float* ctar;
+  float* joint;  // joint cost volume [D][H][jrow]: C_L and C_R are its views
+  int64_t jrow;
   int32_t* ref_arg;
   float* ref_best;
   float* ref_am;
@@ -206,12 +206,11 @@ __device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, f
   const int v0 = uniform(w.z) * kBandRows;
   const uint8_t* left = uniform(pd->left);
   const int64_t lpitch = uniform(pd->lpitch);
-  float* cref = uniform(pd->cref);
-  float* ctar = uniform(pd->ctar);
+  const CostOut out = cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D);
   for (int ct = c0; ct < last; ++ct) {
     if (ct > c0) __syncthreads();  // LDS is reused by the next tile
     cost_tile<R, kBandRows>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
-                            cost_out_dual(cref, ctar, H, W), cwork);
+                            out, cwork);
   }
 }
 
@@ -234,7 +233,7 @@ __global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_
   auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
   cost_tile<R, kBandRows>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
                           uniform(w.w) * kCostTW, uniform(w.z) * kBandRows,
-                          cost_out_dual(uniform(pd->cref), uniform(pd->ctar), H, W), cwork);
+                          cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D), cwork);
 }
 
 template <int A>
@@ -251,11 +250,14 @@ __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsig
   const uint8_t* left = uniform(pd->left);
   const float* warped = uniform(pd->warped);
   const int64_t lpitch = uniform(pd->lpitch);
-  const float* cost = uniform(full ? pd->cref : pd->ctar);
+  // the joint volume's reference view, or its target view (plane stride one longer)
+  const float* cost = uniform(pd->joint);
+  const int jrow = static_cast<int>(uniform(pd->jrow));
+  const int64_t cps = static_cast<int64_t>(H) * jrow + (full ? 0 : 1);
   auto guide = [&](int Y, int X) {
     return full ? pixel(left, lpitch, Y, X) : warped[static_cast<int64_t>(Y) * W + X];
   };
-  agg_tile<A, 16>(cost, static_cast<int64_t>(H) * W, W, H, W, D, args.bk, by, bx, guide, sink, smem);
+  agg_tile<A, 16>(cost, cps, jrow, H, W, D, args.bk, by, bx, guide, sink, smem);
   // each thread < 256 wrote its own pixel's state in the last sink call
   if (threadIdx.x < 256) {
     const int q = threadIdx.x;
@@ -368,8 +370,9 @@ int validate_pair(const rsv_pair_desc& pd, int K) {
   if (pd.left.dtype != RSV_U8 || pd.right.dtype != RSV_U8) return RSV_E_DTYPE;
   if (pd.left.height != pd.right.height || pd.left.width != pd.right.width) return RSV_E_SHAPE;
   if (pd.left.height < K || pd.left.width < K) return RSV_E_SHAPE;
-  if (static_cast<int64_t>(pd.left.height) * pd.left.width > kAggMaxPixels) return RSV_E_SHAPE;
   if (pd.D < 1 || pd.D > RSV_MAX_D) return RSV_E_SHAPE;
+  // the joint cost volume's target view: plane stride H * row stride + 1 (32-bit tile offsets)
+  if (pd.left.height * joint_row_stride(pd.left.width, pd.D) + 1 > kAggMaxPixels) return RSV_E_SHAPE;
   if (!pd.disp_sub || !pd.valid) return RSV_E_NULL;
   if (!(pd.camera.f > 0.0) || !(pd.camera.baseline > 0.0)) return RSV_E_PARAM;
   return RSV_OK;
@@ -425,15 +428,15 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   size_t ws_bytes = 0;
   int max_pixels = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-  std::vector<size_t> off_cref(n), off_ctar(n), off_maps(n);
+  std::vector<size_t> off_joint(n), off_maps(n);
+  std::vector<int64_t> jrows(n);
   for (int i = 0; i < n; ++i) {
     const rsv_pair_desc& q = pairs[i];
     const int H = q.left.height, W = q.left.width, D = q.D;
     const size_t N = static_cast<size_t>(H) * W;
-    off_cref[i] = ws_bytes;
-    ws_bytes = align(ws_bytes + sizeof(float) * N * D);
-    off_ctar[i] = ws_bytes;
-    ws_bytes = align(ws_bytes + sizeof(float) * N * D);
+    jrows[i] = joint_row_stride(W, D);
+    off_joint[i] = ws_bytes;
+    ws_bytes = align(ws_bytes + sizeof(float) * static_cast<size_t>(D) * H * jrows[i]);
     off_maps[i] = ws_bytes;
     ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float) * 4));  // + warped image
     max_pixels = std::max<int>(max_pixels, static_cast<int>(N));
@@ -510,8 +513,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   for (int i = 0; i < n; ++i) {
     PairDev& P = pd[i];
     const size_t N = static_cast<size_t>(P.H) * P.W;
-    P.cref = reinterpret_cast<float*>(base + o_ws + off_cref[i]);
-    P.ctar = reinterpret_cast<float*>(base + o_ws + off_ctar[i]);
+    P.joint = reinterpret_cast<float*>(base + o_ws + off_joint[i]);
+    P.jrow = jrows[i];
     unsigned char* m = base + o_ws + off_maps[i];
     P.ref_arg = reinterpret_cast<int32_t*>(m);
     P.tar_arg = P.ref_arg + N;

@@ -37,6 +37,12 @@ __host__ __device__ inline CostOut cost_out_dual(float* ref, float* tar, int H, 
   return CostOut{ref, static_cast<int64_t>(H) * W, static_cast<uint32_t>(W), W, tar};
 }
 
+// Row stride the library's own joint volumes use: W + D - 1 centres rounded up to 64,
+// so every 64-centre row segment is 256-byte aligned.
+__host__ __device__ inline int64_t joint_row_stride(int W, int D) {
+  return (static_cast<int64_t>(W) + D - 1 + 63) / 64 * 64;
+}
+
 // The joint volume [D][H][row] over centres u = 0 .. W + D - 2.
 __host__ __device__ inline CostOut cost_out_joint(float* joint, int64_t row, int H, int W, int D) {
   return CostOut{joint, H * row, static_cast<uint32_t>(row), W + D - 1, nullptr};

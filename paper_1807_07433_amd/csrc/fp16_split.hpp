@@ -12,6 +12,7 @@ typedef float float2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef float float4_a4 __attribute__((ext_vector_type(4), aligned(4)));  // 4-byte-aligned loads
 
 // The residuals x - hi are taken by mixed-precision FMAs straight from the packed
 // halves (-hi * 1 + x, exact since hi is x rounded to 11 bits), which saves the two
