@@ -44,12 +44,15 @@ struct VolumeSink {
       if (d < D && Y < H && X < W) {
         const float4_t v = *reinterpret_cast<const float4_t*>(o + dd * G::OST + row * 16 + c4);
         float* p = agg + d * (static_cast<int64_t>(H) * W) + static_cast<int64_t>(Y) * W + X;
+        // Non-temporal: the aggregated volume is read only by a later kernel, and
+        // allocating it in the caches evicts the cost volume the next aggregation
+        // still reads (with the joint volume both aggregations read the same one).
         if (vec4 && X + 3 < W) {
-          *reinterpret_cast<float4_t*>(p) = v;
+          __builtin_nontemporal_store(v, reinterpret_cast<float4_t*>(p));
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (X + e < W) p[e] = v[e];
+            if (X + e < W) __builtin_nontemporal_store(v[e], p + e);
         }
       }
     }

@@ -19,6 +19,7 @@ constexpr int kSelUnroll = 16;
 
 // Walk d = 0 .. D-1 of one pixel in both volumes (stride `plane`): loads for both
 // run ahead of the compare chains in chunks of kSelUnroll, then of 4, then singly.
+// Every value is read once, so the loads are non-temporal.
 __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const float* __restrict__ pt,
                                           int64_t plane, int D, Scan& s, int& targ) {
   bool need_next = false;
@@ -42,8 +43,8 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
     float a[kSelUnroll], b[kSelUnroll];
 #pragma unroll
     for (int i = 0; i < kSelUnroll; ++i) {
-      a[i] = pr[(d + i) * plane];
-      b[i] = pt[(d + i) * plane];
+      a[i] = __builtin_nontemporal_load(pr + (d + i) * plane);
+      b[i] = __builtin_nontemporal_load(pt + (d + i) * plane);
     }
 #pragma unroll
     for (int i = 0; i < kSelUnroll; ++i) consume(a[i], b[i], d + i);
@@ -52,13 +53,13 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
     float a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] = pr[(d + i) * plane];
-      b[i] = pt[(d + i) * plane];
+      a[i] = __builtin_nontemporal_load(pr + (d + i) * plane);
+      b[i] = __builtin_nontemporal_load(pt + (d + i) * plane);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) consume(a[i], b[i], d + i);
   }
-  for (; d < D; ++d) consume(pr[d * plane], pt[d * plane], d);
+  for (; d < D; ++d) consume(__builtin_nontemporal_load(pr + d * plane), __builtin_nontemporal_load(pt + d * plane), d);
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_scan_kernel(
