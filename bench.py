@@ -107,12 +107,13 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
                    Also reported: its HBM rate (8 B per entry) and the matrix-core work
                    it issues (3 split-fp16 MFMAs per K-step, padded window union)
                    against the fp16 matrix peak;
-      select:      HBM, reads both aggregated volumes, 8 B per entry."""
+      select:      HBM, reads the reference aggregated volume, 4 B per entry (the
+                   target volume is reduced to its argmax inside its aggregation)."""
     n = W * H * D
     m = (2 * prm.agg_radius + 1) ** 2
     out = {}
     joint_bytes = 4 * H * (D * W + D * (D - 1) // 2)
-    for k, nbytes in (("cost_volume", joint_bytes), ("select_subpixel", 8 * n)):
+    for k, nbytes in (("cost_volume", joint_bytes), ("select_subpixel", 4 * n)):
         ms = stage_ms[k]
         gbs = nbytes / (ms * 1e-3) / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -166,7 +167,7 @@ def bench_batch(a, rsv, torch):
     # 64 sequential plain calls, buffers sized for the largest pair and reused
     f32 = dict(dtype=torch.float32, device=dev)
     mx = max(c.pair.left.size * c.params.D for c in cases)
-    vols = [torch.empty(mx, **f32) for _ in range(2)]
+    vols = [torch.empty(mx, **f32)]
     mxj = max(c.params.D * c.pair.left.shape[0] * rsv.joint_row_stride(c.pair.left.shape[1], c.params.D)
               for c in cases)
     jbuf = torch.empty(mxj, **f32)
@@ -185,13 +186,13 @@ def bench_batch(a, rsv, torch):
 
     def plain_all():
         for (left, right, plane, cam, D), c, o in zip(pairs, cases, outs):
-            ar, at = o["v"]
+            ar, = o["v"]
             rsv.warp(right, plane, out=o["wp"])
             rsv.cost_volume_joint(left, o["wp"], c.params, out=o["j"])
             cr, ct = rsv.joint_views(o["j"], left.shape[1])
             rsv.aggregate(cr, left, c.params, out=ar)
-            rsv.aggregate(ct, o["wp"], c.params, out=at)
-            rsv.select_subpixel(ar, at, c.params, out=o["sel"])
+            rsv.aggregate_argmax(ct, o["wp"], c.params, out=o["sel"]["disp_tar"])
+            rsv.select_subpixel(ar, None, c.params, out=o["sel"])
             rsv.triangulate(o["sel"]["disp_sub"], o["sel"]["valid"], plane, cam, out_disp=o["dfin"],
                             out_xyz=o["xyz"])
 
@@ -326,7 +327,6 @@ def main():
     joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
     cref, ctar = rsv.joint_views(joint, W)  # both cost volumes, views of the joint one
     aref = torch.empty((D, H, W), **f32)
-    atar = torch.empty((D, H, W), **f32)
     sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_tar": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_sub": torch.empty((H, W), **f32),
@@ -347,9 +347,9 @@ def main():
         mark(2)
         rsv.aggregate(cref, L, prm, out=aref)
         mark(3)
-        rsv.aggregate(ctar, wp, prm, out=atar)
+        rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])  # the target volume only feeds its argmax
         mark(4)
-        rsv.select_subpixel(aref, atar, prm, out=sel)
+        rsv.select_subpixel(aref, None, prm, out=sel)
         mark(5)
         rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
         mark(6)

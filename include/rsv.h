@@ -154,6 +154,17 @@ int rsv_aggregate(const float* cost, rsv_image guide, const rsv_params* p, float
 int rsv_aggregate_strided(const float* cost, int64_t plane_stride, int64_t row_stride,
                           rsv_image guide, const rsv_params* p, float* agg, void* stream);
 
+/* The winner-take-all disparity of an aggregated volume that is needed for nothing
+ * else (the target volume, Sec. II-B.3): the aggregation of rsv_aggregate_strided's
+ * view, reduced over d as it is computed, without writing the volume:
+ *   disp[v][u] = argmax_d agg(d, v, u), ties -> lowest d
+ * bit for bit the disp_tar that rsv_select_subpixel computes from rsv_aggregate's
+ * volume.
+ *   disp   out, int32 [H][W] dense
+ * Errors: as rsv_aggregate_strided (RSV_E_NULL for disp). */
+int rsv_aggregate_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,
+                         rsv_image guide, const rsv_params* p, int32_t* disp, void* stream);
+
 /* Disparity selection and refinement (Sec. II-B.3 and II-B.4):
  *   disp_ref = argmax_d agg_ref, disp_tar = argmax_d agg_tar (ties -> lowest d);
  *   valid    = (u - disp_ref >= 0) && |disp_ref - disp_tar(u - disp_ref, v)| <= lr_threshold
@@ -169,6 +180,15 @@ int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t heig
                         int32_t width, const rsv_params* p, int32_t* disp_ref,
                         int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
                         void* stream);
+
+/* rsv_select_subpixel with the target disparities given (e.g. from
+ * rsv_aggregate_argmax) instead of the target volume: WTA and Eq. 12 on agg_ref,
+ * Eq. 11 against disp_tar.  Outputs equal rsv_select_subpixel's bit for bit.
+ *   disp_tar  int32 [H][W], read
+ * Errors: as rsv_select_subpixel. */
+int rsv_select_subpixel_ref(const float* agg_ref, const int32_t* disp_tar, int32_t height,
+                            int32_t width, const rsv_params* p, int32_t* disp_ref,
+                            float* disp_sub, uint8_t* valid, float* top2, void* stream);
 
 /* Post-processing (Sec. II-C) and 3-D reconstruction (Sec. II-D):
  *   disp_final = disp_sub + s(u - disp_sub, v)            (every pixel)

@@ -59,33 +59,132 @@ struct VolumeSink {
   }
 };
 
-template <int A, int TY, typename TG>
+// (b, a) <- the better of (b, a) and the quad lane selected by the DPP quad_perm
+// pattern PERM: the larger value, the lower d on ties.
+template <int PERM>
+__device__ __forceinline__ void quad_merge(float& b, int& a) {
+  const float ob = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(b), PERM, 0xF, 0xF, false));
+  const int oa = __builtin_amdgcn_mov_dpp(a, PERM, 0xF, 0xF, false);
+  if (ob > b || (ob == b && oa < a)) {
+    b = ob;
+    a = oa;
+  }
+}
+
+// agg_tile sink for a volume that is only needed through its argmax over d (the
+// target volume of Sec. II-B.3): the 16 x 16 pixels' running winner, nothing written
+// until the end; the select kernel's order (the first maximum over d).  Two forms:
+// * state null (the LDS-loaded tile): thread i covers pixel i / 4 and disparities
+//   4 (i % 4) .. + 3 of the tile: its first maximum, then the quad's (lower d on
+//   ties), then against the earlier tiles' winner (replaced only when strictly
+//   greater).  All four threads of a quad keep the same winner in registers.
+// * state in LDS (the register-staged tile, whose registers are full): thread p <
+//   256 scans pixel p's 16 values in order against the winner kept in LDS.
+struct ArgmaxSink {
+  int D;
+  float* state = nullptr;  // [2][256]: best, then arg bits
+  float best = -INFINITY;
+  int arg = 0;
+
+  __device__ __forceinline__ void operator()(int t, const float* o) {
+    using G = AggGeo<1, 16>;
+    if (state) {
+      const int p = threadIdx.x;
+      if (p >= 256) return;
+      float b = t == 0 ? -INFINITY : state[p];
+      int a = t == 0 ? 0 : __float_as_int(state[256 + p]);
+      const int n = min(16, D - 16 * t);
+      for (int dd = 0; dd < n; ++dd) {
+        const float v = o[dd * G::OST + p];
+        if ((t == 0 && dd == 0) || v > b) {
+          b = v;
+          a = 16 * t + dd;
+        }
+      }
+      state[p] = b;
+      state[256 + p] = __int_as_float(a);
+      return;
+    }
+    const int i = threadIdx.x, p = i >> 2, q = i & 3;
+    float b = -INFINITY;
+    int a = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = 16 * t + 4 * q + k;
+      const float v = o[(4 * q + k) * G::OST + p];
+      if (d < D && v > b) {
+        b = v;
+        a = d;
+      }
+    }
+    // the quad's lanes i ^ 1, then i ^ 2 (DPP quad permutations, no LDS traffic)
+    quad_merge<0xB1>(b, a);
+    quad_merge<0x4E>(b, a);
+    if (t == 0 || b > best) {
+      best = b;
+      arg = a;
+    }
+  }
+
+  // Writes the winners after the last call: one thread per in-image pixel.
+  __device__ __forceinline__ void finish(int32_t* disp, int H, int W, int by, int bx) const {
+    int p;
+    int a;
+    if (state) {
+      p = threadIdx.x;
+      if (p >= 256) return;
+      a = __float_as_int(state[256 + p]);  // written by this thread
+    } else {
+      if (threadIdx.x & 3) return;
+      p = threadIdx.x >> 2;
+      a = arg;
+    }
+    const int Y = by + (p >> 4), X = bx + (p & 15);
+    if (Y < H && X < W) disp[static_cast<int64_t>(Y) * W + X] = a;
+  }
+};
+
+// ARG: write the argmax map `disp` instead of the volume `agg`.
+template <int A, int TY, typename TG, bool ARG>
 __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
     const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
-    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
+    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg, int32_t* __restrict__ disp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + TY - 1) / TY;
   const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * TY, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
-  VolumeSink<TY> sink{agg, H, W, D, by, bx, vec4};
-  agg_tile<A, TY>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  if constexpr (ARG) {
+    static_assert(TY == 16, "the argmax sink covers 16 x 16 pixels");
+    ArgmaxSink sink{D, reinterpret_cast<float*>(smem + agg_tile_lds_bytes<A, TY>())};
+    agg_tile<A, TY>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+    sink.finish(disp, H, W, by, bx);
+  } else {
+    VolumeSink<TY> sink{agg, H, W, D, by, bx, vec4};
+    agg_tile<A, TY>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  }
 }
 
 // The same tile with its cost tiles loaded straight into LDS two disparity tiles
 // ahead (agg_tile_dma.hpp): used when its buffers fit one CU's LDS (rho <= 5) and
 // W >= 4.
-template <int A, typename TG>
+template <int A, typename TG, bool ARG>
 __global__ __launch_bounds__(1024) void aggregate_dma_kernel(
     const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
-    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg) {
+    int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg, int32_t* __restrict__ disp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
   const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
-  VolumeSink<16> sink{agg, H, W, D, by, bx, vec4};
-  agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  if constexpr (ARG) {
+    ArgmaxSink sink{D};
+    agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+    sink.finish(disp, H, W, by, bx);
+  } else {
+    VolumeSink<16> sink{agg, H, W, D, by, bx, vec4};
+    agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  }
 }
 
 template <int A>
@@ -93,14 +192,14 @@ constexpr bool agg_dma_fits() {
   return agg_tile_dma_lds_bytes<A>() <= 160 * 1024;
 }
 
-template <int A, typename TG>
+template <int A, typename TG, bool ARG>
 int launch_agg_dma(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
-                   float* agg, hipStream_t st) {
+                   float* agg, int32_t* disp, hipStream_t st) {
   const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
   const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
   const bool vec4 = (g.width % 4) == 0 && aligned(agg, 16);
   const size_t lds = agg_tile_dma_lds_bytes<A>();
-  auto kern = aggregate_dma_kernel<A, TG>;
+  auto kern = aggregate_dma_kernel<A, TG, ARG>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) {
@@ -108,22 +207,22 @@ int launch_agg_dma(const float* cost, int64_t cps, int crs, const rsv_image& g, 
     return RSV_E_HIP;
   }
   kern<<<dim3(tiles), dim3(1024), lds, st>>>(cost, cps, crs, static_cast<const TG*>(g.data), g.pitch,
-                                             g.height, g.width, p->D, bk, vec4, agg);
+                                             g.height, g.width, p->D, bk, vec4, agg, disp);
   return check_launch();
 }
 
-template <int A, typename TG>
+template <int A, typename TG, bool ARG>
 int launch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
-               float* agg, hipStream_t st) {
+               float* agg, int32_t* disp, hipStream_t st) {
   if constexpr (agg_dma_fits<A>()) {
-    if (g.width >= 4) return launch_agg_dma<A, TG>(cost, cps, crs, g, p, agg, st);
+    if (g.width >= 4) return launch_agg_dma<A, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
   }
   constexpr int TY = kAggTileRows;
   const int tiles = ((g.width + 15) / 16) * ((g.height + TY - 1) / TY);
   const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
   const bool vec4 = (g.width % 4) == 0 && aligned(agg, 16);
-  const size_t lds = agg_tile_lds_bytes<A, TY>();
-  auto kern = aggregate_kernel<A, TY, TG>;
+  const size_t lds = agg_tile_lds_bytes<A, TY>() + (ARG ? 2 * 256 * sizeof(float) : 0);
+  auto kern = aggregate_kernel<A, TY, TG, ARG>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) {
@@ -131,38 +230,44 @@ int launch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, cons
     return RSV_E_HIP;
   }
   kern<<<dim3(tiles), dim3(64 * TY), lds, st>>>(cost, cps, crs, static_cast<const TG*>(g.data), g.pitch,
-                                                g.height, g.width, p->D, bk, vec4, agg);
+                                                g.height, g.width, p->D, bk, vec4, agg, disp);
   return check_launch();
 }
 
-template <typename TG>
+template <typename TG, bool ARG>
 int dispatch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
-                 float* agg, hipStream_t st) {
+                 float* agg, int32_t* disp, hipStream_t st) {
   switch (p->agg_radius) {
-    case 1: return launch_agg<1, TG>(cost, cps, crs, g, p, agg, st);
-    case 2: return launch_agg<2, TG>(cost, cps, crs, g, p, agg, st);
-    case 3: return launch_agg<3, TG>(cost, cps, crs, g, p, agg, st);
-    case 4: return launch_agg<4, TG>(cost, cps, crs, g, p, agg, st);
-    case 5: return launch_agg<5, TG>(cost, cps, crs, g, p, agg, st);
-    case 6: return launch_agg<6, TG>(cost, cps, crs, g, p, agg, st);
+    case 1: return launch_agg<1, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
+    case 2: return launch_agg<2, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
+    case 3: return launch_agg<3, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
+    case 4: return launch_agg<4, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
+    case 5: return launch_agg<5, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
+    case 6: return launch_agg<6, TG, ARG>(cost, cps, crs, g, p, agg, disp, st);
     default: return RSV_E_PARAM;
   }
 }
 
+// One output: the volume agg, or (agg null) the argmax map disp.
 int run_agg(const float* cost, int64_t cps, int64_t crs, const rsv_image& guide, const rsv_params* p,
-            float* agg, void* stream) {
+            float* agg, int32_t* disp, void* stream) {
   if (int s = validate_image(guide)) return s;
   if (int s = validate_agg_params(p)) return s;
-  if (!cost || !agg) return RSV_E_NULL;
-  if (!aligned(cost, 4) || !aligned(agg, 4)) return RSV_E_ALIGN;
-  if (cost == agg) return RSV_E_PARAM;
+  if (!cost || (!agg && !disp)) return RSV_E_NULL;
+  if (!aligned(cost, 4) || (agg && !aligned(agg, 4)) || (disp && !aligned(disp, 4))) return RSV_E_ALIGN;
+  if (cost == agg || static_cast<const void*>(cost) == static_cast<const void*>(disp)) return RSV_E_PARAM;
   // element offsets inside 16 disparity planes stay below 2^31
   if (crs < guide.width || cps < 1 || cps > kAggMaxPixels ||
       static_cast<int64_t>(guide.height - 1) * crs + guide.width > kAggMaxPixels)
     return RSV_E_SHAPE;
   hipStream_t st = as_stream(stream);
-  if (guide.dtype == RSV_U8) return dispatch_agg<uint8_t>(cost, cps, static_cast<int>(crs), guide, p, agg, st);
-  return dispatch_agg<float>(cost, cps, static_cast<int>(crs), guide, p, agg, st);
+  const int rs = static_cast<int>(crs);
+  if (agg) {
+    if (guide.dtype == RSV_U8) return dispatch_agg<uint8_t, false>(cost, cps, rs, guide, p, agg, nullptr, st);
+    return dispatch_agg<float, false>(cost, cps, rs, guide, p, agg, nullptr, st);
+  }
+  if (guide.dtype == RSV_U8) return dispatch_agg<uint8_t, true>(cost, cps, rs, guide, p, nullptr, disp, st);
+  return dispatch_agg<float, true>(cost, cps, rs, guide, p, nullptr, disp, st);
 }
 
 }  // namespace rsv
@@ -171,10 +276,19 @@ extern "C" int rsv_aggregate(const float* cost, rsv_image guide, const rsv_param
                              void* stream) {
   using namespace rsv;
   if (int s = validate_image(guide)) return s;
-  return run_agg(cost, static_cast<int64_t>(guide.height) * guide.width, guide.width, guide, p, agg, stream);
+  if (!agg) return RSV_E_NULL;
+  return run_agg(cost, static_cast<int64_t>(guide.height) * guide.width, guide.width, guide, p, agg, nullptr,
+                 stream);
 }
 
 extern "C" int rsv_aggregate_strided(const float* cost, int64_t plane_stride, int64_t row_stride,
                                      rsv_image guide, const rsv_params* p, float* agg, void* stream) {
-  return rsv::run_agg(cost, plane_stride, row_stride, guide, p, agg, stream);
+  if (!agg) return RSV_E_NULL;
+  return rsv::run_agg(cost, plane_stride, row_stride, guide, p, agg, nullptr, stream);
+}
+
+extern "C" int rsv_aggregate_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                    rsv_image guide, const rsv_params* p, int32_t* disp, void* stream) {
+  if (!disp) return RSV_E_NULL;
+  return rsv::run_agg(cost, plane_stride, row_stride, guide, p, nullptr, disp, stream);
 }

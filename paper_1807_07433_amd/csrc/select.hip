@@ -17,9 +17,11 @@ namespace rsv {
 constexpr int kSelThreads = 256;
 constexpr int kSelUnroll = 16;
 
-// Walk d = 0 .. D-1 of one pixel in both volumes (stride `plane`): loads for both
-// run ahead of the compare chains in chunks of kSelUnroll, then of 4, then singly.
-// Every value is read once, so the loads are non-temporal.
+// Walk d = 0 .. D-1 of one pixel in both volumes (stride `plane`; pt null: the
+// reference volume only): loads run ahead of the compare chains in chunks of
+// kSelUnroll, then of 4, then singly.  Every value is read once, so the loads are
+// non-temporal.
+template <bool TAR>
 __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const float* __restrict__ pt,
                                           int64_t plane, int D, Scan& s, int& targ) {
   bool need_next = false;
@@ -32,19 +34,20 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
       targ = 0;
     } else {
       scan_step(s, need_next, prev, a, d);
-      if (b > tbest) {
+      if (TAR && b > tbest) {
         tbest = b;
         targ = d;
       }
     }
   };
+  auto load_t = [&](int d) { return TAR ? __builtin_nontemporal_load(pt + d * plane) : 0.f; };
   int d = 0;
   for (; d + kSelUnroll <= D; d += kSelUnroll) {
     float a[kSelUnroll], b[kSelUnroll];
 #pragma unroll
     for (int i = 0; i < kSelUnroll; ++i) {
       a[i] = __builtin_nontemporal_load(pr + (d + i) * plane);
-      b[i] = __builtin_nontemporal_load(pt + (d + i) * plane);
+      b[i] = load_t(d + i);
     }
 #pragma unroll
     for (int i = 0; i < kSelUnroll; ++i) consume(a[i], b[i], d + i);
@@ -54,14 +57,16 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       a[i] = __builtin_nontemporal_load(pr + (d + i) * plane);
-      b[i] = __builtin_nontemporal_load(pt + (d + i) * plane);
+      b[i] = load_t(d + i);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) consume(a[i], b[i], d + i);
   }
-  for (; d < D; ++d) consume(__builtin_nontemporal_load(pr + d * plane), __builtin_nontemporal_load(pt + d * plane), d);
+  for (; d < D; ++d) consume(__builtin_nontemporal_load(pr + d * plane), load_t(d), d);
 }
 
+// TAR: scan the target volume too and write dtar; otherwise dtar is an input.
+template <bool TAR>
 __global__ __launch_bounds__(kSelThreads) void select_scan_kernel(
     const float* __restrict__ aref, const float* __restrict__ atar, int H, int W, int D,
     int32_t* __restrict__ dref, int32_t* __restrict__ dtar, float* __restrict__ dsub,
@@ -73,9 +78,9 @@ __global__ __launch_bounds__(kSelThreads) void select_scan_kernel(
   const int64_t i = static_cast<int64_t>(v) * W + u;
   Scan s;
   int ta;
-  scan_pair(aref + i, atar + i, plane, D, s, ta);
+  scan_pair<TAR>(aref + i, TAR ? atar + i : nullptr, plane, D, s, ta);
   dref[i] = s.arg;
-  dtar[i] = ta;
+  if (TAR) dtar[i] = ta;
   dsub[i] = parabola(s.arg, s.best, s.am, s.ap, D);
   if (top2) {
     top2[i] = s.best;
@@ -97,23 +102,46 @@ __global__ __launch_bounds__(kSelThreads) void lr_check_kernel(const int32_t* __
 
 }  // namespace rsv
 
-extern "C" int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t height,
-                                   int32_t width, const rsv_params* p, int32_t* disp_ref,
-                                   int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
-                                   void* stream) {
-  using namespace rsv;
+namespace rsv {
+
+// With agg_tar: both scans; without: disp_tar is the target argmax map, given.
+int run_select(const float* agg_ref, const float* agg_tar, int32_t height, int32_t width, const rsv_params* p,
+               int32_t* disp_ref, int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
+               void* stream) {
   if (int s = validate_select_params(p)) return s;
-  if (!agg_ref || !agg_tar || !disp_ref || !disp_tar || !disp_sub || !valid) return RSV_E_NULL;
+  if (!agg_ref || !disp_ref || !disp_tar || !disp_sub || !valid) return RSV_E_NULL;
   if (height < 1 || width < 1) return RSV_E_SHAPE;
   if (static_cast<int64_t>(height) * width > INT32_MAX) return RSV_E_SHAPE;
   if (!aligned(agg_ref, 4) || !aligned(agg_tar, 4) || !aligned(disp_ref, 4) ||
       !aligned(disp_tar, 4) || !aligned(disp_sub, 4) || (top2 && !aligned(top2, 4)))
     return RSV_E_ALIGN;
   const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
-  select_scan_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(
-      agg_ref, agg_tar, height, width, p->D, disp_ref, disp_tar, disp_sub, top2);
+  if (agg_tar)
+    select_scan_kernel<true><<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(
+        agg_ref, agg_tar, height, width, p->D, disp_ref, disp_tar, disp_sub, top2);
+  else
+    select_scan_kernel<false><<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(
+        agg_ref, nullptr, height, width, p->D, disp_ref, disp_tar, disp_sub, top2);
   if (int st = check_launch()) return st;
   lr_check_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(disp_ref, disp_tar, width,
                                                                     p->lr_threshold, valid);
   return check_launch();
+}
+
+}  // namespace rsv
+
+extern "C" int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t height,
+                                   int32_t width, const rsv_params* p, int32_t* disp_ref,
+                                   int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
+                                   void* stream) {
+  if (int s = rsv::validate_select_params(p)) return s;
+  if (!agg_tar) return RSV_E_NULL;
+  return rsv::run_select(agg_ref, agg_tar, height, width, p, disp_ref, disp_tar, disp_sub, valid, top2, stream);
+}
+
+extern "C" int rsv_select_subpixel_ref(const float* agg_ref, const int32_t* disp_tar, int32_t height,
+                                       int32_t width, const rsv_params* p, int32_t* disp_ref, float* disp_sub,
+                                       uint8_t* valid, float* top2, void* stream) {
+  return rsv::run_select(agg_ref, nullptr, height, width, p, disp_ref, const_cast<int32_t*>(disp_tar),
+                         disp_sub, valid, top2, stream);
 }

@@ -160,12 +160,37 @@ def aggregate(cost: torch.Tensor, guide: torch.Tensor, params,
     return out
 
 
-def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor, params, want_top2: bool = False,
+def aggregate_argmax(cost: torch.Tensor, guide: torch.Tensor, params,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """argmax over d of the aggregation of a [D][H][W] volume or view (ties -> lowest
+    d), without writing the aggregated volume (rsv_aggregate_argmax): the target
+    disparities that select_subpixel takes in place of the target volume."""
+    lib = load()
+    D, H, W = cost.shape
+    _dev(cost, "cost", torch.float32, (int(params.D), H, W))
+    if tuple(guide.shape) != (H, W):
+        raise ValueError("guide must match the volume's H, W")
+    if cost.stride(2) != 1:
+        raise ValueError("cost views need unit column stride")
+    out = out if out is not None else torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    _contig(out, "disp", torch.int32, (H, W))
+    p = _params(params)
+    check(lib.rsv_aggregate_argmax(cost.data_ptr(), cost.stride(0), cost.stride(1), image(guide, "guide"),
+                                   C.byref(p), out.data_ptr(), _stream(cost.device)), "rsv_aggregate_argmax")
+    return out
+
+
+def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor | None, params, want_top2: bool = False,
                     out: dict | None = None) -> dict:
+    """WTA, left-right check and Eq. 12.  With agg_tar None, out["disp_tar"] must hold
+    the target disparities (aggregate_argmax) and rsv_select_subpixel_ref runs."""
     lib = load()
     D, H, W = agg_ref.shape
     _contig(agg_ref, "agg_ref", torch.float32, (int(params.D), H, W))
-    _contig(agg_tar, "agg_tar", torch.float32, (D, H, W))
+    if agg_tar is not None:
+        _contig(agg_tar, "agg_tar", torch.float32, (D, H, W))
+    elif not out or "disp_tar" not in out:
+        raise ValueError("without agg_tar, out['disp_tar'] must hold the target disparities")
     dev = agg_ref.device
     o = dict(out) if out else {}
     o.setdefault("disp_ref", torch.empty((H, W), dtype=torch.int32, device=dev))
@@ -182,10 +207,16 @@ def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor, params, want_t
     if top2 is not None:
         _contig(top2, "top2", torch.float32, (2, H, W))
     p = _params(params)
-    check(lib.rsv_select_subpixel(agg_ref.data_ptr(), agg_tar.data_ptr(), H, W, C.byref(p),
-                                  o["disp_ref"].data_ptr(), o["disp_tar"].data_ptr(),
-                                  o["disp_sub"].data_ptr(), o["valid"].data_ptr(), _ptr(top2),
-                                  _stream(dev)), "rsv_select_subpixel")
+    if agg_tar is not None:
+        check(lib.rsv_select_subpixel(agg_ref.data_ptr(), agg_tar.data_ptr(), H, W, C.byref(p),
+                                      o["disp_ref"].data_ptr(), o["disp_tar"].data_ptr(),
+                                      o["disp_sub"].data_ptr(), o["valid"].data_ptr(), _ptr(top2),
+                                      _stream(dev)), "rsv_select_subpixel")
+    else:
+        check(lib.rsv_select_subpixel_ref(agg_ref.data_ptr(), o["disp_tar"].data_ptr(), H, W, C.byref(p),
+                                          o["disp_ref"].data_ptr(), o["disp_sub"].data_ptr(),
+                                          o["valid"].data_ptr(), _ptr(top2), _stream(dev)),
+              "rsv_select_subpixel_ref")
     return o
 
 
@@ -254,19 +285,26 @@ def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_re
 
 
 def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
-                want_top2: bool = False, joint: bool = True) -> dict:
+                want_top2: bool = False, joint: bool = True, tar_volume: bool = True) -> dict:
     """The plain path, one C-ABI call per stage on the current stream (Fig. 1):
     warp -> both cost volumes -> aggregation of each -> WTA + L-R + subpixel ->
     post-processing + 3-D points.  With joint=True the two cost volumes are views of
-    one joint volume (rsv_cost_volume_joint); otherwise two dense volumes."""
+    one joint volume (rsv_cost_volume_joint); otherwise two dense volumes.  With
+    tar_volume=False the target volume is reduced to its argmax as it is aggregated
+    (rsv_aggregate_argmax) and "agg_tar" is None; every other output is the same."""
     wp = warp(right, plane)
     if joint:
         cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
     else:
         cref, ctar = cost_volume(left, wp, params)
     aref = aggregate(cref, left, params)
-    atar = aggregate(ctar, wp, params)
-    sel = select_subpixel(aref, atar, params, want_top2=want_top2)
+    if tar_volume:
+        atar = aggregate(ctar, wp, params)
+        sel = select_subpixel(aref, atar, params, want_top2=want_top2)
+    else:
+        atar = None
+        sel = select_subpixel(aref, None, params, want_top2=want_top2,
+                              out={"disp_tar": aggregate_argmax(ctar, wp, params)})
     dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
     out = dict(warped=wp, cost_ref=cref, cost_tar=ctar, agg_ref=aref, agg_tar=atar,
                disp_final=dfin, xyz=xyz)
@@ -275,5 +313,5 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
-           "joint_row_stride", "aggregate", "select_subpixel",
+           "joint_row_stride", "aggregate", "aggregate_argmax", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "cost_adjoint", "image", "load"]

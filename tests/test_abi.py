@@ -166,3 +166,19 @@ def test_aggregate_strided_validation(lib, ps, rs, status):
     assert lib.rsv_aggregate_strided(None, 32 * 48, 48, _img(), C.byref(p), FAKE, None) == -1
     assert lib.rsv_aggregate_strided(FAKE, 32 * 48, 48, _img(), C.byref(_params(agg_radius=9)),
                                      FAKE + 4096, None) == -3
+
+
+def test_argmax_and_select_ref_validation(lib):
+    p = _params()
+    assert lib.rsv_aggregate_argmax(FAKE, 32 * 48, 48, _img(), C.byref(p), None, None) == -1
+    assert lib.rsv_aggregate_argmax(None, 32 * 48, 48, _img(), C.byref(p), FAKE, None) == -1
+    assert lib.rsv_aggregate_argmax(FAKE, 32 * 48, 47, _img(), C.byref(p), FAKE + 4096, None) == -2
+    assert lib.rsv_aggregate_argmax(FAKE, 32 * 48, 48, _img(), C.byref(_params(gamma_d=0.0)),
+                                    FAKE + 4096, None) == -3
+    assert lib.rsv_aggregate_argmax(FAKE, 32 * 48, 48, _img(), C.byref(p), FAKE + 2, None) == -5
+    assert lib.rsv_select_subpixel_ref(FAKE, None, 32, 48, C.byref(p), FAKE, FAKE, FAKE, None, None) == -1
+    assert lib.rsv_select_subpixel_ref(FAKE, FAKE, 0, 48, C.byref(p), FAKE, FAKE, FAKE, None, None) == -2
+    assert lib.rsv_select_subpixel_ref(FAKE, FAKE, 32, 48, C.byref(_params(lr_threshold=-1)), FAKE, FAKE,
+                                       FAKE, None, None) == -3
+    # the full form still needs its target volume
+    assert lib.rsv_select_subpixel(FAKE, None, 32, 48, C.byref(p), FAKE, FAKE, FAKE, FAKE, None, None) == -1

@@ -124,6 +124,12 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
     _say("  rsv_select_subpixel")
     sel = rsv.select_subpixel(aref, atar, prm, want_top2=True)
     _check_selection("end-to-end", sel, ref, ref["agg_ref"], ref["agg_tar"], max(e1, e2, 1e-7))
+    _say("  rsv_aggregate_argmax + rsv_select_subpixel_ref (no target volume)")
+    dt = rsv.aggregate_argmax(jtar, wp, prm)
+    assert torch.equal(dt, sel["disp_tar"]), "argmax of the target aggregation"
+    sel_ref = rsv.select_subpixel(aref, None, prm, want_top2=True, out={"disp_tar": dt})
+    for k in ("disp_ref", "disp_sub", "valid", "top2"):
+        assert torch.equal(sel_ref[k], sel[k]), k
     top2 = P.to_np(sel["top2"])
     P.check_close("best", top2[0], ref["best"], P.AGG_TOL)
     if D > 1:
@@ -168,6 +174,38 @@ def test_pitched_inputs_match_dense(rsv_gpu):
     b = rsv.reconstruct(Lp, Rp, case.plane, _camera(case), prm)
     for k in ("warped", "cost_ref", "cost_tar", "agg_ref", "agg_tar", "disp_ref", "disp_sub", "valid"):
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("H,W,D,r,rho,seed", [(33, 90, 20, 3, 5, 41), (21, 37, 9, 2, 6, 42)])
+def test_strided_views_match_dense(rsv_gpu, H, W, D, r, rho, seed):
+    """rsv_aggregate_strided on an arbitrary padded view (odd row and plane strides)
+    and rsv_cost_volume_joint at the smallest row stride W + D - 1 (rows not 64-aligned)
+    give the dense path's floats bit for bit."""
+    rsv = rsv_gpu
+    import ctypes as C
+    from paper_1807_07433_amd import _lib
+    from paper_1807_07433_amd.ops import _params, _stream
+    case = synth.small_case(H, W, D, r, rho, seed)
+    prm = case.params
+    L, R = _gpu(case.pair.left), _gpu(case.pair.right)
+    wp = rsv.warp(R, case.plane)
+    cref, ctar = rsv.cost_volume(L, wp, prm)
+    _say(f"[strided] H={H} W={W} D={D} r={r} rho={rho}: padded view, odd strides")
+    rs, ps = W + 7, H * (W + 7) + 3
+    buf = torch.full((D * ps + 16,), float("nan"), dtype=torch.float32, device="cuda")
+    view = buf.as_strided((D, H, W), (ps, rs, 1), 5)
+    view.copy_(ctar)
+    assert torch.equal(rsv.aggregate(view, wp, prm), rsv.aggregate(ctar, wp, prm))
+    _say("  joint volume at row stride W + D - 1")
+    rs = W + D - 1
+    joint = torch.full((D, H, rs), float("nan"), dtype=torch.float32, device="cuda")
+    p = _params(prm)
+    _lib.check(_lib.load().rsv_cost_volume_joint(rsv.image(L, "left"), wp.data_ptr(), C.byref(p),
+                                                 joint.data_ptr(), rs, _stream(L.device)),
+               "rsv_cost_volume_joint")
+    jref, jtar = rsv.joint_views(joint, W)
+    assert torch.equal(jref, cref) and torch.equal(jtar, ctar)
+    assert torch.equal(rsv.aggregate(jtar, wp, prm), rsv.aggregate(ctar, wp, prm))
 
 
 def test_flat_images_give_zero_costs_and_lowest_d(rsv_gpu):
@@ -280,9 +318,23 @@ def _sampled_full(rsv, case, n_cost, n_agg, n_pix, seed):
     return out
 
 
+def _fused_target_matches(rsv, case, out):
+    """The plain path without a target volume gives the same maps, bit for bit."""
+    p = case.pair
+    _say("  target aggregation reduced to its argmax: every output equal")
+    f = rsv.reconstruct(_gpu(p.left), _gpu(p.right), case.plane, _camera(case), case.params, tar_volume=False)
+    assert f["agg_tar"] is None
+    for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
+        assert torch.equal(f[k].nan_to_num(), out[k].nan_to_num()), k
+
+
 def test_full_road1280_d64_sampled(rsv_gpu):
-    _sampled_full(rsv_gpu, synth.road1280_d64(), 20000, 1500, 200, 7)
+    case = synth.road1280_d64()
+    out = _sampled_full(rsv_gpu, case, 20000, 1500, 200, 7)
+    _fused_target_matches(rsv_gpu, case, out)
 
 
 def test_full_road1920_d128_sampled(rsv_gpu):
-    _sampled_full(rsv_gpu, synth.road1920_d128(), 10000, 600, 60, 8)
+    case = synth.road1920_d128()
+    out = _sampled_full(rsv_gpu, case, 10000, 600, 60, 8)
+    _fused_target_matches(rsv_gpu, case, out)

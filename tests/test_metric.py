@@ -19,7 +19,7 @@ def test_eq13_reproduces_the_printed_throughput():
 
 def test_kernel_roofline_units():
     """Cost against HBM at 4 B per distinct cost value (the joint volume), select at
-    8 B per entry; the aggregation against the FP32 arithmetic peak at 2m + 2 FLOP per
+    4 B per entry (the reference volume); the aggregation against the FP32 arithmetic peak at 2m + 2 FLOP per
     entry, m = (2 rho + 1)^2."""
     class P:
         agg_radius = 5
@@ -29,7 +29,7 @@ def test_kernel_roofline_units():
     # every (d, v) row holds W reference values plus d target values past the right edge
     distinct = sum(720 * (1280 + d) for d in range(64))
     assert k["cost_volume"]["bound"] == "hbm" and k["cost_volume"]["bytes_per_launch"] == 4 * distinct
-    assert abs(k["select_subpixel"]["achieved"] - 8 * n / 0.05e-3 / 1e9) < 1.0
+    assert abs(k["select_subpixel"]["achieved"] - 4 * n / 0.05e-3 / 1e9) < 1.0
     agg = k["aggregate"]
     assert agg["bound"] == "alu" and agg["flops_per_launch"] == (2 * 121 + 2) * n
     assert abs(agg["achieved"] - (2 * 121 + 2) * n / 0.2e-3 / 1e12) < 0.01
