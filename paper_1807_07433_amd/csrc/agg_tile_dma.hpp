@@ -31,18 +31,47 @@
 
 namespace rsv {
 
+// LDS layout: out | raw0 | raw1 | hi | lo | guide tile | spatial table.  The last two
+// are read only by the weight computation, before the first sink call; from then on
+// a sink may use the LDS from agg_tile_dma_spare_offset on.
 template <int A>
-__host__ __device__ constexpr size_t agg_tile_dma_lds_bytes() {
+__host__ __device__ constexpr size_t agg_tile_dma_spare_offset() {
   using G = AggGeo<A, 16>;
-  return sizeof(float) * (16 * G::OST + G::RAW + G::SKN) + 2 /*raw*/ * 16 * G::NCH * 16 /*B per chunk*/ +
+  return sizeof(float) * 16 * G::OST + 2 /*raw*/ * 16 * G::NCH * 16 /*B per chunk*/ +
          2 /*hi,lo*/ * 16 * G::PLANE * sizeof(_Float16);
 }
 
-// One 16-byte-per-lane global-to-LDS load: lane l's 16 bytes at src go to LDS byte
-// address lds_wave + 16 l (lds_wave is the wave's destination base, uniform).
-__device__ __forceinline__ void lds_dma16(const float* src, uint32_t lds_wave) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds_wave)
-               : "memory", "m0");
+template <int A>
+__host__ __device__ constexpr size_t agg_tile_dma_lds_bytes() {
+  using G = AggGeo<A, 16>;
+  return agg_tile_dma_spare_offset<A>() + sizeof(float) * (G::RAW + G::SKN);
+}
+
+// The LDS-loaded tile fits one CU's 160 KiB of LDS up to radius 5.
+template <int A>
+constexpr bool agg_dma_fits() {
+  return agg_tile_dma_lds_bytes<A>() <= 160 * 1024;
+}
+
+// One 16-byte-per-lane global-to-LDS load: lane l's 16 bytes at base + voff (a
+// uniform base in SGPRs, a 32-bit byte offset per lane) go to LDS byte address
+// lds_wave + 16 l (lds_wave is the wave's destination base, uniform).  The
+// destination goes through m0, which the statement saves and restores itself (the
+// compiler reserves m0 and does not honour it as a clobber).
+// lds_wave is taken from its first lane inside the statement, so it may sit in a
+// vector register (inside device functions the compiler does not always keep it
+// scalar).
+__device__ __forceinline__ void lds_dma16(const float* base, uint32_t voff, uint32_t lds_wave) {
+  uint32_t saved, dst;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "v_readfirstlane_b32 %1, %4\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %2, %3\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved), "=&s"(dst)
+      : "v"(voff), "s"(base), "v"(lds_wave)
+      : "memory");
 }
 
 // s_waitcnt vmcnt(n); the memory clobber keeps LDS reads of the loaded data after it.
@@ -52,7 +81,8 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// LDS byte address of a pointer into the workgroup's LDS.
+// LDS byte address of a pointer into the workgroup's LDS (use it where the pointer is
+// known to address LDS, e.g. on a kernel's __shared__ array).
 __device__ __forceinline__ uint32_t lds_address(const void* p) {
   typedef const __attribute__((address_space(3))) char* lds_ptr;
   return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr)p));
@@ -62,19 +92,21 @@ template <int A, typename GuideAt, typename Sink>
 __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int64_t cps, int crs, int H,
                                              int W, int D,
                                              const BilateralK& bk, int by, int bx, GuideAt guide_at,
-                                             Sink& sink, unsigned char* smem) {
+                                             Sink& sink, unsigned char* smem, uint32_t smem_lds) {
+  // smem_lds: LDS byte address of smem (lds_address in the kernel), so that device
+  // functions holding smem as a generic pointer can address the DMA destinations
   using G = AggGeo<A, 16>;
   constexpr int NT = G::NT;                      // 1024
   constexpr int NITEM = 16 * G::NCH;             // (disparity, chunk) items per tile
   constexpr int SPT = (NITEM + NT - 1) / NT;     // items per thread
   static_assert(SPT <= 3, "wait counts below assume at most 3 loads per wave and tile");
   float* out = reinterpret_cast<float*>(smem);
-  float* gt = out + 16 * G::OST;
-  float* skt = gt + G::RAW;
-  float* raw0 = skt + G::SKN;                    // 16 B aligned: all sizes above are multiples of 4
+  float* raw0 = out + 16 * G::OST;               // 16 B aligned: 16 * OST is a multiple of 4
   float* raw1 = raw0 + 4 * NITEM;
   _Float16* hi = reinterpret_cast<_Float16*>(raw1 + 4 * NITEM);
   _Float16* lo = hi + 16 * G::PLANE;
+  float* gt = reinterpret_cast<float*>(smem + agg_tile_dma_spare_offset<A>());
+  float* skt = gt + G::RAW;
   const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
   const int x0 = bx - A - G::PAD;
 
@@ -105,16 +137,20 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   // loads this wave issues per tile (items with at least one lane in the list)
   const int nq = __builtin_amdgcn_readfirstlane((NITEM - 64 * wave + NT - 1) / NT);
 
+  // Byte offsets from the tile's first plane fit 32 bits: eoff <= 15 cps + (H-1) crs +
+  // W - 1 < 2^30 under the 2^26 limits on cps and (H-1) crs + W.
   auto issue = [&](int t, float* raw) {
-    const float* base = cost + static_cast<int64_t>(16 * t) * cps;
+    const float* base = uniform(cost + static_cast<int64_t>(16 * t) * cps);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       if (q * NT + 64 * wave < NITEM) {  // uniform per wave
         const int d = 16 * t + static_cast<int>(meta[q] & 15u);
         const bool ok = (meta[q] >> 4 & 15u) != 0 && d < D;
-        const float* src = ok ? base + eoff[q] : cost;  // a valid address either way
-        const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_address(raw + 4 * (q * NT + 64 * wave)));
-        if (tid + q * NT < NITEM) lds_dma16(src, dst);
+        const uint32_t voff = ok ? 4u * static_cast<uint32_t>(eoff[q]) : 0u;  // plane 16 t exists
+        const uint32_t dst = __builtin_amdgcn_readfirstlane(
+            smem_lds + static_cast<uint32_t>(reinterpret_cast<const unsigned char*>(raw + 4 * (q * NT + 64 * wave)) -
+                                             smem));
+        if (tid + q * NT < NITEM) lds_dma16(base, voff, dst);
       }
     }
   };

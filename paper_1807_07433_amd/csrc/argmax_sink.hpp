@@ -1,0 +1,95 @@
+// Sink of the aggregation tiles for a volume that is only needed through its
+// winner-take-all disparity (Sec. II-B.3): shared by rsv_aggregate_argmax and the
+// batch kernel's target-volume items.
+#pragma once
+
+#include "aggregate_mfma.hpp"
+
+namespace rsv {
+
+// (b, a) <- the better of (b, a) and the quad lane selected by the DPP quad_perm
+// pattern PERM: the larger value, the lower d on ties.
+template <int PERM>
+__device__ __forceinline__ void quad_merge(float& b, int& a) {
+  const float ob = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(b), PERM, 0xF, 0xF, false));
+  const int oa = __builtin_amdgcn_mov_dpp(a, PERM, 0xF, 0xF, false);
+  if (ob > b || (ob == b && oa < a)) {
+    b = ob;
+    a = oa;
+  }
+}
+
+// agg_tile sink for a volume that is only needed through its argmax over d (the
+// target volume of Sec. II-B.3): the 16 x 16 pixels' running winner, nothing written
+// until the end; the select kernel's order (the first maximum over d).  Two forms:
+// * state null (the LDS-loaded tile): thread i covers pixel i / 4 and disparities
+//   4 (i % 4) .. + 3 of the tile: its first maximum, then the quad's (lower d on
+//   ties), then against the earlier tiles' winner (replaced only when strictly
+//   greater).  All four threads of a quad keep the same winner in registers.
+// * state in LDS (the register-staged tile, whose registers are full): thread p <
+//   256 scans pixel p's 16 values in order against the winner kept in LDS.
+struct ArgmaxSink {
+  int D;
+  float* state = nullptr;  // [2][256]: best, then arg bits
+  float best = -INFINITY;
+  int arg = 0;
+
+  __device__ __forceinline__ void operator()(int t, const float* o) {
+    using G = AggGeo<1, 16>;
+    if (state) {
+      const int p = threadIdx.x;
+      if (p >= 256) return;
+      float b = t == 0 ? -INFINITY : state[p];
+      int a = t == 0 ? 0 : __float_as_int(state[256 + p]);
+      const int n = min(16, D - 16 * t);
+      for (int dd = 0; dd < n; ++dd) {
+        const float v = o[dd * G::OST + p];
+        if ((t == 0 && dd == 0) || v > b) {
+          b = v;
+          a = 16 * t + dd;
+        }
+      }
+      state[p] = b;
+      state[256 + p] = __int_as_float(a);
+      return;
+    }
+    const int i = threadIdx.x, p = i >> 2, q = i & 3;
+    float b = -INFINITY;
+    int a = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = 16 * t + 4 * q + k;
+      const float v = o[(4 * q + k) * G::OST + p];
+      if (d < D && v > b) {
+        b = v;
+        a = d;
+      }
+    }
+    // the quad's lanes i ^ 1, then i ^ 2 (DPP quad permutations, no LDS traffic)
+    quad_merge<0xB1>(b, a);
+    quad_merge<0x4E>(b, a);
+    if (t == 0 || b > best) {
+      best = b;
+      arg = a;
+    }
+  }
+
+  // Writes the winners after the last call: one thread per in-image pixel.
+  __device__ __forceinline__ void finish(int32_t* disp, int H, int W, int by, int bx) const {
+    int p;
+    int a;
+    if (state) {
+      p = threadIdx.x;
+      if (p >= 256) return;
+      a = __float_as_int(state[256 + p]);  // written by this thread
+    } else {
+      if (threadIdx.x & 3) return;
+      p = threadIdx.x >> 2;
+      a = arg;
+    }
+    const int Y = by + (p >> 4), X = bx + (p & 15);
+    if (Y < H && X < W) disp[static_cast<int64_t>(Y) * W + X] = a;
+  }
+};
+
+}  // namespace rsv

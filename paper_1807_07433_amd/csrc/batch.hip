@@ -1,26 +1,27 @@
 // Batched form: many stereo pairs of uneven size and disparity range in one
-// hipGraph launch of persistent work-queue kernels.
+// hipGraph launch.
 //
-// A plan holds, per pair, the warped right image, the two cost volumes and the WTA
+// A plan holds, per pair, the warped right image, the joint cost volume and the WTA
 // state, plus the work lists, and captures the graph
-//     reset counters -> warp -> cost kernel -> aggregate+WTA kernel -> tail kernel.
-// The persistent kernels pull items from atomic counters, so pairs of any size and
-// D share the GPU without per-pair launches:
+//     reset counters -> warp -> cost kernel -> aggregate+WTA kernel ->
+//     target-tile kernel -> tail kernel.
 //   warp: every pixel of every pair, with rsv_warp's arithmetic;
 //   cost items (pair, band of 4 rows, 64-centre column tiles): ZNCC with the
-//       arithmetic of rsv_cost_volume (shared cost_tile), writing C_ref and C_tar;
-//   aggregation items (pair, 16 x 16 tile, ref | tar): bilateral aggregation on the
-//       matrix cores with the arithmetic of rsv_aggregate (shared agg_tile) and
-//       winner-take-all folded in: each 16-disparity tile of aggregated values is
-//       fed, from LDS, through the select kernel's own scan step (running best,
-//       second best and the winner's neighbours, ties keep the lowest d).  No
-//       aggregated volume is written.  The aggregation list is cut into 8 contiguous
+//       arithmetic of rsv_cost_volume_joint (shared cost_tile), persistent over a
+//       work queue or one workgroup per tile;
+//   aggregation items (pair, 16 x 16 tile, reference volume; and target tiles the
+//       LDS-loaded tile cannot take): bilateral aggregation on the matrix cores with
+//       the arithmetic of rsv_aggregate (shared agg_tile) and winner-take-all folded
+//       in: each 16-disparity tile of aggregated values is fed, from LDS, through the
+//       select kernel's own scan step (running best, second best and the winner's
+//       neighbours, ties keep the lowest d).  The list is cut into 8 contiguous
 //       stretches, one queue per XCD (workgroups are dealt to the XCDs round-robin),
 //       so neighbouring tiles share an L2; a workgroup whose queue is empty takes
-//       items from the next queues.
-// Workgroups claim items in chunks of 4 neighbours, one atomic per chunk.  The tail
-// applies the left-right check (Eq. 11), the
-// parabola (Eq. 12), post-processing and triangulation per pixel, with the plain
+//       items from the next queues, in chunks of 4 neighbours, one atomic per chunk;
+//   target tiles (rho <= 5, W >= 4): one workgroup per tile on the LDS-loaded tile,
+//       keeping only the argmax over d (rsv_aggregate_argmax's arithmetic).
+// No aggregated volume is written.  The tail applies the left-right check (Eq. 11),
+// the parabola (Eq. 12), post-processing and triangulation per pixel, with the plain
 // path's functions.  Every output therefore equals the plain path's bit for bit.
 // The kernel boundaries replace any cross-workgroup wait.
 #include <hip/hip_runtime.h>
@@ -30,6 +31,8 @@
 #include <vector>
 
 #include "agg_tile.hpp"
+#include "agg_tile_dma.hpp"
+#include "argmax_sink.hpp"
 #include "cost_tile.hpp"
 #include "select_math.hpp"
 #include "warp_math.hpp"
@@ -284,6 +287,58 @@ __global__ __launch_bounds__(kAggItemThreads) void batch_agg_kernel(BatchArgs ar
   for_each_item(args, home, s_item, [&](int it) { batch_agg_item<A>(args, args.items[it], smem); });
 }
 
+// Target-volume items on the LDS-loaded tile (rho <= 5, W >= 4), one workgroup per
+// item {pair, kind, tile row, tile column}: only the argmax over d is kept, in
+// registers (ArgmaxSink), as in rsv_aggregate_argmax.  A kernel of its own, so the
+// tile keeps a kernel's register budget.
+template <int A>
+__global__ __launch_bounds__(1024) void batch_tar_grid_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 w = args.items[blockIdx.x];
+  const PairDev* pd = uniform(args.pairs + uniform(w.x));
+  const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
+  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
+  const float* warped = uniform(pd->warped);
+  const int jrow = static_cast<int>(uniform(pd->jrow));
+  auto guide = [&](int Y, int X) { return warped[static_cast<int64_t>(Y) * W + X]; };
+  ArgmaxSink sink{D};
+  agg_tile_dma<A>(uniform(pd->joint), static_cast<int64_t>(H) * jrow + 1, jrow, H, W, D, args.bk, by, bx, guide,
+                  sink, smem, lds_address(smem));
+  sink.finish(uniform(pd->tar_arg), H, W, by, bx);
+}
+
+// Reference-volume items on the LDS-loaded tile (rho <= 5, W >= 4), one workgroup
+// per item: the select kernel's scan (WtaSink) with its state in the LDS of the
+// guide and spatial tables, which are dead once the weights are computed.
+template <int A>
+__global__ __launch_bounds__(1024) void batch_ref_grid_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  static_assert(agg_tile_dma_spare_offset<A>() + sizeof(WtaState) <= 160 * 1024, "scan state must fit");
+  const int4 w = args.items[blockIdx.x];
+  const PairDev* pd = uniform(args.pairs + uniform(w.x));
+  const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
+  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
+  const uint8_t* left = uniform(pd->left);
+  const int64_t lpitch = uniform(pd->lpitch);
+  const int jrow = static_cast<int>(uniform(pd->jrow));
+  auto guide = [&](int Y, int X) { return pixel(left, lpitch, Y, X); };
+  WtaState* st = reinterpret_cast<WtaState*>(smem + agg_tile_dma_spare_offset<A>());
+  WtaSink sink{st, D, true};
+  agg_tile_dma<A>(uniform(pd->joint), static_cast<int64_t>(H) * jrow, jrow, H, W, D, args.bk, by, bx, guide, sink,
+                  smem, lds_address(smem));
+  if (threadIdx.x < 256) {  // each such thread wrote its own pixel's state in the last sink call
+    const int q = threadIdx.x;
+    const int Y = by + (q >> 4), X = bx + (q & 15);
+    if (Y < H && X < W) {
+      const int64_t i = static_cast<int64_t>(Y) * W + X;
+      uniform(pd->ref_arg)[i] = st->arg[q];
+      uniform(pd->ref_best)[i] = st->best[q];
+      uniform(pd->ref_am)[i] = st->am[q];
+      uniform(pd->ref_ap)[i] = st->ap[q];
+    }
+  }
+}
+
 // Left-right check, Eq. 12, post-processing and 3-D points for every pixel of every pair.
 __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, int tau) {
   const PairDev P = pairs[blockIdx.y];
@@ -317,8 +372,9 @@ struct rsv_batch_plan {
   void* dev_mem = nullptr;  // one allocation: pair table, item lists, counters, workspace
   rsv::PairDev* d_pairs = nullptr;
   int* d_heads = nullptr;   // [cost, aggregation queues]
-  rsv::BatchArgs cost_args{}, agg_args{};
-  int n_cost_items = 0, n_agg_items = 0;
+  rsv::BatchArgs cost_args{}, agg_args{}, tar_args{}, ref_args{};
+  // agg: items of the persistent aggregation kernel; tar / ref: of the tile kernels
+  int n_cost_items = 0, n_agg_items = 0, n_tar_items = 0, n_ref_items = 0;
   int cost_grid = 0, agg_grid = 0;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -349,19 +405,43 @@ const void* pick_cost_kernel(int R, bool grid) {
 }
 
 const void* pick_agg_kernel(int A, size_t* lds) {
-  size_t t = 0;
-  const void* k = nullptr;
   switch (A) {
-    case 1: t = agg_tile_lds_bytes<1, 16>(); k = agg_kernel_ptr<1>(); break;
-    case 2: t = agg_tile_lds_bytes<2, 16>(); k = agg_kernel_ptr<2>(); break;
-    case 3: t = agg_tile_lds_bytes<3, 16>(); k = agg_kernel_ptr<3>(); break;
-    case 4: t = agg_tile_lds_bytes<4, 16>(); k = agg_kernel_ptr<4>(); break;
-    case 5: t = agg_tile_lds_bytes<5, 16>(); k = agg_kernel_ptr<5>(); break;
-    case 6: t = agg_tile_lds_bytes<6, 16>(); k = agg_kernel_ptr<6>(); break;
+    case 1: *lds = agg_tile_lds_bytes<1, 16>() + sizeof(WtaState); return agg_kernel_ptr<1>();
+    case 2: *lds = agg_tile_lds_bytes<2, 16>() + sizeof(WtaState); return agg_kernel_ptr<2>();
+    case 3: *lds = agg_tile_lds_bytes<3, 16>() + sizeof(WtaState); return agg_kernel_ptr<3>();
+    case 4: *lds = agg_tile_lds_bytes<4, 16>() + sizeof(WtaState); return agg_kernel_ptr<4>();
+    case 5: *lds = agg_tile_lds_bytes<5, 16>() + sizeof(WtaState); return agg_kernel_ptr<5>();
+    case 6: *lds = agg_tile_lds_bytes<6, 16>() + sizeof(WtaState); return agg_kernel_ptr<6>();
     default: return nullptr;
   }
-  *lds = t + sizeof(WtaState);
-  return k;
+}
+
+// The target- and reference-tile kernels for radius A (null when the LDS-loaded
+// tile does not fit: rho = 6), with their LDS bytes.
+template <int A>
+const void* tile_kernel_ptr(bool ref, size_t* lds) {
+  if constexpr (agg_dma_fits<A>()) {
+    if (ref) {
+      *lds = std::max(agg_tile_dma_lds_bytes<A>(), agg_tile_dma_spare_offset<A>() + sizeof(WtaState));
+      return reinterpret_cast<const void*>(batch_ref_grid_kernel<A>);
+    }
+    *lds = agg_tile_dma_lds_bytes<A>();
+    return reinterpret_cast<const void*>(batch_tar_grid_kernel<A>);
+  } else {
+    return nullptr;
+  }
+}
+
+const void* pick_tile_kernel(int A, bool ref, size_t* lds) {
+  switch (A) {
+    case 1: return tile_kernel_ptr<1>(ref, lds);
+    case 2: return tile_kernel_ptr<2>(ref, lds);
+    case 3: return tile_kernel_ptr<3>(ref, lds);
+    case 4: return tile_kernel_ptr<4>(ref, lds);
+    case 5: return tile_kernel_ptr<5>(ref, lds);
+    case 6: return tile_kernel_ptr<6>(ref, lds);
+    default: return nullptr;
+  }
 }
 
 int validate_pair(const rsv_pair_desc& pd, int K) {
@@ -424,7 +504,10 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     });
 
   std::vector<PairDev> pd(n);
-  std::vector<int4> cost_items, agg_items;
+  std::vector<int4> cost_items, agg_items, tar_items, ref_items;
+  size_t tar_lds = 0, ref_lds = 0;
+  const void* tk = pick_tile_kernel(A, false, &tar_lds);
+  const void* rk = pick_tile_kernel(A, true, &ref_lds);
   size_t ws_bytes = 0;
   int max_pixels = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -471,7 +554,15 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
         cost_items.push_back(make_int4(i, kItemCost | (cost_tiles << 8), b, ct));
     for (int kind : {kItemAggRef, kItemAggTar})
       for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
-        for (int tx = 0; tx < P.tiles_x; ++tx) agg_items.push_back(make_int4(i, kind, ty, tx));
+        for (int tx = 0; tx < P.tiles_x; ++tx) {
+          // tiles go to the tile kernels when the LDS-loaded tile applies, else to the
+          // persistent kernel
+          const int4 it = make_int4(i, kind, ty, tx);
+          if (tk && P.W >= 4)
+            (kind == kItemAggTar ? tar_items : ref_items).push_back(it);
+          else
+            agg_items.push_back(it);
+        }
   }
   // queue boundaries: [0, n_cost) for the cost kernel; 8 equal stretches of the agg list
   std::vector<int> qbeg(2 + kAggQueues + 1);
@@ -487,6 +578,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   plan->tuning = tn;
   plan->n_cost_items = static_cast<int>(cost_items.size());
   plan->n_agg_items = static_cast<int>(agg_items.size());
+  plan->n_tar_items = static_cast<int>(tar_items.size());
+  plan->n_ref_items = static_cast<int>(ref_items.size());
 
   size_t off = 0;
   const size_t o_pairs = off;
@@ -495,6 +588,10 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   off = align(off + sizeof(int4) * cost_items.size());
   const size_t o_ai = off;
   off = align(off + sizeof(int4) * agg_items.size());
+  const size_t o_ti = off;
+  off = align(off + sizeof(int4) * tar_items.size());
+  const size_t o_ri = off;
+  off = align(off + sizeof(int4) * ref_items.size());
   const size_t o_heads = off;
   off = align(off + sizeof(int) * (1 + kAggQueues));
   const size_t o_qbeg = off;
@@ -533,6 +630,12 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   if ((e = hipMemcpy(base + o_ci, cost_items.data(), sizeof(int4) * cost_items.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
+  if (!tar_items.empty() && (e = hipMemcpy(base + o_ti, tar_items.data(), sizeof(int4) * tar_items.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if (!ref_items.empty() && (e = hipMemcpy(base + o_ri, ref_items.data(), sizeof(int4) * ref_items.size(),
+                                            hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
   if ((e = hipMemcpy(base + o_ai, agg_items.data(), sizeof(int4) * agg_items.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
@@ -552,6 +655,12 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   if ((e = hipFuncSetAttribute(ck, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(cost_lds))) !=
       hipSuccess)
     return fail(e);
+  if (tk && (e = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(tar_lds))) != hipSuccess)
+    return fail(e);
+  if (rk && (e = hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(ref_lds))) != hipSuccess)
+    return fail(e);
   if ((e = hipFuncSetAttribute(ak, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(agg_lds))) !=
       hipSuccess)
     return fail(e);
@@ -570,7 +679,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   const int apc = tn.agg_blocks_per_cu > 0 ? std::min(tn.agg_blocks_per_cu, agg_fit) : agg_fit;
   plan->cost_grid = cost_grid_mode ? std::max(1, plan->n_cost_items)
                                    : std::min(cus * cpc, std::max(1, plan->n_cost_items));
-  plan->agg_grid = std::min(cus * apc, std::max(1, plan->n_agg_items));
+  plan->agg_grid = plan->n_agg_items > 0 ? std::min(cus * apc, plan->n_agg_items) : 0;
 
   const int* d_qbeg = reinterpret_cast<const int*>(base + o_qbeg);
   BatchArgs& ca = plan->cost_args;
@@ -587,8 +696,15 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   aa.qbeg = d_qbeg + 2;
   aa.nq = kAggQueues;
   aa.head = plan->d_heads + 1;
+  BatchArgs& ta = plan->tar_args;
+  ta = ca;
+  ta.items = reinterpret_cast<const int4*>(base + o_ti);
+  BatchArgs& ra = plan->ref_args;
+  ra = ca;
+  ra.items = reinterpret_cast<const int4*>(base + o_ri);
 
-  // graph: reset counters -> warp -> cost kernel -> aggregation + WTA kernel -> tail
+  // graph: reset counters -> warp -> cost kernel -> aggregation + WTA kernel ->
+  // target-tile kernel -> tail
   if ((e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
@@ -597,8 +713,18 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   batch_warp_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs);
   void* cargs[] = {&plan->cost_args};
   hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
-  void* aargs[] = {&plan->agg_args};
-  hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
+  if (plan->agg_grid > 0) {
+    void* aargs[] = {&plan->agg_args};
+    hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
+  }
+  if (plan->n_tar_items > 0) {
+    void* targs[] = {&plan->tar_args};
+    hipLaunchKernel(tk, dim3(plan->n_tar_items), dim3(1024), targs, tar_lds, plan->capture_stream);
+  }
+  if (plan->n_ref_items > 0) {
+    void* rargs[] = {&plan->ref_args};
+    hipLaunchKernel(rk, dim3(plan->n_ref_items), dim3(1024), rargs, ref_lds, plan->capture_stream);
+  }
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
   e = hipStreamEndCapture(plan->capture_stream, &plan->graph);
@@ -625,7 +751,7 @@ extern "C" int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items,
   if (!plan) return RSV_E_NULL;
   if (n_items) {
     n_items[0] = plan->n_cost_items;
-    n_items[1] = plan->n_agg_items;
+    n_items[1] = plan->n_agg_items + plan->n_tar_items + plan->n_ref_items;
   }
   if (grid_blocks) {
     grid_blocks[0] = plan->cost_grid;
