@@ -132,6 +132,29 @@ def test_batch_realistic_sizes_equal_plain(rsv_gpu):
     plan.close()
 
 
+@pytest.mark.parametrize("r,rho,shapes", [
+    (3, 6, [(37, 150, 31), (24, 70, 8)]),             # radius 6: every tile in the persistent kernel
+    (1, 2, [(20, 3, 5), (30, 90, 17), (9, 5, 4)])])  # widths below 4 there, the rest in the tile kernels
+def test_batch_persistent_path_equals_plain(rsv_gpu, r, rho, shapes):
+    rsv = rsv_gpu
+    from paper_1807_07433_amd.batch import BatchPlan
+    prm = synth.MethodParams(D=0, block_radius=r, agg_radius=rho, gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
+    cases = [synth.small_case(H, W, D, r, rho, 960 + k, plane_a=0.07, plane_b=4.0 + k,
+                              gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
+             for k, (H, W, D) in enumerate(shapes)]
+    pairs = _pairs(cases)
+    _say(f"[batch] r={r} rho={rho} shapes {shapes}")
+    plan = BatchPlan(pairs, prm)
+    _say(f"  plan {plan.info()}")
+    plan.run()
+    torch.cuda.synchronize()
+    for i, (pair, c) in enumerate(zip(pairs, cases)):
+        left, right, plane, cam, D = pair
+        p = rsv.StereoParams(D=D, block_radius=r, agg_radius=rho, gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
+        _check_equal(f"pair {i}", plan.outputs[i], rsv.reconstruct(left, right, plane, cam, p))
+    plan.close()
+
+
 @pytest.mark.parametrize("largest_first,tiles,cpc", [(0, 1, 0), (1, 4, 2), (1, 3, 1), (1, 4, -1)])
 def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc):
     rsv = rsv_gpu
