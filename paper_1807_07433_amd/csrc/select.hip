@@ -1,13 +1,14 @@
-// rsv_select_subpixel: winner-take-all on both aggregated volumes (Sec. II-B.3),
-// the left-right consistency check (Sec. II-B.4, Eq. 11) and the parabola subpixel
-// refinement (Eq. 12).
+// rsv_select_subpixel, rsv_select_subpixel_ref: winner-take-all on the aggregated
+// volumes (Sec. II-B.3), the left-right consistency check (Sec. II-B.4, Eq. 11) and
+// the parabola subpixel refinement (Eq. 12).
 //
 // Two launches: a scan kernel in which each thread walks d for one pixel in both
-// aggregated volumes at once (coalesced loads across the row, 256-pixel row segments
-// per block), keeping the target argmax and, for the reference volume, the best,
-// second best and the neighbours of the running best (ties go to the lowest d);
-// then the left-right check on the two disparity maps, which reads the target
-// disparity at u - d of any segment once every scan has finished.
+// aggregated volumes at once, or in the reference volume only when the target
+// disparities are given (coalesced loads across the row, 256-pixel row segments per
+// block), keeping the target argmax and, for the reference volume, the best, second
+// best and the neighbours of the running best (ties go to the lowest d); then the
+// left-right check on the two disparity maps, which reads the target disparity at
+// u - d of any segment once every scan has finished.
 #include <math.h>
 
 #include "select_math.hpp"
