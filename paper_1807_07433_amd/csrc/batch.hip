@@ -212,7 +212,7 @@ __device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, f
   const CostOut out = cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D);
   for (int ct = c0; ct < last; ++ct) {
     if (ct > c0) __syncthreads();  // LDS is reused by the next tile
-    cost_tile<R, kBandRows>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
+    cost_tile<R, kBandRows, false>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
                             out, cwork);
   }
 }
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_
   const float* warped = uniform(pd->warped);
   const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
   auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
-  cost_tile<R, kBandRows>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
+  cost_tile<R, kBandRows, false>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
                           uniform(w.w) * kCostTW, uniform(w.z) * kBandRows,
                           cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D), cwork);
 }

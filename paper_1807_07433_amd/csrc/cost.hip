@@ -10,13 +10,13 @@ namespace rsv {
 
 constexpr int kCostTH = 4;
 
-template <int R, typename TL>
+template <int R, typename TL, bool TAR>
 __global__ __launch_bounds__(kCostTW* kCostTH, R <= 3 ? 4 : 1) void cost_volume_kernel(
     const TL* __restrict__ left, int64_t lpitch, const float* __restrict__ warped, int H, int W,
     int D, float sigma_min, CostOut out) {
   extern __shared__ float smem[];
   auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
-  cost_tile<R, kCostTH>(left, lpitch, warped_at, H, W, D, sigma_min, blockIdx.x * kCostTW,
+  cost_tile<R, kCostTH, TAR>(left, lpitch, warped_at, H, W, D, sigma_min, blockIdx.x * kCostTW,
                         blockIdx.y * kCostTH, out, smem);
 }
 
@@ -27,7 +27,7 @@ int launch_cost(const rsv_image& left, const float* warped, const rsv_params* p,
   const size_t lds = sizeof(float) * cost_tile_lds_floats(D, R, kCostTH);
   const dim3 block(kCostTW * kCostTH);
   const dim3 grid((W + D - 1 + kCostTW - 1) / kCostTW, (H + kCostTH - 1) / kCostTH);
-  auto kern = cost_volume_kernel<R, TL>;
+  auto kern = out.tar ? cost_volume_kernel<R, TL, true> : cost_volume_kernel<R, TL, false>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,

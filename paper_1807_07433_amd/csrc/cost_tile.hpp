@@ -15,6 +15,8 @@
 // stride is a compile-time constant so the column reads use immediate offsets.
 #pragma once
 
+#include <type_traits>
+
 #include "zncc_math.hpp"
 
 namespace rsv {
@@ -53,8 +55,9 @@ __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
   return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1);
 }
 
-// warped_at(y, x) returns the warped target at in-image (y, x).
-template <int R, int TH, typename TL, typename WarpAt>
+// warped_at(y, x) returns the warped target at in-image (y, x).  TAR: out.tar may be
+// non-null (the dual layout); with TAR false the target stores are not compiled.
+template <int R, int TH, bool TAR, typename TL, typename WarpAt>
 __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t lpitch, WarpAt warped_at,
                                           int H, int W, int D, float sigma_min, int u0, int v0,
                                           const CostOut& out, float* smem) {
@@ -87,7 +90,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
     ir[i] = target_inv<R>(wt + r * wtw + c, wtw, sigma_min);
   }
 
-  LeftBlock<R> lb;
+  LeftBlock<R, std::is_same<TL, uint8_t>::value> lb;
   lb.load(lt + ty * ltw + tx, ltw, sigma_min);
   __syncthreads();
 
@@ -104,7 +107,7 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   const uint32_t roff = static_cast<uint32_t>(v) * out.ref_row + static_cast<uint32_t>(u);
   const uint32_t toff = static_cast<uint32_t>(v) * static_cast<uint32_t>(W) + static_cast<uint32_t>(u);
   const bool ref_ok = row_ok && u < out.ref_cols;
-  const bool tar_ok = row_ok && cost_tar != nullptr;
+  const bool tar_ok = TAR && row_ok && cost_tar != nullptr;
   const float* wrow = wt + ty * wtw + tx + (D - 1);  // window column k at step d: wrow[k - d]
   const float* irow = ir + ty * nt + tx + (D - 1);   // 1/e_r of centre u - d: irow[-d]
 
@@ -134,9 +137,11 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
 #pragma unroll
         for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
       const float c = (num * lb.inv) * irow[-d];
-      const int64_t pd = d * plane;
       if (ref_ok) (cost_ref + d * ref_plane)[roff] = c;
-      if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) (cost_tar + (pd - d))[toff] = c;
+      if constexpr (TAR) {
+        const int64_t pd = d * plane;
+        if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) (cost_tar + (pd - d))[toff] = c;
+      }
     }
   }
 }

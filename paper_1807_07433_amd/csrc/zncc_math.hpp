@@ -23,31 +23,52 @@ __device__ __forceinline__ float inv_block_norm(double n, double S, double Q, fl
 }
 
 // Left block of width K = 2R+1 read from a row-major tile: produces the centred
-// values n*l - S (FP32) and 1/e_l.
-template <int R>
+// values n*l - S (FP32) and 1/e_l.  INT: the tile holds integers in [0, 255] (a
+// uint8 image), so S, Q and n*l - S are exact in FP32 (all below 2^24) and equal
+// the FP64 sums bit for bit; otherwise they are formed in FP64.
+template <int R, bool INT>
 struct LeftBlock {
   static constexpr int K = 2 * R + 1;
   static constexpr int N = K * K;
+  static_assert(!INT || N * 255 * 255 < (1 << 24), "integer block sums must stay exact in FP32");
   float c[K][K];
   float inv;
 
   __device__ __forceinline__ void load(const float* tile, int stride, float sigma_min) {
-    double S = 0.0, Q = 0.0;
+    if constexpr (INT) {
+      float S = 0.f, Q = 0.f;
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+      for (int j = 0; j < K; ++j)
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const float x = tile[j * stride + k];
-        c[j][k] = x;
-        S += static_cast<double>(x);
-        Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
-      }
-    inv = inv_block_norm(static_cast<double>(N), S, Q, sigma_min);
+        for (int k = 0; k < K; ++k) {
+          const float x = tile[j * stride + k];
+          c[j][k] = x;
+          S += x;
+          Q = fmaf(x, x, Q);
+        }
+      inv = inv_block_norm(static_cast<double>(N), static_cast<double>(S), static_cast<double>(Q), sigma_min);
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+      for (int j = 0; j < K; ++j)
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        c[j][k] = static_cast<float>(static_cast<double>(N) * static_cast<double>(c[j][k]) - S);
+        for (int k = 0; k < K; ++k) c[j][k] = fmaf(static_cast<float>(N), c[j][k], -S);
+    } else {
+      double S = 0.0, Q = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float x = tile[j * stride + k];
+          c[j][k] = x;
+          S += static_cast<double>(x);
+          Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
+        }
+      inv = inv_block_norm(static_cast<double>(N), S, Q, sigma_min);
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          c[j][k] = static_cast<float>(static_cast<double>(N) * static_cast<double>(c[j][k]) - S);
+    }
   }
 };
 
