@@ -75,19 +75,22 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   float* ir = lt + rows * ltw;
   const int cw0 = u0 - (D - 1) - R;  // global column of warped tile column 0
 
-  for (int i = tid; i < rows * wtc; i += NT) {
-    const int r = i / wtc, c = i - r * wtc;
-    wt[r * wtw + c] = warped_at(clampi(v0 - R + r, 0, H - 1), clampi(cw0 + c, 0, W - 1)) - kWarpShift;
-  }
-  for (int i = tid; i < rows * ltw; i += NT) {
-    const int r = i / ltw, c = i - r * ltw;
-    lt[i] = pixel(left, lpitch, clampi(v0 - R + r, 0, H - 1), clampi(u0 - R + c, 0, W - 1));
+  // Thread (tx, ty) fills columns tx, tx + 64, ... of rows ty, ty + TH, ...
+  for (int r = ty; r < rows; r += TH) {
+    const int y = clampi(v0 - R + r, 0, H - 1);
+    for (int c = tx; c < wtc; c += kCostTW)
+      wt[r * wtw + c] = warped_at(y, clampi(cw0 + c, 0, W - 1)) - kWarpShift;
+    for (int c = tx; c < ltw; c += kCostTW)
+      lt[r * ltw + c] = pixel(left, lpitch, y, clampi(u0 - R + c, 0, W - 1));
   }
   __syncthreads();
-  // 1/e_r for target centres x = u0 - (D-1) + c, rows v0 + r.
-  for (int i = tid; i < TH * nt; i += NT) {
-    const int r = i / nt, c = i - r * nt;
-    ir[i] = target_inv<R>(wt + r * wtw + c, wtw, sigma_min);
+  // 1/e_r for target centres x = u0 - (D-1) + c, rows v0 + r, two rows per thread:
+  // thread t takes rows 2 (t / 128) and 2 (t / 128) + 1 of columns t % 128, + 128, ...
+  static_assert(TH % 2 == 0 && NT / (TH / 2) == 128, "target rows are taken in pairs");
+  {
+    const int r = 2 * (tid >> 7);
+    for (int c = tid & 127; c < nt; c += 128)
+      target_inv_pair<R>(wt + r * wtw + c, wtw, sigma_min, ir[r * nt + c], ir[(r + 1) * nt + c]);
   }
 
   LeftBlock<R, std::is_same<TL, uint8_t>::value> lb;

@@ -72,20 +72,32 @@ struct LeftBlock {
   }
 };
 
-// 1/e_r of the target block whose top-left corner is tile[0].
+// 1/e_r of two vertically adjacent target blocks: the one whose top-left corner is
+// tile[0] and the one a row below.  They share 2R rows, which are summed once.
 template <int R>
-__device__ __forceinline__ float target_inv(const float* tile, int stride, float sigma_min) {
+__device__ __forceinline__ void target_inv_pair(const float* tile, int stride, float sigma_min,
+                                                float& inv0, float& inv1) {
   constexpr int K = 2 * R + 1;
-  double S = 0.0, Q = 0.0;
+  double St = 0.0, Qt = 0.0, Sm = 0.0, Qm = 0.0, Sb = 0.0, Qb = 0.0;
 #pragma unroll
-  for (int j = 0; j < K; ++j)
+  for (int k = 0; k < K; ++k) {
+    const double t = static_cast<double>(tile[k]);
+    const double b = static_cast<double>(tile[K * stride + k]);
+    St += t;
+    Qt = fma(t, t, Qt);
+    Sb += b;
+    Qb = fma(b, b, Qb);
+  }
+#pragma unroll
+  for (int j = 1; j < K; ++j)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double x = static_cast<double>(tile[j * stride + k]);
-      S += x;
-      Q = fma(x, x, Q);
+      Sm += x;
+      Qm = fma(x, x, Qm);
     }
-  return inv_block_norm(static_cast<double>(K * K), S, Q, sigma_min);
+  inv0 = inv_block_norm(static_cast<double>(K * K), St + Sm, Qt + Qm, sigma_min);
+  inv1 = inv_block_norm(static_cast<double>(K * K), Sm + Sb, Qm + Qb, sigma_min);
 }
 
 }  // namespace rsv
