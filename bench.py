@@ -68,8 +68,8 @@ def source_sha(paths):
 CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
 KERNEL_SOURCES = {
     "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
-    "aggregate": ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "fp16_split.hpp", "bilateral_math.hpp",
-                  "rsv_internal.hpp"],
+    "aggregate": ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
+                  "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"],
     "select_subpixel": ["select.hip", "select_math.hpp", "rsv_internal.hpp"],
 }
 
