@@ -94,6 +94,37 @@ def recorded_traffic(kernel: str, workload: str):
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
 PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 matrix, published
+# LDS: 128 B per clock per CU (the CDNA LDS width), 256 CUs at 2.4 GHz
+PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
+
+
+def agg_lds_bytes(W, H, D, rho):
+    """LDS bytes one aggregation launch moves, from the tile's design (16 x 16 outputs
+    per block, 16 waves of 4 x 4 patches, (16 + 2 rho) x 28 staged positions):
+    per 16-disparity tile, the raw fp32 tile written by the direct loads and read back
+    (rho <= 5 and W >= 4 only), the fp16 hi / lo planes written, each wave's B
+    fragments (2 + rho K-steps x hi, lo x 64 lanes x 16 B) and the output tile written
+    and read; per block, the guide and spatial-table reads of the weights (2 per
+    weight, 8 weights per lane and K-step)."""
+    ks = 2 + rho
+    raw = (16 + 2 * rho) * 28
+    dma = rho <= 5 and W >= 4
+    per_tile = (2 * 16 * raw * 4 if dma else 0) + 2 * 16 * raw * 2 + 16 * ks * 2 * 64 * 16 + 2 * 16 * 256 * 4
+    per_block = 1024 * ks * 8 * 2 * 4
+    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    return tiles * (((D + 15) // 16) * per_tile + per_block)
+
+
+def cost_lds_bytes(W, H, D, r):
+    """LDS bytes one cost launch moves, from the tile's design (64 centres x 4 rows per
+    block, centres u < W + D - 1): per entry, one new window column (2r + 1 floats) and
+    1/e_r of the target centre; per block, the tile fills, the target statistics (a pair
+    of rows reads 2r + 2 rows of 2r + 1) and the left blocks."""
+    k = 2 * r + 1
+    bx, by = (W + D - 1 + 63) // 64, (H + 3) // 4
+    rows, wtc, ltw, nt = 4 + 2 * r, 64 + D - 1 + 2 * r, 64 + 2 * r, 64 + D - 1
+    per_block = 4 * (256 * D * (k + 1) + rows * (wtc + ltw) + 2 * nt * ((k + 1) * k + 2) + 256 * k * k)
+    return bx * by * per_block
 
 
 def kernel_rooflines(stage_ms, W, H, D, prm):
@@ -108,16 +139,25 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
                    it issues (3 split-fp16 MFMAs per K-step, padded window union)
                    against the fp16 matrix peak;
       select:      HBM, reads the reference aggregated volume, 4 B per entry (the
-                   target volume is reduced to its argmax inside its aggregation)."""
+                   target volume is reduced to its argmax inside its aggregation).
+    The cost and aggregation kernels also carry their LDS traffic (agg_lds_bytes,
+    cost_lds_bytes) against the LDS peak."""
     n = W * H * D
     m = (2 * prm.agg_radius + 1) ** 2
     out = {}
     joint_bytes = 4 * H * (D * W + D * (D - 1) // 2)
+    def lds_view(nbytes, ms):
+        tbs = nbytes / (ms * 1e-3) / 1e12
+        return {"bytes_per_launch": nbytes, "achieved_tbs": round(tbs, 2), "peak_tbs": round(PEAK_LDS_TBS, 1),
+                "frac": round(tbs / PEAK_LDS_TBS, 4)}
+
     for k, nbytes in (("cost_volume", joint_bytes), ("select_subpixel", 4 * n)):
         ms = stage_ms[k]
         gbs = nbytes / (ms * 1e-3) / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes, "ms": round(ms, 5)}
+    out["cost_volume"]["lds_view"] = lds_view(cost_lds_bytes(W, H, D, prm.block_radius),
+                                              stage_ms["cost_volume"])
     ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
     flops = (2 * m + 2) * n
     tf = flops / (ms * 1e-3) / 1e12
@@ -131,7 +171,8 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
                         "hbm_view": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)},
                         "mfma_view": {"issued_flops_per_launch": issued, "achieved_tflops": round(itf, 1),
                                       "peak": PEAK_FP16_MFMA_TFLOPS,
-                                      "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)}}
+                                      "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)},
+                        "lds_view": lds_view(agg_lds_bytes(W, H, D, prm.agg_radius), ms)}
     return out
 
 

@@ -23,6 +23,7 @@ def test_kernel_roofline_units():
     entry, m = (2 rho + 1)^2."""
     class P:
         agg_radius = 5
+        block_radius = 3
     st = {"cost_volume": 0.1, "aggregate_ref": 0.2, "aggregate_tar": 0.2, "select_subpixel": 0.05}
     k = bench.kernel_rooflines(st, 1280, 720, 64, P)
     n = 1280 * 720 * 64
@@ -43,3 +44,23 @@ def test_kernel_sha_covers_every_source():
         for f in files:
             assert os.path.exists(os.path.join(bench.CSRC, f)), (kernel, f)
         assert len(bench.kernel_sha(kernel)) == 16
+
+
+def test_lds_traffic_of_the_tiles():
+    """LDS bytes from the tiles' design, counted by hand for 1280x720, D = 64.
+    Aggregation, rho = 5: 26 x 28 staged positions; per 16-disparity tile the raw fp32
+    tile written and read (2 x 16 x 728 x 4 B), the hi / lo planes (2 x 16 x 728 x 2 B),
+    16 waves' B fragments (7 K-steps x 2 planes x 64 lanes x 16 B) and the output tile
+    written and read (2 x 16 x 256 x 4 B); per block 56 weights per lane, two 4-byte
+    reads each.  Without the direct loads (rho = 6) the raw term is absent."""
+    per_tile = 2 * 16 * 728 * 4 + 2 * 16 * 728 * 2 + 16 * 7 * 2 * 64 * 16 + 2 * 16 * 256 * 4
+    assert per_tile == 401920
+    assert bench.agg_lds_bytes(1280, 720, 64, 5) == 80 * 45 * (4 * per_tile + 1024 * 56 * 2 * 4)
+    raw6 = 28 * 28
+    tile6 = 2 * 16 * raw6 * 2 + 16 * 8 * 2 * 64 * 16 + 2 * 16 * 256 * 4
+    assert bench.agg_lds_bytes(1280, 720, 64, 6) == 80 * 45 * (4 * tile6 + 1024 * 8 * 8 * 2 * 4)
+    # cost, r = 3, 21 x 180 blocks of 64 x 4 centres: per entry a window column of 7 and
+    # 1/e_r; per block the fills (10 rows of 133 warped + 70 left columns), two row
+    # pairs x 127 target centres reading 8 x 7 values and writing 2, 256 left blocks of 49
+    per_block = 256 * 64 * 8 + 10 * (133 + 70) + 2 * 127 * (8 * 7 + 2) + 256 * 49
+    assert bench.cost_lds_bytes(1280, 720, 64, 3) == 21 * 180 * 4 * per_block
