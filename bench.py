@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable form")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed plain frame")
     ap.add_argument("--diff-pairs", type=int, default=8)
     ap.add_argument("--diff-reps", type=int, default=10)
     ap.add_argument("--diff-steps", type=int, default=50)
@@ -316,6 +317,34 @@ def bench_diff(a, rsv, torch):
             "objective": [round(hist[0], 6), round(hist[-1], 6)]}
 
 
+def plain_graph(torch, step, steps, outputs):
+    """The plain frame captured once as a graph (HIP graph under ROCm) and replayed:
+    the same kernels on the same buffers without per-launch host work.  Checks that
+    a replay reproduces the eager frame's outputs bit for bit."""
+    eager = [t.clone() for t in outputs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()  # default priority
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        step()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(torch.nan_to_num(x), torch.nan_to_num(y)) for x, y in zip(outputs, eager))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": round(ms, 5), "fps": round(1000.0 / ms, 2), "replay_equals_eager": same}
+
+
 def cpu_baseline(case, rows: int):
     """The FP64 oracle, as it stands, on a band of `rows` full-width rows of the same pair
     (same D and windows): warp -> both volumes -> both aggregations -> select -> 3-D."""
@@ -417,6 +446,7 @@ def main():
     t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
     mde = mde_per_s(W, H, D, t_ca * 1e-3)          # the metric: cost + both aggregations
     mde_frame = mde_per_s(W, H, D, ms_step * 1e-3)  # whole frame, warp to 3-D points
+    graph = None if a.no_graph else plain_graph(torch, step, a.steps, (sel["disp_sub"], sel["valid"], xyz))
     kernels = kernel_rooflines(stage_ms, W, H, D, prm)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     roof = {k: v for k, v in kernels[dom].items() if k in ("bound", "achieved", "peak", "unit", "frac")}
@@ -451,6 +481,8 @@ def main():
         "kernels": kernels,
         "library": _lib.LIB_PATH,
     }
+    if graph is not None:
+        out["plain_graph"] = graph
     if a.copy_calibration:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

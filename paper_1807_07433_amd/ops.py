@@ -193,12 +193,13 @@ def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor | None, params,
         raise ValueError("without agg_tar, out['disp_tar'] must hold the target disparities")
     dev = agg_ref.device
     o = dict(out) if out else {}
-    o.setdefault("disp_ref", torch.empty((H, W), dtype=torch.int32, device=dev))
-    o.setdefault("disp_tar", torch.empty((H, W), dtype=torch.int32, device=dev))
-    o.setdefault("disp_sub", torch.empty((H, W), dtype=torch.float32, device=dev))
-    o.setdefault("valid", torch.empty((H, W), dtype=torch.uint8, device=dev))
+    shapes = {"disp_ref": ((H, W), torch.int32), "disp_tar": ((H, W), torch.int32),
+              "disp_sub": ((H, W), torch.float32), "valid": ((H, W), torch.uint8)}
     if want_top2:
-        o.setdefault("top2", torch.empty((2, H, W), dtype=torch.float32, device=dev))
+        shapes["top2"] = ((2, H, W), torch.float32)
+    for k, (shp, dt) in shapes.items():
+        if k not in o:  # allocate only what the caller did not pass
+            o[k] = torch.empty(shp, dtype=dt, device=dev)
     _contig(o["disp_ref"], "disp_ref", torch.int32, (H, W))
     _contig(o["disp_tar"], "disp_tar", torch.int32, (H, W))
     _contig(o["disp_sub"], "disp_sub", torch.float32, (H, W))

@@ -232,6 +232,67 @@ def test_rerun_is_bitwise_deterministic(rsv_gpu):
         assert torch.equal(a[k].nan_to_num(), b[k].nan_to_num()), k
 
 
+def test_plain_frame_graph_replays_equal_eager(rsv_gpu):
+    """The plain frame (warp, joint cost volume, reference aggregation, target argmax,
+    selection, 3-D points) captured as one graph: every replay, with eager work and
+    synchronisations between replays and the outputs cleared before each, reproduces
+    the eager frame bit for bit."""
+    rsv = rsv_gpu
+    case = synth.road320_d32()
+    prm = case.params
+    L, R = _gpu(case.pair.left), _gpu(case.pair.right)
+    H, W = L.shape
+    D = prm.D
+    cam = _camera(case)
+    f32 = dict(dtype=torch.float32, device="cuda")
+    wp = torch.empty((H, W), **f32)
+    joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
+    cref, ctar = rsv.joint_views(joint, W)
+    aref = torch.empty((D, H, W), **f32)
+    sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device="cuda"),
+           "disp_tar": torch.empty((H, W), dtype=torch.int32, device="cuda"),
+           "disp_sub": torch.empty((H, W), **f32),
+           "valid": torch.empty((H, W), dtype=torch.uint8, device="cuda")}
+    dfin = torch.empty((H, W), **f32)
+    xyz = torch.empty((H, W, 3), **f32)
+    outs = [sel["disp_ref"], sel["disp_tar"], sel["disp_sub"], sel["valid"], dfin, xyz]
+
+    def frame():
+        rsv.warp(R, case.plane, out=wp)
+        rsv.cost_volume_joint(L, wp, prm, out=joint)
+        rsv.aggregate(cref, L, prm, out=aref)
+        rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
+        rsv.select_subpixel(aref, None, prm, out=sel)
+        rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
+
+    _say("[graph] eager frame, 320x180 D=32")
+    frame()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        frame()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    _say("[graph] capture")
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        frame()
+    other = rsv.reconstruct(_gpu(case.pair.right), _gpu(case.pair.left), case.plane, cam, prm)
+    for i in range(3):
+        _say(f"[graph] replay {i}")
+        for t in outs:
+            t.zero_()
+        rsv.reconstruct(_gpu(case.pair.right), _gpu(case.pair.left), case.plane, cam, prm)  # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (x, y) in enumerate(zip(outs, eager)):
+            assert torch.equal(x.nan_to_num(), y.nan_to_num()), (i, k)
+    assert other["disp_sub"].shape == (H, W)
+
+
 # ------------------------------------------------------------------ full size, sampled
 def _agg_columns(cost_at, guide, us, vs, D, prm, chunk=8):
     """Oracle aggregated values at every d for each sampled pixel: [n, D]."""
