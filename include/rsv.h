@@ -23,6 +23,9 @@
  *   - Arguments are validated on the host before anything is launched; a call
  *     that returns an error has launched nothing.  Kernel faults surface at the
  *     caller's next synchronisation.  Stateless calls are re-entrant.
+ *   - Stateless calls launch kernels only: no memset, copy, allocation or
+ *     synchronisation, so a sequence of them may be captured into a HIP graph on
+ *     `stream` and replayed (the buffers are bound at capture).
  *   - Return value: RSV_OK (0) or a negative rsv_status.
  */
 #ifndef RSV_H_
