@@ -95,8 +95,9 @@ def recorded_traffic(kernel: str, workload: str):
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
 PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense fp16 matrix, published
-# LDS: 128 B per clock per CU (the CDNA LDS width), 256 CUs at 2.4 GHz
-PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
+# LDS reads: 256 B per clock per CU on CDNA4 (the probe in libprobe.so measures
+# ~150 TB/s with 16-byte loads), 256 CUs at 2.4 GHz
+PEAK_LDS_TBS = 256 * 256 * 2.4e9 / 1e12
 
 
 def agg_lds_bytes(W, H, D, rho):
@@ -317,6 +318,37 @@ def bench_diff(a, rsv, torch):
             "objective": [round(hist[0], 6), round(hist[-1], 6)]}
 
 
+def lds_probe(torch):
+    """Measured LDS read bandwidth (libprobe.so): 2048 blocks of 256 threads, each
+    thread 512 iterations of 128 bytes in conflict-free 8- or 16-byte LDS loads, timed
+    with HIP events."""
+    import ctypes as C
+    from paper_1807_07433_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        return None
+    lib = C.CDLL(B.PROBE_LIB)
+    fn = lib.rsv_probe_lds_read
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    blocks, iters = 2048, 512
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for width in (8, 16):
+        if fn(width, blocks, iters, out.data_ptr(), st) != 0:
+            return None
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn(width, blocks, iters, out.data_ptr(), st)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[f"b{8 * width}_tbs"] = round(blocks * 256 * iters * 128 / (ms * 1e-3) / 1e12, 2)
+    res["peak_tbs"] = round(PEAK_LDS_TBS, 1)
+    return res
+
+
 def plain_graph(torch, step, steps, outputs):
     """The plain frame captured once as a graph (HIP graph under ROCm) and replayed:
     the same kernels on the same buffers without per-launch host work.  Checks that
@@ -447,7 +479,14 @@ def main():
     mde = mde_per_s(W, H, D, t_ca * 1e-3)          # the metric: cost + both aggregations
     mde_frame = mde_per_s(W, H, D, ms_step * 1e-3)  # whole frame, warp to 3-D points
     graph = None if a.no_graph else plain_graph(torch, step, a.steps, (sel["disp_sub"], sel["valid"], xyz))
+    probe = lds_probe(torch)
     kernels = kernel_rooflines(stage_ms, W, H, D, prm)
+    if probe:
+        measured = max(probe["b64_tbs"], probe["b128_tbs"])
+        for k in ("cost_volume", "aggregate"):
+            v = kernels[k]["lds_view"]
+            v["measured_peak_tbs"] = measured
+            v["frac_of_measured"] = round(v["achieved_tbs"] / measured, 4)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     roof = {k: v for k, v in kernels[dom].items() if k in ("bound", "achieved", "peak", "unit", "frac")}
     roof["traffic"] = recorded_traffic(dom, a.workload)
@@ -483,6 +522,8 @@ def main():
     }
     if graph is not None:
         out["plain_graph"] = graph
+    if probe:
+        out["lds_probe"] = probe
     if a.copy_calibration:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -20,6 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsv.so")
+PROBE_LIB = os.path.join(PKG, "libprobe.so")
 ARCH = "gfx950"
 
 COMMON = [
@@ -76,7 +77,24 @@ def build(jobs: int | None = None, asm: bool = False, verbose: bool = True) -> s
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} from {len(srcs)} sources")
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = True) -> str:
+    """libprobe.so: the LDS bandwidth probe that bench.py measures the LDS peak with
+    (measurement only; librsv.so does not use it)."""
+    src = os.path.join(PKG, "probe", "lds_probe.hip")
+    obj = os.path.join(BUILD, "lds_probe.hip.o")
+    for cmd in ([hipcc(), *COMMON, "-c", src, "-o", obj],
+                [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", PROBE_LIB + ".tmp"]):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
 
 
 def main(argv=None):

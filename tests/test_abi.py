@@ -182,3 +182,19 @@ def test_argmax_and_select_ref_validation(lib):
                                        FAKE, None, None) == -3
     # the full form still needs its target volume
     assert lib.rsv_select_subpixel(FAKE, None, 32, 48, C.byref(p), FAKE, FAKE, FAKE, FAKE, None, None) == -1
+
+
+def test_lds_probe_library_loads_and_rejects_bad_arguments():
+    """libprobe.so (the LDS bandwidth probe bench.py uses) is built beside librsv.so,
+    exports its entry point and rejects bad arguments before launching anything."""
+    from paper_1807_07433_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        pytest.fail("libprobe.so is not built; run __graft_entry__.build()")
+    probe = C.CDLL(B.PROBE_LIB)
+    fn = probe.rsv_probe_lds_read
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    assert fn(12, 1, 1, FAKE, None) == -1   # width must be 8 or 16
+    assert fn(16, 0, 1, FAKE, None) == -1   # at least one block
+    assert fn(16, 1, 0, FAKE, None) == -1   # at least one iteration
+    assert fn(8, 1, 1, None, None) == -1    # output buffer required
