@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable form")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed plain frame")
+    ap.add_argument("--no-lds-probe", action="store_true", help="skip the LDS bandwidth probe")
     ap.add_argument("--diff-pairs", type=int, default=8)
     ap.add_argument("--diff-reps", type=int, default=10)
     ap.add_argument("--diff-steps", type=int, default=50)
@@ -479,7 +480,7 @@ def main():
     mde = mde_per_s(W, H, D, t_ca * 1e-3)          # the metric: cost + both aggregations
     mde_frame = mde_per_s(W, H, D, ms_step * 1e-3)  # whole frame, warp to 3-D points
     graph = None if a.no_graph else plain_graph(torch, step, a.steps, (sel["disp_sub"], sel["valid"], xyz))
-    probe = lds_probe(torch)
+    probe = None if a.no_lds_probe else lds_probe(torch)
     kernels = kernel_rooflines(stage_ms, W, H, D, prm)
     if probe:
         measured = max(probe["b64_tbs"], probe["b128_tbs"])
