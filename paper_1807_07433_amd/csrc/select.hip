@@ -22,7 +22,7 @@ constexpr int kSelUnroll = 16;
 // reference volume only): loads run ahead of the compare chains in chunks of
 // kSelUnroll, then of 4, then singly.  Every value is read once, so the loads are
 // non-temporal.
-template <bool TAR>
+template <bool TAR, bool TOP2>
 __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const float* __restrict__ pt,
                                           int64_t plane, int D, Scan& s, int& targ) {
   bool need_next = false;
@@ -34,7 +34,7 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
       tbest = b;
       targ = 0;
     } else {
-      scan_step(s, need_next, prev, a, d);
+      scan_step<TOP2>(s, need_next, prev, a, d);
       if (TAR && b > tbest) {
         tbest = b;
         targ = d;
@@ -66,8 +66,9 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
   for (; d < D; ++d) consume(__builtin_nontemporal_load(pr + d * plane), load_t(d), d);
 }
 
-// TAR: scan the target volume too and write dtar; otherwise dtar is an input.
-template <bool TAR>
+// TAR: scan the target volume too and write dtar; otherwise dtar is an input.  TOP2:
+// write the best and second-best values to top2.
+template <bool TAR, bool TOP2>
 __global__ __launch_bounds__(kSelThreads) void select_scan_kernel(
     const float* __restrict__ aref, const float* __restrict__ atar, int H, int W, int D,
     int32_t* __restrict__ dref, int32_t* __restrict__ dtar, float* __restrict__ dsub,
@@ -79,11 +80,11 @@ __global__ __launch_bounds__(kSelThreads) void select_scan_kernel(
   const int64_t i = static_cast<int64_t>(v) * W + u;
   Scan s;
   int ta;
-  scan_pair<TAR>(aref + i, TAR ? atar + i : nullptr, plane, D, s, ta);
+  scan_pair<TAR, TOP2>(aref + i, TAR ? atar + i : nullptr, plane, D, s, ta);
   dref[i] = s.arg;
   if (TAR) dtar[i] = ta;
   dsub[i] = parabola(s.arg, s.best, s.am, s.ap, D);
-  if (top2) {
+  if (TOP2) {
     top2[i] = s.best;
     top2[plane + i] = s.second;
   }
@@ -117,12 +118,10 @@ int run_select(const float* agg_ref, const float* agg_tar, int32_t height, int32
       !aligned(disp_tar, 4) || !aligned(disp_sub, 4) || (top2 && !aligned(top2, 4)))
     return RSV_E_ALIGN;
   const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
-  if (agg_tar)
-    select_scan_kernel<true><<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(
-        agg_ref, agg_tar, height, width, p->D, disp_ref, disp_tar, disp_sub, top2);
-  else
-    select_scan_kernel<false><<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(
-        agg_ref, nullptr, height, width, p->D, disp_ref, disp_tar, disp_sub, top2);
+  auto kern = agg_tar ? (top2 ? select_scan_kernel<true, true> : select_scan_kernel<true, false>)
+                      : (top2 ? select_scan_kernel<false, true> : select_scan_kernel<false, false>);
+  kern<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(agg_ref, agg_tar, height, width, p->D, disp_ref,
+                                                          disp_tar, disp_sub, top2);
   if (int st = check_launch()) return st;
   lr_check_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(disp_ref, disp_tar, width,
                                                                     p->lr_threshold, valid);

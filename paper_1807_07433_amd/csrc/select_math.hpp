@@ -29,19 +29,21 @@ __device__ __forceinline__ void scan_init(Scan& s, bool& need_next, float& prev,
   prev = a;
 }
 
-// One step of the scan at disparity d >= 1 with value a.
+// One step of the scan at disparity d >= 1 with value a.  SECOND: also track the
+// second best (only the optional top-two output reads it).
+template <bool SECOND = true>
 __device__ __forceinline__ void scan_step(Scan& s, bool& need_next, float& prev, float a, int d) {
   if (need_next) {
     s.ap = a;
     need_next = false;
   }
   if (a > s.best) {
-    s.second = s.best;
+    if (SECOND) s.second = s.best;
     s.best = a;
     s.arg = d;
     s.am = prev;
     need_next = true;
-  } else if (a > s.second) {
+  } else if (SECOND && a > s.second) {
     s.second = a;
   }
   prev = a;
