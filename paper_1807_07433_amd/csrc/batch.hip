@@ -84,7 +84,7 @@ struct BatchArgs {
 // Scan state of the 256 pixels of one aggregation item, in LDS between disparity
 // tiles (kept out of registers, which the tile needs).
 struct WtaState {
-  float best[256], second[256], am[256], ap[256], prev[256];
+  float best[256], am[256], ap[256], prev[256];
   int arg[256], need_next[256];
 };
 
@@ -94,7 +94,8 @@ struct WtaState {
 struct WtaSink {
   WtaState* st;
   int D;
-  bool full;  // reference volume: best, second best and neighbours; target: argmax only
+  bool full;  // reference volume: best and its neighbours; target: argmax only (the
+              // batch has no top-two output, so no second best is kept)
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
     const int p = threadIdx.x;
@@ -106,7 +107,6 @@ struct WtaSink {
       s.best = st->best[p];
       s.arg = st->arg[p];
       if (full) {
-        s.second = st->second[p];
         s.am = st->am[p];
         s.ap = st->ap[p];
         prev = st->prev[p];
@@ -121,7 +121,7 @@ struct WtaSink {
         if (d == 0)
           scan_init(s, need_next, prev, a);
         else
-          scan_step(s, need_next, prev, a, d);
+          scan_step<false>(s, need_next, prev, a, d);
       } else if (d == 0 || a > s.best) {
         s.best = a;
         s.arg = d;
@@ -130,7 +130,6 @@ struct WtaSink {
     st->best[p] = s.best;
     st->arg[p] = s.arg;
     if (full) {
-      st->second[p] = s.second;
       st->am[p] = s.am;
       st->ap[p] = s.ap;
       st->prev[p] = prev;
