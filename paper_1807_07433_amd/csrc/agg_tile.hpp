@@ -49,10 +49,15 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
   const int x0 = bx - A - G::PAD;  // image column of tile column 0 (even)
 
   // Item q of this thread: disparity dd of the tile, chunk k = 4 columns of one row.
-  // meta = dd | in-image column mask << 4 (bit e: column X + e); eoff = dd * cps +
+  // meta = dd | in-image column mask << 4 (bit e: column X + e) | (offset of the
+  // chunk in the hi / lo planes + 1, 0 past the item list) << 8; eoff = dd * cps +
   // Y * crs + X, the element offset from the tile's first disparity plane (32-bit
-  // for cps and H * crs <= 2^26), added to a per-tile uniform base.
-  int eoff[SPT], ldso[SPT];
+  // for cps and H * crs <= 2^26), added to a per-tile uniform base.  The fetch and
+  // store steps read opaque copies of meta, so that the decisions derived from it are
+  // recomputed per tile rather than hoisted out of the tile loop as lane masks
+  // (which, at radius 6, spilled and were reloaded from scratch every tile).
+  static_assert(2 * 16 * G::PLANE + 1 < (1 << 24), "plane offset field");
+  int eoff[SPT];
   unsigned meta[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
@@ -64,9 +69,9 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
     if (it < NITEM && Y >= 0 && Y < H)
 #pragma unroll
       for (int e = 0; e < 4; ++e) m |= (X + e >= 0 && X + e < W) ? (1u << e) : 0u;
-    meta[q] = static_cast<unsigned>(dd) | (m << 4);
+    const unsigned ldso1 = it < NITEM ? static_cast<unsigned>(dd * G::PLANE + 4 * k) + 1u : 0u;
+    meta[q] = static_cast<unsigned>(dd) | (m << 4) | (ldso1 << 8);
     eoff[q] = m ? dd * static_cast<int>(cps) + Y * crs + X : 0;
-    ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
   float4_t pre[SPT];
   // The load form is chosen per wave (uniform branch): whole 4-column chunks as one
@@ -80,8 +85,10 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       float4_t v = {0.f, 0.f, 0.f, 0.f};
-      const unsigned m = meta[q] >> 4;
-      const unsigned mm = 16 * t + static_cast<int>(meta[q] & 15u) < D ? m : 0u;
+      unsigned mq = meta[q];
+      asm volatile("" : "+v"(mq));
+      const unsigned m = mq >> 4 & 15u;
+      const unsigned mm = 16 * t + static_cast<int>(mq & 15u) < D ? m : 0u;
       const float* p = base + eoff[q];  // column X of the chunk (X may be < 0 at the border)
       if (__all(mm == 0xFu)) {
         const float4_a4 a = *reinterpret_cast<const float4_a4*>(p);
@@ -101,9 +108,13 @@ __device__ __forceinline__ void agg_tile(const float* __restrict__ cost, int64_t
     for (int q = 0; q < SPT; ++q) {
       half4_t h, l;
       split4(pre[q], h, l);
-      const bool real = ldso[q] >= 0;
-      *reinterpret_cast<half4_t*>(real ? hi + buf * 16 * G::PLANE + ldso[q] : dummy) = h;
-      *reinterpret_cast<half4_t*>(real ? lo + buf * 16 * G::PLANE + ldso[q] : dummy) = l;
+      unsigned mq = meta[q];
+      asm volatile("" : "+v"(mq));
+      const unsigned ldso1 = mq >> 8;
+      const bool real = ldso1 != 0;
+      const int ldso = static_cast<int>(ldso1) - 1;
+      *reinterpret_cast<half4_t*>(real ? hi + buf * 16 * G::PLANE + ldso : dummy) = h;
+      *reinterpret_cast<half4_t*>(real ? lo + buf * 16 * G::PLANE + ldso : dummy) = l;
     }
   };
 

@@ -169,8 +169,13 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
       if (ldso[q] < 0) continue;
       const int it = tid + q * NT;
       float4_t v = *reinterpret_cast<const float4_t*>(raw + 4 * it);
-      const unsigned m = (16 * t + static_cast<int>(meta[q] & 15u) < D) ? (meta[q] >> 4 & 15u) : 0u;
-      const int sh = static_cast<int>(meta[q] >> 8) - 3;  // column X + e is loaded element e + sh
+      // An opaque copy of the item's metadata: the decisions below are recomputed from
+      // it on every tile.  Otherwise the compiler hoists them out of the tile loop as
+      // dozens of lane masks, which spill to VGPR lanes and are read back every tile.
+      unsigned mq = meta[q];
+      asm volatile("" : "+v"(mq));
+      const unsigned m = (16 * t + static_cast<int>(mq & 15u) < D) ? (mq >> 4 & 15u) : 0u;
+      const int sh = static_cast<int>(mq >> 8) - 3;  // column X + e is loaded element e + sh
       if (m != 0xFu || sh != 0) {
         float4_t w = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
