@@ -60,10 +60,14 @@ def mde_per_s(W: int, H: int, D: int, seconds: float) -> float:
 
 
 def source_sha(paths):
-    """sha256 (16 hex digits) over the sources that define a kernel, in order."""
+    """sha256 (16 hex digits) over the sources that define a kernel, in order, with
+    comments and whitespace removed (so editing a comment keeps a profile valid)."""
     h = hashlib.sha256()
     for p in paths:
-        h.update(open(p, "rb").read())
+        txt = open(p).read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(" ".join(txt.split()).encode())
     return h.hexdigest()[:16]
 
 

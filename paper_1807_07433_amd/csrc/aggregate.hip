@@ -1,10 +1,15 @@
-// rsv_aggregate: bilateral cost aggregation (Sec. II-B.2, Eq. 8-10).
+// rsv_aggregate, rsv_aggregate_strided, rsv_aggregate_argmax: bilateral cost
+// aggregation (Sec. II-B.2, Eq. 8-10) of a dense volume or of any strided view (e.g.
+// of the joint cost volume), writing the aggregated volume or only its argmax over d
+// (the target volume's use in Sec. II-B.3).
 //
 // The weights of Eq. 9-10 depend on the pixel pair only, never on d, so the
 // aggregation of a 4 x 4 patch over 16 disparities is a small matrix product with a
-// banded weight matrix, run on the matrix cores (agg_tile.hpp, aggregate_mfma.hpp).
-// Each block owns a kAggTileRows x 16 output tile and writes its aggregated values
-// plane by plane, one 16-disparity tile at a time.
+// banded weight matrix, run on the matrix cores (aggregate_mfma.hpp).  Each block
+// owns a 16 x 16 output tile.  Its cost tiles come into LDS by direct loads
+// (agg_tile_dma.hpp; rho <= 5, W >= 4) or through registers (agg_tile.hpp), and its
+// results leave one 16-disparity tile at a time through a sink: the volume's planes
+// (non-temporal stores) or the running argmax (argmax_sink.hpp).
 #include "agg_tile_dma.hpp"
 #include "argmax_sink.hpp"
 

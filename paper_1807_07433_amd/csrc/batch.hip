@@ -1,25 +1,28 @@
 // Batched form: many stereo pairs of uneven size and disparity range in one
 // hipGraph launch.
 //
-// A plan holds, per pair, the warped right image, the joint cost volume and the WTA
-// state, plus the work lists, and captures the graph
-//     reset counters -> warp -> cost kernel -> aggregate+WTA kernel ->
-//     target-tile kernel -> tail kernel.
+// A plan holds, per pair, the warped right image, the joint cost volume and the
+// selection maps, plus the work lists, and captures the graph
+//     reset counters -> warp -> cost kernel -> [persistent aggregation kernel] ->
+//     target-tile kernel -> reference-tile kernel -> tail kernel.
 //   warp: every pixel of every pair, with rsv_warp's arithmetic;
 //   cost items (pair, band of 4 rows, 64-centre column tiles): ZNCC with the
 //       arithmetic of rsv_cost_volume_joint (shared cost_tile), persistent over a
 //       work queue or one workgroup per tile;
-//   aggregation items (pair, 16 x 16 tile, reference volume; and target tiles the
-//       LDS-loaded tile cannot take): bilateral aggregation on the matrix cores with
-//       the arithmetic of rsv_aggregate (shared agg_tile) and winner-take-all folded
-//       in: each 16-disparity tile of aggregated values is fed, from LDS, through the
-//       select kernel's own scan step (running best, second best and the winner's
-//       neighbours, ties keep the lowest d).  The list is cut into 8 contiguous
-//       stretches, one queue per XCD (workgroups are dealt to the XCDs round-robin),
-//       so neighbouring tiles share an L2; a workgroup whose queue is empty takes
-//       items from the next queues, in chunks of 4 neighbours, one atomic per chunk;
-//   target tiles (rho <= 5, W >= 4): one workgroup per tile on the LDS-loaded tile,
-//       keeping only the argmax over d (rsv_aggregate_argmax's arithmetic).
+//   target and reference tiles (rho <= 5, W >= 4): one workgroup per (pair, 16 x 16
+//       tile) on the LDS-loaded tile (agg_tile_dma) reading views of the joint
+//       volume.  The target tile keeps only the argmax over d (rsv_aggregate_argmax's
+//       arithmetic); the reference tile feeds each 16-disparity tile of aggregated
+//       values, from LDS, through the select kernel's scan step (running best, its d
+//       and its neighbours, ties keep the lowest d), with the scan state in the LDS
+//       of the weight tables;
+//   the persistent kernel takes the tiles the LDS-loaded tile cannot (rho = 6 or
+//       W < 4), reference and target, on the register-staged tile (agg_tile), both
+//       through the scan sink (a target tile through its argmax part only).  Its list is cut into 8 contiguous stretches, one queue per XCD
+//       (workgroups are dealt to the XCDs round-robin), so neighbouring tiles share
+//       an L2; a workgroup whose queue is empty takes items from the next queues, in
+//       chunks of 4 neighbours, one atomic per chunk.  It is left out when its list
+//       is empty.
 // No aggregated volume is written.  The tail applies the left-right check (Eq. 11),
 // the parabola (Eq. 12), post-processing and triangulation per pixel, with the plain
 // path's functions.  Every output therefore equals the plain path's bit for bit.
