@@ -75,7 +75,7 @@ CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
 KERNEL_SOURCES = {
     "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
     "aggregate": ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
-                  "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"],
+                  "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"],
     "select_subpixel": ["select.hip", "select_math.hpp", "rsv_internal.hpp"],
 }
 
@@ -134,15 +134,18 @@ def cost_lds_bytes(W, H, D, r):
     return bx * by * per_block
 
 
-def kernel_rooflines(stage_ms, W, H, D, prm):
-    """Per-launch algorithmic work / average launch time for the three volume kernels,
-    each against the resource that bounds it at these sizes:
+def kernel_rooflines(stage_ms, W, H, D, prm, fused=False):
+    """Per-launch algorithmic work / average launch time for the volume kernels, each
+    against the resource that bounds it at these sizes (fused: the selection runs
+    inside the reference aggregation, so there is no select kernel):
       cost_volume: HBM, writes the joint volume that holds C_ref and C_tar (the
                    identity after Eq. 5): every distinct cost value once, 4 B each,
                    H (D W + D (D - 1) / 2) values (image reads are O(1/D));
       aggregate:   FP32 arithmetic, 2m + 2 FLOP per entry (m = (2 rho + 1)^2 weighted
                    terms, weight sum and normalisation), against the FP32 vector peak.
-                   Also reported: its HBM rate (8 B per entry) and the matrix-core work
+                   Also reported: its HBM rate (per launch, averaged over the two:
+                   4 B per entry read, plus 4 B written by an unfused reference
+                   launch) and the matrix-core work
                    it issues (3 split-fp16 MFMAs per K-step, padded window union)
                    against the fp16 matrix peak;
       select:      HBM, reads the reference aggregated volume, 4 B per entry (the
@@ -158,7 +161,8 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
         return {"bytes_per_launch": nbytes, "achieved_tbs": round(tbs, 2), "peak_tbs": round(PEAK_LDS_TBS, 1),
                 "frac": round(tbs / PEAK_LDS_TBS, 4)}
 
-    for k, nbytes in (("cost_volume", joint_bytes), ("select_subpixel", 4 * n)):
+    hbm_kernels = [("cost_volume", joint_bytes)] + ([] if fused else [("select_subpixel", 4 * n)])
+    for k, nbytes in hbm_kernels:
         ms = stage_ms[k]
         gbs = nbytes / (ms * 1e-3) / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -171,7 +175,7 @@ def kernel_rooflines(stage_ms, W, H, D, prm):
     tiles = ((W + 15) // 16) * ((H + 15) // 16)
     issued = tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
     itf = issued / (ms * 1e-3) / 1e12
-    gbs = 8 * n / (ms * 1e-3) / 1e9
+    gbs = (4 * n if fused else 6 * n) / (ms * 1e-3) / 1e9
     out["aggregate"] = {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
                         "flops_per_launch": flops, "ms": round(ms, 5),
@@ -238,9 +242,12 @@ def bench_batch(a, rsv, torch):
             rsv.warp(right, plane, out=o["wp"])
             rsv.cost_volume_joint(left, o["wp"], c.params, out=o["j"])
             cr, ct = rsv.joint_views(o["j"], left.shape[1])
-            rsv.aggregate(cr, left, c.params, out=ar)
             rsv.aggregate_argmax(ct, o["wp"], c.params, out=o["sel"]["disp_tar"])
-            rsv.select_subpixel(ar, None, c.params, out=o["sel"])
+            if rsv.aggregate_select_supported(left.shape[1], c.params):
+                rsv.aggregate_select(cr, left, c.params, o["sel"]["disp_tar"], out=o["sel"])
+            else:
+                rsv.aggregate(cr, left, c.params, out=ar)
+                rsv.select_subpixel(ar, None, c.params, out=o["sel"])
             rsv.triangulate(o["sel"]["disp_sub"], o["sel"]["valid"], plane, cam, out_disp=o["dfin"],
                             out_xyz=o["xyz"])
 
@@ -433,39 +440,49 @@ def main():
     wp = torch.empty((H, W), **f32)
     joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
     cref, ctar = rsv.joint_views(joint, W)  # both cost volumes, views of the joint one
-    aref = torch.empty((D, H, W), **f32)
+    aref = None if rsv.aggregate_select_supported(W, prm) else torch.empty((D, H, W), **f32)
     sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_tar": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_sub": torch.empty((H, W), **f32),
            "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
     dfin = torch.empty((H, W), **f32)
     xyz = torch.empty((H, W, 3), **f32)
-    stages = ["warp", "cost_volume", "aggregate_ref", "aggregate_tar", "select_subpixel",
-              "triangulate"]
+    # Where rsv_aggregate_select runs (radius <= 5), the selection is folded into the
+    # reference aggregation and no aggregated volume is written; the stage
+    # "aggregate_ref" then includes WTA, Eq. 11 and Eq. 12, and "select_subpixel" is
+    # empty.  Otherwise the reference volume is written and selected from.
+    fused = rsv.aggregate_select_supported(W, prm)
+    stages = ["warp", "cost_volume", "aggregate_tar", "aggregate_ref"] + \
+        ([] if fused else ["select_subpixel"]) + ["triangulate"]
 
     def step(ev=None):
-        def mark(i):
-            if ev is not None:
-                ev[i].record()
-        mark(0)
+        marks = iter(ev) if ev is not None else None
+
+        def mark():
+            if marks is not None:
+                next(marks).record()
+        mark()
         rsv.warp(R, case.plane, out=wp)
-        mark(1)
+        mark()
         rsv.cost_volume_joint(L, wp, prm, out=joint)
-        mark(2)
-        rsv.aggregate(cref, L, prm, out=aref)
-        mark(3)
+        mark()
         rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])  # the target volume only feeds its argmax
-        mark(4)
-        rsv.select_subpixel(aref, None, prm, out=sel)
-        mark(5)
+        mark()
+        if fused:
+            rsv.aggregate_select(cref, L, prm, sel["disp_tar"], out=sel)
+        else:
+            rsv.aggregate(cref, L, prm, out=aref)
+            mark()
+            rsv.select_subpixel(aref, None, prm, out=sel)
+        mark()
         rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
-        mark(6)
+        mark()
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(a.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(a.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -485,7 +502,7 @@ def main():
     mde_frame = mde_per_s(W, H, D, ms_step * 1e-3)  # whole frame, warp to 3-D points
     graph = None if a.no_graph else plain_graph(torch, step, a.steps, (sel["disp_sub"], sel["valid"], xyz))
     probe = None if a.no_lds_probe else lds_probe(torch)
-    kernels = kernel_rooflines(stage_ms, W, H, D, prm)
+    kernels = kernel_rooflines(stage_ms, W, H, D, prm, fused)
     if probe:
         measured = max(probe["b64_tbs"], probe["b128_tbs"])
         for k in ("cost_volume", "aggregate"):
@@ -514,10 +531,11 @@ def main():
                                f"NCC {2 * prm.block_radius + 1}x{2 * prm.block_radius + 1}, "
                                f"bilateral {2 * prm.agg_radius + 1}x{2 * prm.agg_radius + 1}",
                    "width": W, "height": H, "D": D, "parallelism": "single-gpu",
-                   "value_definition": "W*H*D / (cost volume + both aggregations) time, Eq. 13"},
+                   "value_definition": "W*H*D / (cost volume + both aggregations) time, Eq. 13",
+                   "selection": "folded into the reference aggregation" if fused else "separate kernel"},
         "fps": round(1000.0 / ms_step, 2),
         "mde_full_frame": round(mde_frame, 2),
-        "ms_per_step_median": round(float(sorted(sum(e[k].elapsed_time(e[k + 1]) for k in range(6))
+        "ms_per_step_median": round(float(sorted(sum(e[k].elapsed_time(e[k + 1]) for k in range(len(stages)))
                                                   for e in evs)[a.steps // 2]), 5),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "wall_s_timed": round(wall, 4),

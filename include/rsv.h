@@ -193,6 +193,24 @@ int rsv_select_subpixel_ref(const float* agg_ref, const int32_t* disp_tar, int32
                             int32_t width, const rsv_params* p, int32_t* disp_ref,
                             float* disp_sub, uint8_t* valid, float* top2, void* stream);
 
+/* The reference aggregation with the selection folded in (Sec. II-B.2 to II-B.4,
+ * Eq. 8-12): rsv_aggregate_strided's view aggregated with the guide, and per pixel
+ * the winner-take-all disparity, Eq. 12 on it and Eq. 11 against disp_tar, as the
+ * aggregation is computed; no aggregated volume is written.  Outputs equal those of
+ * rsv_aggregate_strided followed by rsv_select_subpixel_ref bit for bit.  Runs
+ * where the cost tiles are loaded straight into LDS: agg_radius <= 5 and W >= 4
+ * (callers fall back to those two calls otherwise).
+ *   cost(d, v, u) = cost[d*plane_stride + v*row_stride + u] (the reference view)
+ *   guide     the left image (u8 or f32)
+ *   disp_tar  int32 [H][W], read: the target disparities (rsv_aggregate_argmax),
+ *             complete before this call's work starts on the stream
+ *   disp_ref  out, int32 [H][W];  disp_sub out, float32 [H][W];  valid out, uint8 [H][W]
+ * Errors: as rsv_aggregate_strided and rsv_select_subpixel; RSV_E_PARAM also for
+ * agg_radius > 5, RSV_E_SHAPE also for W < 4. */
+int rsv_aggregate_select(const float* cost, int64_t plane_stride, int64_t row_stride,
+                         rsv_image guide, const rsv_params* p, const int32_t* disp_tar,
+                         int32_t* disp_ref, float* disp_sub, uint8_t* valid, void* stream);
+
 /* Post-processing (Sec. II-C) and 3-D reconstruction (Sec. II-D):
  *   disp_final = disp_sub + s(u - disp_sub, v)            (every pixel)
  *   xyz[v][u]  = (x, y, z), z = f*baseline/disp_final, x = (u-u0) z/f, y = (v-v0) z/f,

@@ -52,6 +52,8 @@ _SIGNATURES = {
     "rsv_aggregate": (C.c_int, [_P, Image, C.POINTER(Params), _P, _P]),
     "rsv_aggregate_strided": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P, _P]),
     "rsv_aggregate_argmax": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P, _P]),
+    "rsv_aggregate_select": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P, _P, _P, _P,
+                                       _P]),
     "rsv_select_subpixel": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(Params), _P, _P, _P,
                                       _P, _P, _P]),
     "rsv_select_subpixel_ref": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(Params), _P, _P, _P, _P,

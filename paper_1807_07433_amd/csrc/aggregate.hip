@@ -12,6 +12,7 @@
 // (non-temporal stores) or the running argmax (argmax_sink.hpp).
 #include "agg_tile_dma.hpp"
 #include "argmax_sink.hpp"
+#include "select_math.hpp"
 
 namespace rsv {
 
@@ -127,6 +128,68 @@ int launch_agg_dma(const float* cost, int64_t cps, int crs, const rsv_image& g, 
   return check_launch();
 }
 
+// The reference aggregation with the selection folded in: the LDS-loaded tile feeds
+// RefQuadSink, and each pixel's four lanes end with the winner (ties to the lowest
+// d), Eq. 12 on it and its neighbours, and Eq. 11 against the target map `dtar`
+// (complete before this launch), written as the select kernels write them.
+template <int A, typename TG>
+__global__ __launch_bounds__(1024) void aggregate_select_kernel(
+    const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
+    int H, int W, int D, BilateralK bk, int tau, const int32_t* __restrict__ dtar,
+    int32_t* __restrict__ dref, float* __restrict__ dsub, uint8_t* __restrict__ valid) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
+  auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
+  RefQuadSink sink{D};
+  agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem, lds_address(smem));
+  if ((threadIdx.x & 3) != 0) return;  // the four lanes of a pixel hold the same result
+  const int q = threadIdx.x >> 2;
+  const int Y = by + (q >> 4), X = bx + (q & 15);
+  if (Y >= H || X >= W) return;
+  const int64_t row = static_cast<int64_t>(Y) * W, i = row + X;
+  const int a = sink.arg, x = X - a;
+  dref[i] = a;
+  dsub[i] = parabola(a, sink.best, sink.am, sink.ap, D);
+  valid[i] = (x >= 0 && abs(a - dtar[row + (x < 0 ? 0 : x)]) <= tau) ? 1 : 0;
+}
+
+template <int A, typename TG>
+int launch_agg_select(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                      const int32_t* dtar, int32_t* dref, float* dsub, uint8_t* valid, hipStream_t st) {
+  if constexpr (agg_dma_fits<A>()) {
+    const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
+    const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+    const size_t lds = agg_tile_dma_lds_bytes<A>();
+    auto kern = aggregate_select_kernel<A, TG>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return RSV_E_HIP;
+    }
+    kern<<<dim3(tiles), dim3(1024), lds, st>>>(cost, cps, crs, static_cast<const TG*>(g.data), g.pitch, g.height,
+                                               g.width, p->D, bk, p->lr_threshold, dtar, dref, dsub, valid);
+    return check_launch();
+  } else {
+    return RSV_E_PARAM;  // the LDS-loaded tile does not fit this radius
+  }
+}
+
+template <typename TG>
+int dispatch_agg_select(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                        const int32_t* dtar, int32_t* dref, float* dsub, uint8_t* valid, hipStream_t st) {
+  switch (p->agg_radius) {
+    case 1: return launch_agg_select<1, TG>(cost, cps, crs, g, p, dtar, dref, dsub, valid, st);
+    case 2: return launch_agg_select<2, TG>(cost, cps, crs, g, p, dtar, dref, dsub, valid, st);
+    case 3: return launch_agg_select<3, TG>(cost, cps, crs, g, p, dtar, dref, dsub, valid, st);
+    case 4: return launch_agg_select<4, TG>(cost, cps, crs, g, p, dtar, dref, dsub, valid, st);
+    case 5: return launch_agg_select<5, TG>(cost, cps, crs, g, p, dtar, dref, dsub, valid, st);
+    default: return RSV_E_PARAM;
+  }
+}
+
 template <int A, typename TG, bool ARG>
 int launch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
                float* agg, int32_t* disp, hipStream_t st) {
@@ -207,4 +270,25 @@ extern "C" int rsv_aggregate_argmax(const float* cost, int64_t plane_stride, int
                                     rsv_image guide, const rsv_params* p, int32_t* disp, void* stream) {
   if (!disp) return RSV_E_NULL;
   return rsv::run_agg(cost, plane_stride, row_stride, guide, p, nullptr, disp, stream);
+}
+
+extern "C" int rsv_aggregate_select(const float* cost, int64_t plane_stride, int64_t row_stride, rsv_image guide,
+                                    const rsv_params* p, const int32_t* disp_tar, int32_t* disp_ref,
+                                    float* disp_sub, uint8_t* valid, void* stream) {
+  using namespace rsv;
+  if (int s = validate_image(guide)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (int s = validate_select_params(p)) return s;
+  if (!cost || !disp_tar || !disp_ref || !disp_sub || !valid) return RSV_E_NULL;
+  if (!aligned(cost, 4) || !aligned(disp_tar, 4) || !aligned(disp_ref, 4) || !aligned(disp_sub, 4))
+    return RSV_E_ALIGN;
+  if (p->agg_radius > 5) return RSV_E_PARAM;
+  if (guide.width < 4 || row_stride < guide.width || plane_stride < 1 || plane_stride > kAggMaxPixels ||
+      static_cast<int64_t>(guide.height - 1) * row_stride + guide.width > kAggMaxPixels)
+    return RSV_E_SHAPE;
+  hipStream_t st = as_stream(stream);
+  const int rs = static_cast<int>(row_stride);
+  if (guide.dtype == RSV_U8)
+    return dispatch_agg_select<uint8_t>(cost, plane_stride, rs, guide, p, disp_tar, disp_ref, disp_sub, valid, st);
+  return dispatch_agg_select<float>(cost, plane_stride, rs, guide, p, disp_tar, disp_ref, disp_sub, valid, st);
 }

@@ -180,6 +180,41 @@ def aggregate_argmax(cost: torch.Tensor, guide: torch.Tensor, params,
     return out
 
 
+def aggregate_select_supported(W: int, params) -> bool:
+    """Whether rsv_aggregate_select runs for this width and radius (agg_radius <= 5, W >= 4)."""
+    return int(params.agg_radius) <= 5 and W >= 4
+
+
+def aggregate_select(cost: torch.Tensor, guide: torch.Tensor, params, disp_tar: torch.Tensor,
+                     out: dict | None = None) -> dict:
+    """The reference aggregation with WTA, Eq. 12 and Eq. 11 (against disp_tar) folded
+    in (rsv_aggregate_select): disp_ref, disp_sub and valid, bit for bit those of
+    aggregate + select_subpixel(agg_ref, None), without the aggregated volume."""
+    lib = load()
+    D, H, W = cost.shape
+    _dev(cost, "cost", torch.float32, (int(params.D), H, W))
+    if tuple(guide.shape) != (H, W):
+        raise ValueError("guide must match the volume's H, W")
+    if cost.stride(2) != 1:
+        raise ValueError("cost views need unit column stride")
+    _contig(disp_tar, "disp_tar", torch.int32, (H, W))
+    dev = cost.device
+    o = dict(out) if out else {}
+    shapes = {"disp_ref": ((H, W), torch.int32), "disp_sub": ((H, W), torch.float32),
+              "valid": ((H, W), torch.uint8)}
+    for k, (shp, dt) in shapes.items():
+        if k not in o:
+            o[k] = torch.empty(shp, dtype=dt, device=dev)
+        _contig(o[k], k, dt, shp)
+    o["disp_tar"] = disp_tar
+    p = _params(params)
+    check(lib.rsv_aggregate_select(cost.data_ptr(), cost.stride(0), cost.stride(1), image(guide, "guide"),
+                                   C.byref(p), disp_tar.data_ptr(), o["disp_ref"].data_ptr(),
+                                   o["disp_sub"].data_ptr(), o["valid"].data_ptr(), _stream(dev)),
+          "rsv_aggregate_select")
+    return o
+
+
 def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor | None, params, want_top2: bool = False,
                     out: dict | None = None) -> dict:
     """WTA, left-right check and Eq. 12.  With agg_tar None, out["disp_tar"] must hold
@@ -286,18 +321,28 @@ def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_re
 
 
 def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
-                want_top2: bool = False, joint: bool = True, tar_volume: bool = True) -> dict:
+                want_top2: bool = False, joint: bool = True, tar_volume: bool = True,
+                ref_volume: bool = True) -> dict:
     """The plain path, one C-ABI call per stage on the current stream (Fig. 1):
     warp -> both cost volumes -> aggregation of each -> WTA + L-R + subpixel ->
     post-processing + 3-D points.  With joint=True the two cost volumes are views of
     one joint volume (rsv_cost_volume_joint); otherwise two dense volumes.  With
     tar_volume=False the target volume is reduced to its argmax as it is aggregated
-    (rsv_aggregate_argmax) and "agg_tar" is None; every other output is the same."""
+    (rsv_aggregate_argmax) and "agg_tar" is None.  With ref_volume=False as well (and
+    where rsv_aggregate_select runs, without top2) the selection is folded into the
+    reference aggregation and "agg_ref" is None.  Every other output is the same."""
     wp = warp(right, plane)
     if joint:
         cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
     else:
         cref, ctar = cost_volume(left, wp, params)
+    if not tar_volume and not ref_volume and not want_top2 and aggregate_select_supported(left.shape[1], params):
+        sel = aggregate_select(cref, left, params, aggregate_argmax(ctar, wp, params))
+        dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
+        out = dict(warped=wp, cost_ref=cref, cost_tar=ctar, agg_ref=None, agg_tar=None,
+                   disp_final=dfin, xyz=xyz)
+        out.update(sel)
+        return out
     aref = aggregate(cref, left, params)
     if tar_volume:
         atar = aggregate(ctar, wp, params)
@@ -314,5 +359,6 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
-           "joint_row_stride", "aggregate", "aggregate_argmax", "select_subpixel",
+           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select",
+           "aggregate_select_supported", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "cost_adjoint", "image", "load"]

@@ -184,6 +184,24 @@ def test_argmax_and_select_ref_validation(lib):
     assert lib.rsv_select_subpixel(FAKE, None, 32, 48, C.byref(p), FAKE, FAKE, FAKE, FAKE, None, None) == -1
 
 
+def test_aggregate_select_validation(lib):
+    """rsv_aggregate_select rejects bad arguments before launching: nulls, alignment,
+    strides, the radii the LDS-loaded tile cannot take, widths below 4, and select
+    parameters."""
+    p = _params()
+    A, B, Cc, Dd = FAKE, FAKE + 4096, FAKE + 8192, FAKE + 12288
+    f = lib.rsv_aggregate_select
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), None, B, Cc, Dd, None) == -1
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), B, None, Cc, Dd, None) == -1
+    assert f(None, 32 * 48, 48, _img(), C.byref(p), B, Cc, Dd, A, None) == -1
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), B + 2, Cc, Dd, A, None) == -5
+    assert f(A, 32 * 48, 47, _img(), C.byref(p), B, Cc, Dd, A, None) == -2        # row stride < W
+    assert f(A, 32 * 48, 48, _img(), C.byref(_params(agg_radius=6)), B, Cc, Dd, A, None) == -3
+    assert f(A, 32 * 3, 3, _img(w=3), C.byref(p), B, Cc, Dd, A, None) == -2      # W < 4
+    assert f(A, 32 * 48, 48, _img(), C.byref(_params(lr_threshold=-1)), B, Cc, Dd, A, None) == -3
+    assert f(A, 32 * 48, 48, _img(), C.byref(_params(gamma_r=0.0)), B, Cc, Dd, A, None) == -3
+
+
 def test_lds_probe_library_loads_and_rejects_bad_arguments():
     """libprobe.so (the LDS bandwidth probe bench.py uses) is built beside librsv.so,
     exports its entry point and rejects bad arguments before launching anything."""

@@ -130,6 +130,11 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
     sel_ref = rsv.select_subpixel(aref, None, prm, want_top2=True, out={"disp_tar": dt})
     for k in ("disp_ref", "disp_sub", "valid", "top2"):
         assert torch.equal(sel_ref[k], sel[k]), k
+    if rsv.aggregate_select_supported(W, prm):
+        _say("  rsv_aggregate_select (selection folded into the reference aggregation)")
+        fused = rsv.aggregate_select(jref, L, prm, dt)
+        for k in ("disp_ref", "disp_sub", "valid"):
+            assert torch.equal(fused[k], sel[k]), k
     top2 = P.to_np(sel["top2"])
     P.check_close("best", top2[0], ref["best"], P.AGG_TOL)
     if D > 1:
@@ -380,13 +385,21 @@ def _sampled_full(rsv, case, n_cost, n_agg, n_pix, seed):
 
 
 def _fused_target_matches(rsv, case, out):
-    """The plain path without a target volume gives the same maps, bit for bit."""
+    """The plain path without a target volume, and without either volume, gives the
+    same maps, bit for bit."""
     p = case.pair
     _say("  target aggregation reduced to its argmax: every output equal")
     f = rsv.reconstruct(_gpu(p.left), _gpu(p.right), case.plane, _camera(case), case.params, tar_volume=False)
     assert f["agg_tar"] is None
     for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
         assert torch.equal(f[k].nan_to_num(), out[k].nan_to_num()), k
+    if rsv.aggregate_select_supported(p.left.shape[1], case.params):
+        _say("  selection folded into the reference aggregation as well: every output equal")
+        g = rsv.reconstruct(_gpu(p.left), _gpu(p.right), case.plane, _camera(case), case.params, tar_volume=False,
+                            ref_volume=False)
+        assert g["agg_ref"] is None
+        for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
+            assert torch.equal(g[k].nan_to_num(), out[k].nan_to_num()), k
 
 
 def test_full_road1280_d64_sampled(rsv_gpu):
