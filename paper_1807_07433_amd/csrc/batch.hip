@@ -4,14 +4,15 @@
 // A plan holds, per pair, the warped right image, the joint cost volume and the
 // selection maps, plus the work lists, and captures the graph
 //     reset counters -> warp -> cost kernel -> [persistent aggregation kernel] ->
-//     target-tile kernel -> reference-tile kernel -> tail kernel.
+//     tile kernel -> tail kernel.
 //   warp: every pixel of every pair, with rsv_warp's arithmetic;
 //   cost items (pair, band of 4 rows, 64-centre column tiles): ZNCC with the
 //       arithmetic of rsv_cost_volume_joint (shared cost_tile), persistent over a
 //       work queue or one workgroup per tile;
 //   target and reference tiles (rho <= 5, W >= 4): one workgroup per (pair, 16 x 16
 //       tile) on the LDS-loaded tile (agg_tile_dma) reading views of the joint
-//       volume.  The target tile keeps only the argmax over d (rsv_aggregate_argmax's
+//       volume, one launch, each pair's target and reference tiles side by side in
+//       the list.  The target tile keeps only the argmax over d (rsv_aggregate_argmax's
 //       arithmetic); the reference tile feeds each 16-disparity tile of aggregated
 //       values, from LDS, through the select kernel's scan step (running best, its d
 //       and its neighbours, ties keep the lowest d), with the scan state in the LDS
@@ -289,14 +290,10 @@ __global__ __launch_bounds__(kAggItemThreads) void batch_agg_kernel(BatchArgs ar
   for_each_item(args, home, s_item, [&](int it) { batch_agg_item<A>(args, args.items[it], smem); });
 }
 
-// Target-volume items on the LDS-loaded tile (rho <= 5, W >= 4), one workgroup per
-// item {pair, kind, tile row, tile column}: only the argmax over d is kept, in
-// registers (ArgmaxSink), as in rsv_aggregate_argmax.  A kernel of its own, so the
-// tile keeps a kernel's register budget.
+// Target-volume items on the LDS-loaded tile (rho <= 5, W >= 4): only the argmax over
+// d is kept, in registers (ArgmaxSink), as in rsv_aggregate_argmax.
 template <int A>
-__global__ __launch_bounds__(1024) void batch_tar_grid_kernel(BatchArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int4 w = args.items[blockIdx.x];
+__device__ __forceinline__ void batch_tar_tile(const BatchArgs& args, int4 w, unsigned char* smem) {
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
   const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
@@ -309,12 +306,10 @@ __global__ __launch_bounds__(1024) void batch_tar_grid_kernel(BatchArgs args) {
   sink.finish(uniform(pd->tar_arg), H, W, by, bx);
 }
 
-// Reference-volume items on the LDS-loaded tile (rho <= 5, W >= 4), one workgroup
-// per item: the select kernel's scan result from all 1024 threads (RefQuadSink).
+// Reference-volume items on the LDS-loaded tile (rho <= 5, W >= 4): the select
+// kernel's scan result from all 1024 threads (RefQuadSink).
 template <int A>
-__global__ __launch_bounds__(1024) void batch_ref_grid_kernel(BatchArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int4 w = args.items[blockIdx.x];
+__device__ __forceinline__ void batch_ref_tile(const BatchArgs& args, int4 w, unsigned char* smem) {
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
   const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
@@ -336,6 +331,21 @@ __global__ __launch_bounds__(1024) void batch_ref_grid_kernel(BatchArgs args) {
       uniform(pd->ref_ap)[i] = sink.ap;
     }
   }
+}
+
+// The tile items {pair, kind, tile row, tile column} of the LDS-loaded tile, one
+// workgroup per item, target or reference by the item's kind (uniform per workgroup).
+// The list holds each pair's target tiles next to its reference tiles, so both passes
+// over a pair's joint cost volume run close together in time.  A kernel of its own
+// (no item loop), so the tile keeps a kernel's register budget.
+template <int A>
+__global__ __launch_bounds__(1024) void batch_tile_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 w = args.items[blockIdx.x];
+  if (uniform(w.y) == kItemAggRef)
+    batch_ref_tile<A>(args, w, smem);
+  else
+    batch_tar_tile<A>(args, w, smem);
 }
 
 // Left-right check, Eq. 12, post-processing and 3-D points for every pixel of every pair.
@@ -371,9 +381,9 @@ struct rsv_batch_plan {
   void* dev_mem = nullptr;  // one allocation: pair table, item lists, counters, workspace
   rsv::PairDev* d_pairs = nullptr;
   int* d_heads = nullptr;   // [cost, aggregation queues]
-  rsv::BatchArgs cost_args{}, agg_args{}, tar_args{}, ref_args{};
+  rsv::BatchArgs cost_args{}, agg_args{}, tile_args{};
   // agg: items of the persistent aggregation kernel; tar / ref: of the tile kernels
-  int n_cost_items = 0, n_agg_items = 0, n_tar_items = 0, n_ref_items = 0;
+  int n_cost_items = 0, n_agg_items = 0, n_tile_items = 0;
   int cost_grid = 0, agg_grid = 0;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -415,27 +425,26 @@ const void* pick_agg_kernel(int A, size_t* lds) {
   }
 }
 
-// The target- and reference-tile kernels for radius A (null when the LDS-loaded
-// tile does not fit: rho = 6), with their LDS bytes.
+// The tile kernel for radius A (null when the LDS-loaded tile does not fit: rho = 6),
+// with its LDS bytes.
 template <int A>
-const void* tile_kernel_ptr(bool ref, size_t* lds) {
+const void* tile_kernel_ptr(size_t* lds) {
   if constexpr (agg_dma_fits<A>()) {
     *lds = agg_tile_dma_lds_bytes<A>();
-    return ref ? reinterpret_cast<const void*>(batch_ref_grid_kernel<A>)
-               : reinterpret_cast<const void*>(batch_tar_grid_kernel<A>);
+    return reinterpret_cast<const void*>(batch_tile_kernel<A>);
   } else {
     return nullptr;
   }
 }
 
-const void* pick_tile_kernel(int A, bool ref, size_t* lds) {
+const void* pick_tile_kernel(int A, size_t* lds) {
   switch (A) {
-    case 1: return tile_kernel_ptr<1>(ref, lds);
-    case 2: return tile_kernel_ptr<2>(ref, lds);
-    case 3: return tile_kernel_ptr<3>(ref, lds);
-    case 4: return tile_kernel_ptr<4>(ref, lds);
-    case 5: return tile_kernel_ptr<5>(ref, lds);
-    case 6: return tile_kernel_ptr<6>(ref, lds);
+    case 1: return tile_kernel_ptr<1>(lds);
+    case 2: return tile_kernel_ptr<2>(lds);
+    case 3: return tile_kernel_ptr<3>(lds);
+    case 4: return tile_kernel_ptr<4>(lds);
+    case 5: return tile_kernel_ptr<5>(lds);
+    case 6: return tile_kernel_ptr<6>(lds);
     default: return nullptr;
   }
 }
@@ -500,10 +509,9 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     });
 
   std::vector<PairDev> pd(n);
-  std::vector<int4> cost_items, agg_items, tar_items, ref_items;
-  size_t tar_lds = 0, ref_lds = 0;
-  const void* tk = pick_tile_kernel(A, false, &tar_lds);
-  const void* rk = pick_tile_kernel(A, true, &ref_lds);
+  std::vector<int4> cost_items, agg_items, tile_items;
+  size_t tile_lds = 0;
+  const void* tk = pick_tile_kernel(A, &tile_lds);
   size_t ws_bytes = 0;
   int max_pixels = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -555,7 +563,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
           // persistent kernel
           const int4 it = make_int4(i, kind, ty, tx);
           if (tk && P.W >= 4)
-            (kind == kItemAggTar ? tar_items : ref_items).push_back(it);
+            tile_items.push_back(it);
           else
             agg_items.push_back(it);
         }
@@ -574,8 +582,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   plan->tuning = tn;
   plan->n_cost_items = static_cast<int>(cost_items.size());
   plan->n_agg_items = static_cast<int>(agg_items.size());
-  plan->n_tar_items = static_cast<int>(tar_items.size());
-  plan->n_ref_items = static_cast<int>(ref_items.size());
+  plan->n_tile_items = static_cast<int>(tile_items.size());
 
   size_t off = 0;
   const size_t o_pairs = off;
@@ -585,9 +592,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   const size_t o_ai = off;
   off = align(off + sizeof(int4) * agg_items.size());
   const size_t o_ti = off;
-  off = align(off + sizeof(int4) * tar_items.size());
-  const size_t o_ri = off;
-  off = align(off + sizeof(int4) * ref_items.size());
+  off = align(off + sizeof(int4) * tile_items.size());
   const size_t o_heads = off;
   off = align(off + sizeof(int) * (1 + kAggQueues));
   const size_t o_qbeg = off;
@@ -626,11 +631,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   if ((e = hipMemcpy(base + o_ci, cost_items.data(), sizeof(int4) * cost_items.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
-  if (!tar_items.empty() && (e = hipMemcpy(base + o_ti, tar_items.data(), sizeof(int4) * tar_items.size(),
-                                            hipMemcpyHostToDevice)) != hipSuccess)
-    return fail(e);
-  if (!ref_items.empty() && (e = hipMemcpy(base + o_ri, ref_items.data(), sizeof(int4) * ref_items.size(),
-                                            hipMemcpyHostToDevice)) != hipSuccess)
+  if (!tile_items.empty() && (e = hipMemcpy(base + o_ti, tile_items.data(), sizeof(int4) * tile_items.size(),
+                                             hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
   if ((e = hipMemcpy(base + o_ai, agg_items.data(), sizeof(int4) * agg_items.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
@@ -652,10 +654,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       hipSuccess)
     return fail(e);
   if (tk && (e = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    static_cast<int>(tar_lds))) != hipSuccess)
-    return fail(e);
-  if (rk && (e = hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    static_cast<int>(ref_lds))) != hipSuccess)
+                                    static_cast<int>(tile_lds))) != hipSuccess)
     return fail(e);
   if ((e = hipFuncSetAttribute(ak, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(agg_lds))) !=
       hipSuccess)
@@ -692,15 +691,12 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   aa.qbeg = d_qbeg + 2;
   aa.nq = kAggQueues;
   aa.head = plan->d_heads + 1;
-  BatchArgs& ta = plan->tar_args;
+  BatchArgs& ta = plan->tile_args;
   ta = ca;
   ta.items = reinterpret_cast<const int4*>(base + o_ti);
-  BatchArgs& ra = plan->ref_args;
-  ra = ca;
-  ra.items = reinterpret_cast<const int4*>(base + o_ri);
 
-  // graph: reset counters -> warp -> cost kernel -> aggregation + WTA kernel ->
-  // target-tile kernel -> tail
+  // graph: reset counters -> warp -> cost kernel -> [persistent aggregation kernel] ->
+  // tile kernel -> tail
   if ((e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
@@ -713,13 +709,9 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     void* aargs[] = {&plan->agg_args};
     hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
   }
-  if (plan->n_tar_items > 0) {
-    void* targs[] = {&plan->tar_args};
-    hipLaunchKernel(tk, dim3(plan->n_tar_items), dim3(1024), targs, tar_lds, plan->capture_stream);
-  }
-  if (plan->n_ref_items > 0) {
-    void* rargs[] = {&plan->ref_args};
-    hipLaunchKernel(rk, dim3(plan->n_ref_items), dim3(1024), rargs, ref_lds, plan->capture_stream);
+  if (plan->n_tile_items > 0) {
+    void* targs[] = {&plan->tile_args};
+    hipLaunchKernel(tk, dim3(plan->n_tile_items), dim3(1024), targs, tile_lds, plan->capture_stream);
   }
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
@@ -747,7 +739,7 @@ extern "C" int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items,
   if (!plan) return RSV_E_NULL;
   if (n_items) {
     n_items[0] = plan->n_cost_items;
-    n_items[1] = plan->n_agg_items + plan->n_tar_items + plan->n_ref_items;
+    n_items[1] = plan->n_agg_items + plan->n_tile_items;
   }
   if (grid_blocks) {
     grid_blocks[0] = plan->cost_grid;
