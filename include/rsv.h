@@ -248,6 +248,10 @@ typedef struct {
   int32_t cost_blocks_per_cu;   /* persistent cost workgroups per CU; 0 = as many as fit
                                    (default); -1 = one workgroup per cost item, no queue */
   int32_t agg_blocks_per_cu;    /* persistent aggregation workgroups per CU; 0 = as fit  */
+  int32_t per_pair_launches;    /* 1: the graph runs each pair's cost launch and then its
+                                   tile launch, pair after pair, so its cost volume is
+                                   still in the caches when aggregated (implies one cost
+                                   workgroup per item); 0: one launch per phase (default) */
 } rsv_tuning;
 
 typedef struct rsv_batch_plan rsv_batch_plan;

@@ -472,6 +472,7 @@ extern "C" void rsv_tuning_default(rsv_tuning* t) {
   t->cost_tiles_per_item = 2;
   t->cost_blocks_per_cu = 0;
   t->agg_blocks_per_cu = 0;
+  t->per_pair_launches = 0;
 }
 
 extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
@@ -550,9 +551,14 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   // agg items: per pair, the reference tiles then the target tiles, row-major, so
   // each queue's stretch of the list is a band of neighbouring tiles of one volume
   // (one tile per cost item when the cost kernel runs one workgroup per item)
-  const int cost_tiles = tn.cost_blocks_per_cu < 0 ? 1 : tn.cost_tiles_per_item;
+  const bool grid_cost = tn.cost_blocks_per_cu < 0 || tn.per_pair_launches != 0;
+  const int cost_tiles = grid_cost ? 1 : tn.cost_tiles_per_item;
+  // per pair (in list order): its ranges of the cost and tile lists
+  std::vector<int> cost_beg, cost_end, tile_beg, tile_end;
   for (int i : order) {
     const PairDev& P = pd[i];
+    cost_beg.push_back(static_cast<int>(cost_items.size()));
+    tile_beg.push_back(static_cast<int>(tile_items.size()));
     for (int b = 0; b < P.nbands; ++b)
       for (int ct = 0; ct < P.ncol_tiles; ct += cost_tiles)
         cost_items.push_back(make_int4(i, kItemCost | (cost_tiles << 8), b, ct));
@@ -567,6 +573,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
           else
             agg_items.push_back(it);
         }
+    cost_end.push_back(static_cast<int>(cost_items.size()));
+    tile_end.push_back(static_cast<int>(tile_items.size()));
   }
   // queue boundaries: [0, n_cost) for the cost kernel; 8 equal stretches of the agg list
   std::vector<int> qbeg(2 + kAggQueues + 1);
@@ -641,7 +649,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       hipSuccess)
     return fail(e);
 
-  const bool cost_grid_mode = tn.cost_blocks_per_cu < 0;
+  const bool cost_grid_mode = grid_cost;
   const void* ck = pick_cost_kernel(R, cost_grid_mode);
   size_t agg_lds = 0;
   const void* ak = pick_agg_kernel(A, &agg_lds);
@@ -703,15 +711,37 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   batch_reset_kernel<<<1, 64, 0, plan->capture_stream>>>(plan->d_heads, 1 + kAggQueues);
   const int tail_x = std::min(1024, (max_pixels + 255) / 256);
   batch_warp_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs);
-  void* cargs[] = {&plan->cost_args};
-  hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
-  if (plan->agg_grid > 0) {
-    void* aargs[] = {&plan->agg_args};
-    hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
-  }
-  if (plan->n_tile_items > 0) {
-    void* targs[] = {&plan->tile_args};
-    hipLaunchKernel(tk, dim3(plan->n_tile_items), dim3(1024), targs, tile_lds, plan->capture_stream);
+  if (tn.per_pair_launches) {
+    // pair after pair: its cost items, then its tiles, each launch over its own range
+    // of the lists (one workgroup per item); the persistent kernel's tiles after all
+    for (size_t k = 0; k < cost_beg.size(); ++k) {
+      BatchArgs c = plan->cost_args;
+      c.items += cost_beg[k];
+      void* cargs[] = {&c};
+      hipLaunchKernel(ck, dim3(cost_end[k] - cost_beg[k]), dim3(kCostThreads), cargs, cost_lds,
+                      plan->capture_stream);
+      if (tile_end[k] > tile_beg[k]) {
+        BatchArgs t = plan->tile_args;
+        t.items += tile_beg[k];
+        void* targs[] = {&t};
+        hipLaunchKernel(tk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), targs, tile_lds, plan->capture_stream);
+      }
+    }
+    if (plan->agg_grid > 0) {
+      void* aargs[] = {&plan->agg_args};
+      hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
+    }
+  } else {
+    void* cargs[] = {&plan->cost_args};
+    hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
+    if (plan->agg_grid > 0) {
+      void* aargs[] = {&plan->agg_args};
+      hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
+    }
+    if (plan->n_tile_items > 0) {
+      void* targs[] = {&plan->tile_args};
+      hipLaunchKernel(tk, dim3(plan->n_tile_items), dim3(1024), targs, tile_lds, plan->capture_stream);
+    }
   }
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
@@ -776,13 +806,16 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
   int status = RSV_OK;
   for (int lf = 0; lf <= 1; ++lf)
     for (int tiles : {1, 2, 4})
-      for (int cpc : {-1, 0, 2}) {
+      for (int cpc : {-1, 0, 2})
+        for (int pp : {0, 1}) {
         if (cpc < 0 && tiles != 1) continue;  // one tile per item there
+        if (pp && cpc >= 0) continue;         // per-pair launches run one workgroup per cost item
         rsv_tuning t;
         rsv_tuning_default(&t);
         t.largest_first = lf;
         t.cost_tiles_per_item = tiles;
         t.cost_blocks_per_cu = cpc;
+        t.per_pair_launches = pp;
         rsv_batch_plan* plan = nullptr;
         const int s = rsv_batch_plan_create(pairs, n, p, &t, &plan);
         if (s != RSV_OK) {

@@ -155,14 +155,16 @@ def test_batch_persistent_path_equals_plain(rsv_gpu, r, rho, shapes):
     plan.close()
 
 
-@pytest.mark.parametrize("largest_first,tiles,cpc", [(0, 1, 0), (1, 4, 2), (1, 3, 1), (1, 4, -1)])
-def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc):
+@pytest.mark.parametrize("largest_first,tiles,cpc,per_pair",
+                         [(0, 1, 0, 0), (1, 4, 2, 0), (1, 3, 1, 0), (1, 4, -1, 0), (0, 1, -1, 1), (1, 2, 0, 1)])
+def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc, per_pair):
     rsv = rsv_gpu
     from paper_1807_07433_amd.batch import BatchPlan, default_tuning
     cases = _cases(SHAPES[:3], 950)
     pairs = _pairs(cases)
     t = default_tuning()
     t.largest_first, t.cost_tiles_per_item, t.cost_blocks_per_cu = largest_first, tiles, cpc
+    t.per_pair_launches = per_pair
     _say(f"[batch] tuning {t.as_dict()}")
     plan = BatchPlan(pairs, PRM, t)
     plan.run()
