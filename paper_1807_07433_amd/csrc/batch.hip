@@ -206,7 +206,7 @@ __device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, f
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const float* warped = uniform(pd->warped);
   const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
-  auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
+  auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
   const int c0 = uniform(w.w);
   const int last = min(c0 + (uniform(w.y) >> 8), uniform(pd->ncol_tiles));
   const int v0 = uniform(w.z) * kBandRows;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const float* warped = uniform(pd->warped);
   const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
-  auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
+  auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
   cost_tile<R, kBandRows, false>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
                           uniform(w.w) * kCostTW, uniform(w.z) * kBandRows,
                           cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D), cwork);
@@ -299,7 +299,7 @@ __device__ __forceinline__ void batch_tar_tile(const BatchArgs& args, int4 w, un
   const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
   const float* warped = uniform(pd->warped);
   const int jrow = static_cast<int>(uniform(pd->jrow));
-  auto guide = [&](int Y, int X) { return warped[static_cast<int64_t>(Y) * W + X]; };
+  auto guide = [&](int Y, int X) { return as_global(warped)[static_cast<int64_t>(Y) * W + X]; };
   ArgmaxSink sink{D};
   agg_tile_dma<A>(uniform(pd->joint), static_cast<int64_t>(H) * jrow + 1, jrow, H, W, D, args.bk, by, bx, guide,
                   sink, smem, lds_address(smem));

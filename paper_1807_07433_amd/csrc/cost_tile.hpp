@@ -55,6 +55,14 @@ __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
   return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1);
 }
 
+// The volume is written through a global-address-space pointer.  Where the output
+// pointer is loaded from memory (the batch kernel's pair descriptors) rather than
+// passed as a kernel argument, the compiler cannot tell it is global and would emit
+// flat stores, which also count in the LDS counter: every wait for the window's LDS
+// reads would then wait for the stores as well.
+typedef __attribute__((address_space(1))) float global_float;
+__device__ __forceinline__ global_float* to_global(float* p) { return (global_float*)p; }
+
 // warped_at(y, x) returns the warped target at in-image (y, x).  TAR: out.tar may be
 // non-null (the dual layout); with TAR false the target stores are not compiled.
 template <int R, int TH, bool TAR, typename TL, typename WarpAt>
@@ -140,10 +148,10 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
 #pragma unroll
         for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
       const float c = (num * lb.inv) * irow[-d];
-      if (ref_ok) (cost_ref + d * ref_plane)[roff] = c;
+      if (ref_ok) to_global(cost_ref + d * ref_plane)[roff] = c;
       if constexpr (TAR) {
         const int64_t pd = d * plane;
-        if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) (cost_tar + (pd - d))[toff] = c;
+        if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) to_global(cost_tar + (pd - d))[toff] = c;
       }
     }
   }

@@ -95,9 +95,18 @@ __device__ __forceinline__ int opaque_tid() {
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
+// A device pointer into global memory, read as such.  Where a pointer is loaded from
+// memory (the batch kernels' pair descriptors) rather than passed as a kernel
+// argument, the compiler cannot tell it is global and emits flat accesses, which also
+// count in the LDS counter, so waits for LDS reads would wait for them too.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ float pixel(const T* img, int64_t pitch, int v, int u) {
-  return static_cast<float>(img[static_cast<int64_t>(v) * pitch + u]);
+  return static_cast<float>(as_global(img)[static_cast<int64_t>(v) * pitch + u]);
 }
 
 }  // namespace rsv
