@@ -96,80 +96,48 @@ struct ArgmaxSink {
 // agg_tile_dma sink for the reference volume: the select kernel's scan result (first
 // maximum over d, ties to the lowest d, and the values at d - 1 and d + 1) from all
 // 1024 threads, in registers; shared by rsv_aggregate_select and the batch kernel's
-// reference tiles.  Thread i covers pixel i / 4 and disparities
-// 4 (i % 4) .. + 3 of each 16-disparity tile: its first maximum with the values beside
-// it (from the quad's neighbouring lanes, or from the previous tile's last value),
-// then two quad permutations merge the four (larger value, lower d on ties).  A
-// winner at a tile's last disparity takes its right neighbour from the next tile.
-// The winner, its value and the values at d - 1 and d + 1 are exactly the scan's
-// wherever Eq. 12 uses them (0 < d < D - 1).
+// reference tiles.  Thread i covers pixel i / 4 and disparities 4 (i % 4) .. + 3 of
+// each 16-disparity tile: its first maximum, then two quad permutations merge the four
+// (larger value, lower d on ties).  When the tile's winner replaces the running one,
+// its neighbours are read from the output tile, still in LDS; at the tile's edges they
+// are the previous tile's last value and the next tile's first.  The winner, its value
+// and the values at d - 1 and d + 1 are exactly the scan's wherever Eq. 12 uses them
+// (0 < d < D - 1).
 struct RefQuadSink {
   int D;
   float best = -INFINITY, am = 0.f, ap = 0.f, lastv = 0.f;
   int arg = 0;
   bool pend = false;
 
-  template <int PERM>
-  static __device__ __forceinline__ float dppf(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), PERM, 0xF, 0xF, false));
-  }
-  template <int PERM>
-  static __device__ __forceinline__ int dppi(int x) {
-    return __builtin_amdgcn_mov_dpp(x, PERM, 0xF, 0xF, false);
-  }
-  template <int PERM>
-  static __device__ __forceinline__ void merge(float& b, int& a, float& m, float& n, int& pd) {
-    const float ob = dppf<PERM>(b), om = dppf<PERM>(m), on = dppf<PERM>(n);
-    const int oa = dppi<PERM>(a), opd = dppi<PERM>(pd);
-    if (ob > b || (ob == b && oa < a)) {
-      b = ob;
-      a = oa;
-      m = om;
-      n = on;
-      pd = opd;
-    }
-  }
-
   __device__ __forceinline__ void operator()(int t, const float* o) {
     using G = AggGeo<1, 16>;
     const int i = threadIdx.x, p = i >> 2, q = i & 3;
-    float v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = o[(4 * q + k) * G::OST + p];
-    // quad lanes: the previous lane's last value, the next lane's first, the tile's
-    // first (d = 16 t) and last (d = 16 t + 15) values
-    const float prevq = dppf<0x90>(v[3]);  // quad_perm [0, 0, 1, 2]
-    const float nextq = dppf<0xF9>(v[0]);  // quad_perm [1, 2, 3, 3]
-    const float first = dppf<0x00>(v[0]);
-    const float last = dppf<0xFF>(v[3]);
-    const float left = q == 0 ? lastv : prevq;
-    float b = -INFINITY, m = 0.f, n = 0.f;
-    int a = 0x7fffffff, pd = 0;
+    float b = -INFINITY;
+    int a = 0x7fffffff;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int d = 16 * t + 4 * q + k;
-      if (d < D && v[k] > b) {
-        b = v[k];
+      const float v = o[(4 * q + k) * G::OST + p];
+      if (d < D && v > b) {
+        b = v;
         a = d;
-        m = k == 0 ? left : v[k - 1];
-        n = k == 3 ? nextq : v[k + 1];
-        pd = (k == 3 && q == 3) ? 1 : 0;
       }
     }
-    merge<0xB1>(b, a, m, n, pd);
-    merge<0x4E>(b, a, m, n, pd);
+    quad_merge<0xB1>(b, a);
+    quad_merge<0x4E>(b, a);
     if (pend) {  // the running winner sat at d = 16 t - 1: its right neighbour is d = 16 t
-      ap = first;
+      ap = o[p];
       pend = false;
     }
     if (t == 0 || b > best) {
+      const int k = a - 16 * t;  // the winner's place in the tile
       best = b;
       arg = a;
-      am = m;
-      ap = n;
-      pend = pd != 0;
+      am = k > 0 ? o[(k - 1) * G::OST + p] : lastv;
+      pend = k == 15;
+      if (!pend) ap = o[(k + 1) * G::OST + p];
     }
-    lastv = last;
+    lastv = o[15 * G::OST + p];
   }
 };
 
