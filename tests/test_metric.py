@@ -64,3 +64,18 @@ def test_lds_traffic_of_the_tiles():
     # pairs x 127 target centres reading 8 x 7 values and writing 2, 256 left blocks of 49
     per_block = 256 * 64 * 8 + 10 * (133 + 70) + 2 * 127 * (8 * 7 + 2) + 256 * 49
     assert bench.cost_lds_bytes(1280, 720, 64, 3) == 21 * 180 * 4 * per_block
+
+
+def test_kernel_rooflines_with_the_selection_folded_in():
+    """With the selection folded into the reference aggregation there is no select
+    kernel to report, and each aggregation launch reads 4 B per entry and writes maps."""
+    class P:
+        agg_radius = 5
+        block_radius = 3
+    st = {"cost_volume": 0.1, "aggregate_ref": 0.25, "aggregate_tar": 0.24}
+    k = bench.kernel_rooflines(st, 1280, 720, 64, P, fused=True)
+    assert set(k) == {"cost_volume", "aggregate"}
+    n = 1280 * 720 * 64
+    ms = 0.5 * (0.25 + 0.24)
+    assert abs(k["aggregate"]["hbm_view"]["achieved_gbs"] - 4 * n / (ms * 1e-3) / 1e9) < 0.1
+    assert k["aggregate"]["flops_per_launch"] == (2 * 121 + 2) * n
