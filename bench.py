@@ -295,11 +295,10 @@ def bench_diff(a, rsv, torch):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record()
         wp = ops.warp(rights[0], plane)
-        cref, _ = ops.cost_volume(lefts[0], wp, prm, want_tar=False)
-        aref = ops.aggregate(cref, lefts[0], prm)
-        ops.selected_cost_sum(aref, d, m)
+        cref, _ = ops.joint_views(ops.cost_volume_joint(lefts[0], wp, prm), W)
+        ops.selected_aggregate_sum(cref, lefts[0], prm, d, m)
         e[1].record()
-        ops.cost_adjoint(lefts[0], rights[0], plane, prm, cref, aref, d, m, workspace=ws)
+        ops.cost_adjoint(lefts[0], rights[0], plane, prm, cref, d, m, workspace=ws)
         e[2].record()
         torch.cuda.synchronize()
         if rep >= 2:

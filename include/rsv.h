@@ -311,31 +311,52 @@ int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p, rsv
 int rsv_selected_cost_sum(const float* agg_ref, const int32_t* disp, const uint8_t* mask,
                           int32_t height, int32_t width, int32_t D, double* out, void* stream);
 
+/* The same loss from a cost volume, with no aggregated volume (Sec. II-B.2, Eq. 8-10,
+ * at one disparity per pixel): sum over the pixels p with mask(p) != 0 and
+ * 0 <= disp(p) < D of
+ *   A(p) = sum_q w(p, q) cost(disp(p), q) / sum_q w(p, q)
+ * over p's (2*agg_radius+1)^2 window inside the image, w of Eq. 9-10 with the guide,
+ * accumulated in float per pixel and in double over pixels.  Equal to
+ * rsv_selected_cost_sum on rsv_aggregate's volume to float rounding.
+ *   cost(d, v, u) = cost[d*plane_stride + v*row_stride + u]  (e.g. the reference
+ *                   view of rsv_cost_volume_joint's volume)
+ *   guide    the left image (u8 or f32), H x W
+ *   disp, mask  int32 / uint8 [H][W];  out  device double[1], overwritten
+ * Errors: RSV_E_NULL, RSV_E_DTYPE, RSV_E_SHAPE (row_stride < W, plane_stride < 1,
+ * (H-1)*row_stride + W > 2^31 - 1), RSV_E_PARAM (agg_radius, gammas), RSV_E_ALIGN. */
+int rsv_selected_aggregate_sum(const float* cost, int64_t plane_stride, int64_t row_stride,
+                               rsv_image guide, const rsv_params* p, const int32_t* disp,
+                               const uint8_t* mask, double* out, void* stream);
+
 /* Bytes of device workspace rsv_cost_adjoint needs for an H x W pair (0 if invalid). */
 size_t rsv_cost_adjoint_workspace_bytes(int32_t height, int32_t width);
 
 /* Adjoint of the loss above with disp and mask held fixed: gradients with respect to
  * the warp plane (a0, a1, a2) of Sec. II-A and both input images, through the warp,
- * the ZNCC of Eq. 3-5 and the bilateral aggregation of Eq. 8-10 (weights recomputed,
- * never stored; their dependence on the left image is included).
+ * the ZNCC of Eq. 3-5 and the bilateral aggregation of Eq. 8-10.  The weights and
+ * the aggregated costs A(p) are recomputed from the images and the cost volume, never
+ * stored; the weights' dependence on the left image is included.
  *   left, right   float32 images the forward ran on (same H, W)
  *   plane, p      the forward's plane and parameters (D <= 256)
- *   cost_ref      the forward's float32 [D][H][W] reference cost volume
- *   agg_ref       the forward's float32 [D][H][W] aggregated reference volume
+ *   cost(d, v, u) = cost[d*plane_stride + v*row_stride + u]: the forward's reference
+ *                 cost volume (rsv_cost_volume's cost_ref, or the reference view of
+ *                 rsv_cost_volume_joint's volume)
  *   disp, mask    int32 / uint8 [H][W]; pixels with mask == 0 or disp outside [0, D)
  *                 are not in the loss
  *   grad_left, grad_right  out float32 [H][W] (dense), overwritten
  *   grad_plane    out device double[3] = dL/d(a0, a1, a2), overwritten
- *   loss          out device double[1] (the same sum as rsv_selected_cost_sum), or NULL
+ *   loss          out device double[1] (the loss of rsv_selected_aggregate_sum), or NULL
  *   workspace     device buffer of rsv_cost_adjoint_workspace_bytes(H, W) bytes, owned
  *                 by the caller; its contents are scratch
  * Results are sums of float atomics: equal to rounding, not bit for bit, run to run.
- * Errors: RSV_E_NULL, RSV_E_DTYPE (images not float32), RSV_E_SHAPE, RSV_E_PARAM,
- * RSV_E_ALIGN. */
+ * Errors: RSV_E_NULL, RSV_E_DTYPE (images not float32), RSV_E_SHAPE (also D > 256,
+ * H or W < block width, the cost view's strides as rsv_selected_aggregate_sum),
+ * RSV_E_PARAM, RSV_E_ALIGN. */
 int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
-                     const float* cost_ref, const float* agg_ref, const int32_t* disp,
-                     const uint8_t* mask, float* grad_left, float* grad_right,
-                     double* grad_plane, double* loss, void* workspace, void* stream);
+                     const float* cost, int64_t plane_stride, int64_t row_stride,
+                     const int32_t* disp, const uint8_t* mask, float* grad_left,
+                     float* grad_right, double* grad_plane, double* loss, void* workspace,
+                     void* stream);
 
 /* --------------------------------------------------------------- diagnostics */
 

@@ -61,8 +61,10 @@ _SIGNATURES = {
     "rsv_triangulate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, Plane, Camera, _P, _P, _P]),
     "rsv_selected_cost_sum": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "rsv_cost_adjoint_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
-    "rsv_cost_adjoint": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, _P, _P, _P, _P, _P,
-                                   _P, _P, _P, _P]),
+    "rsv_selected_aggregate_sum": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P, _P,
+                                             _P, _P]),
+    "rsv_cost_adjoint": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, C.c_int64, C.c_int64, _P,
+                                   _P, _P, _P, _P, _P, _P, _P]),
     "rsv_tuning_default": (None, [_P]),
     "rsv_batch_plan_create": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P]),
     "rsv_batch_run": (C.c_int, [_P, _P]),

@@ -2,13 +2,16 @@
 disparities, as a torch.autograd.Function whose backward is the hand-written
 adjoint kernel (rsv_cost_adjoint), plus a plane-refinement loop built on it.
 
-    loss = AggregatedZNCC.apply(left, right, theta, delta, params, disp, mask)
+    loss = AggregatedZNCC.apply(left, right, theta, delta, params, disp, mask[, joint])
 
 theta = (a0, a1, a2) of the warp shift s = a0 + a1 v + a2 u - delta (Sec. II-A).
-The forward runs the plain path's kernels (warp, ZNCC reference volume, bilateral
-aggregation) and sums agg_ref[disp(p)][p] over mask(p) != 0.  disp and mask are held
-fixed inside one evaluation (WTA stays exact and is re-run between steps by
-`select`).  Gradients flow to left, right (float32 images) and theta.
+The forward runs the plain path's kernels (warp, joint ZNCC volume) and sums the
+aggregation of Eq. 8 at disp(p) over mask(p) != 0 (rsv_selected_aggregate_sum); no
+aggregated volume is formed.  `joint`, if given, is the joint cost volume of this
+very (left, right, plane), e.g. the one `select` returns, and is not recomputed.
+disp and mask are held fixed inside one evaluation (WTA stays exact and is re-run
+between steps by `select`).  Gradients flow to left, right (float32 images) and
+theta.
 """
 from __future__ import annotations
 
@@ -24,13 +27,13 @@ def _plane(theta: torch.Tensor, delta: float):
 
 class AggregatedZNCC(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, left, right, theta, delta, params, disp, mask):
+    def forward(ctx, left, right, theta, delta, params, disp, mask, joint=None):
         plane = _plane(theta, delta)
-        wp = ops.warp(right, plane)
-        cref, _ = ops.cost_volume(left, wp, params, want_tar=False)
-        aref = ops.aggregate(cref, left, params)
-        loss = ops.selected_cost_sum(aref, disp, mask)
-        ctx.save_for_backward(left, right, cref, aref, disp, mask)
+        if joint is None:
+            joint = ops.cost_volume_joint(left, ops.warp(right, plane), params)
+        cref, _ = ops.joint_views(joint, left.shape[1])
+        loss = ops.selected_aggregate_sum(cref, left, params, disp, mask)
+        ctx.save_for_backward(left, right, joint, disp, mask)
         ctx.plane = plane
         ctx.params = params
         ctx.theta_meta = (theta.dtype, theta.device)
@@ -38,26 +41,34 @@ class AggregatedZNCC(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gout):
-        left, right, cref, aref, disp, mask = ctx.saved_tensors
-        gl, gr, gp, _ = ops.cost_adjoint(left, right, ctx.plane, ctx.params, cref, aref, disp, mask)
+        left, right, joint, disp, mask = ctx.saved_tensors
+        cref, _ = ops.joint_views(joint, left.shape[1])
+        gl, gr, gp, _ = ops.cost_adjoint(left, right, ctx.plane, ctx.params, cref, disp, mask)
         dtype, device = ctx.theta_meta
         s = gout.to(torch.float64)
         g_theta = (gp * s).to(device=device, dtype=dtype)
         sf = s.to(torch.float32)
-        return gl * sf, gr * sf, g_theta, None, None, None, None
+        return gl * sf, gr * sf, g_theta, None, None, None, None, None
 
 
-def select(left, right, plane, params):
-    """Plain-path selection for the current plane: returns (disp_ref int32, mask uint8)
-    with mask = left-right valid and 0 < d < D-1 (pixels where Eq. 12 applies)."""
+def select(left, right, plane, params, return_joint: bool = False):
+    """Plain-path selection for the current plane, in its fastest form (joint cost
+    volume, target argmax, selection folded into the reference aggregation where it
+    runs): returns (disp_ref int32, mask uint8) with mask = left-right valid and
+    0 < d < D-1 (pixels where Eq. 12 applies); with return_joint, also the joint cost
+    volume, which AggregatedZNCC takes for the same plane."""
+    W = left.shape[1]
     wp = ops.warp(right, plane)
-    cref, ctar = ops.cost_volume(left, wp, params)
-    aref = ops.aggregate(cref, left, params)
-    atar = ops.aggregate(ctar, wp, params)
-    sel = ops.select_subpixel(aref, atar, params)
+    joint = ops.cost_volume_joint(left, wp, params)
+    cref, ctar = ops.joint_views(joint, W)
+    dtar = ops.aggregate_argmax(ctar, wp, params)
+    if ops.aggregate_select_supported(W, params):
+        sel = ops.aggregate_select(cref, left, params, dtar)
+    else:
+        sel = ops.select_subpixel(ops.aggregate(cref, left, params), None, params, out={"disp_tar": dtar})
     d = sel["disp_ref"]
     mask = (sel["valid"].bool() & (d > 0) & (d < int(params.D) - 1)).to(torch.uint8)
-    return d, mask
+    return (d, mask, joint) if return_joint else (d, mask)
 
 
 def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, reselect_every=1,
@@ -77,13 +88,17 @@ def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, resele
     for it in range(steps):
         theta = z * scale
         plane = _plane(theta, delta)
-        if sel is None or it % reselect_every == 0:
-            sel = [select(l, r, plane, params) for l, r in zip(lefts, rights)]
+        fresh = sel is None or it % reselect_every == 0
+        if fresh:
+            sel = []
+            for l, r in zip(lefts, rights):
+                d, m, joint = select(l, r, plane, params, return_joint=True)
+                sel.append((d, m, joint, m.sum(dtype=torch.float64).clamp_min(1.0)))
         opt.zero_grad()
         objective = 0.0
-        for (l, r), (d, m) in zip(zip(lefts, rights), sel):
-            loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m)
-            objective = objective + loss / max(int(m.sum()), 1)
+        for (l, r), (d, m, joint, cnt) in zip(zip(lefts, rights), sel):
+            loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m, joint if fresh else None)
+            objective = objective + loss / cnt
         objective = objective / len(lefts)
         (-objective).backward()
         opt.step()

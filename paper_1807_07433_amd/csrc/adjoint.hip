@@ -1,7 +1,9 @@
-// rsv_cost_adjoint: gradient of the differentiable form
+// The differentiable form: the loss
 //     L(theta, I_l, I_r) = sum over p in Omega of A_ref(p, d*(p))
 // (aggregated reference cost of Eq. 8 at frozen disparities d* on a frozen pixel
-// set Omega) with respect to the warp plane (Sec. II-A) and both images.
+// set Omega), its value from a cost volume (rsv_selected_aggregate_sum) and its
+// gradient with respect to the warp plane (Sec. II-A) and both images
+// (rsv_cost_adjoint).
 //
 // The chain rule runs through the bilateral weights (guide = left image, Eq. 10),
 // the ZNCC of Eq. 3-5 and the linear-interpolation warp:
@@ -9,13 +11,18 @@
 //   dL/dw(p, q)  = (c(q, d*(p)) - A(p)) / Z(p)
 //   G dc/dl_i    = a (r_i - mu_r) - b (l_i - mu_l),  G dc/dr_i = a (l_i - mu_l) - g (r_i - mu_r)
 //   with a = G / sqrt(S_ll S_rr), b = G c / S_ll, g = G c / S_rr.
-// The weights are recomputed (never stored); the forward's cost and aggregated
-// volumes supply c and A.  One block covers 16 x 8 reference pixels q: it gathers
-// G(q, .) for its pixels into private LDS columns (64 disparities at a time),
-// scatters the block gradients into LDS accumulators for the left image and the
-// warped image, then flushes them with float atomics; the warped-image gradient
-// goes through the transpose of the interpolation straight into the right image,
-// and its shift derivative -(I1 - I0) (1, v, u) into the plane gradient.
+// The weights are recomputed (never stored), and so is A(p): the cost volume (any
+// strided view, e.g. the reference view of the joint volume) supplies c, and no
+// aggregated volume is needed.  One block covers 16 x 8 reference pixels q.  It
+// stages the left tile, the warped tile and the statistics of every target block its
+// pixels meet (mean and 1/sqrt(S_rr), once per block); gathers G(q, .) for its pixels
+// into private LDS columns (64 disparities at a time); keeps each pixel's left-block
+// gradient in registers across disparities and scatters the warped-block gradient
+// into an LDS accumulator; then flushes both with float atomics.  Accumulators are
+// indexed by block position, not pixel, so clamp-to-edge reads are folded onto their
+// edge pixel only at the flush.  The warped-image gradient goes through the transpose
+// of the interpolation into the right image, and its shift derivative
+// -(I1 - I0) (1, v, u) into the plane gradient.
 #include "bilateral_math.hpp"
 #include "warp_math.hpp"
 
@@ -38,17 +45,12 @@ __global__ void adjoint_zero_kernel(float* __restrict__ a, float* __restrict__ b
   if (i == 0 && loss) *loss = 0.0;
 }
 
-// 1 / sum of the Eq. 9-10 weights of each pixel's window, with the aggregation
-// kernel's weight function (summed in window order).
-template <int A>
-__global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, int64_t gpitch, int H,
-                                                   int W, BilateralK bk,
-                                                   float* __restrict__ zinv) {
+// Sum of the Eq. 9-10 weights of the window of (u, v), in window order, with the
+// aggregation kernels' weight function; taps outside the image are skipped.
+template <int A, typename T>
+__device__ __forceinline__ float window_weight_sum(const T* __restrict__ g, int64_t gpitch, int H, int W,
+                                                   int v, int u, float gp, const BilateralK& bk) {
   constexpr int K = 2 * A + 1;
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
-  if (u >= W || v >= H) return;
-  const float gp = pixel(g, gpitch, v, u);
   float z = 0.f;
 #pragma unroll
   for (int j = 0; j < K; ++j)
@@ -60,12 +62,24 @@ __global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, 
         wt = bilateral_weight(pixel(g, gpitch, y, x), gp, j - A, k - A, bk);
       z += wt;
     }
+  return z;
+}
+
+// 1 / sum of the Eq. 9-10 weights of each pixel's window.
+template <int A>
+__global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, int64_t gpitch, int H,
+                                                   int W, BilateralK bk,
+                                                   float* __restrict__ zinv) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (u >= W || v >= H) return;
+  const float z = window_weight_sum<A>(g, gpitch, H, W, v, u, pixel(g, gpitch, v, u), bk);
   zinv[static_cast<int64_t>(v) * W + u] = 1.f / z;
 }
 
 struct AdjLayout {
-  int hl, ltw, lth, wtw, wth, ztw, zth;
-  size_t off_lt, off_wt, off_zt, off_dt, off_gl, off_gw, off_col, off_red, bytes;
+  int hl, ltw, lth, wtw, wth, ztw, zth, tsw;
+  size_t off_red, off_ts, off_lt, off_wt, off_zt, off_dt, off_gl, off_gw, off_col, bytes;
 };
 
 __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
@@ -77,9 +91,12 @@ __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
   L.wth = kAdjTY + 2 * R;
   L.ztw = kAdjTX + 2 * A;
   L.zth = kAdjTY + 2 * A;
+  L.tsw = kAdjTX + D - 1;  // target block centres per tile row
   size_t o = 0;
-  L.off_red = o;  // doubles first (8-byte aligned)
+  L.off_red = o;  // 8-byte items first
   o += sizeof(double) * 4 * kAdjThreads;
+  L.off_ts = o;
+  o += sizeof(float2) * L.tsw * kAdjTY;
   L.off_lt = o;
   o += sizeof(float) * L.ltw * L.lth;
   L.off_wt = o;
@@ -102,7 +119,7 @@ template <int R, int A>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
     const float* __restrict__ left, int64_t lpitch, const float* __restrict__ right, int64_t rpitch,
     int H, int W, int D, rsv_plane pl, BilateralK bk, float sigma_min,
-    const float* __restrict__ cost, const float* __restrict__ agg, const int32_t* __restrict__ disp,
+    const float* __restrict__ cost, int64_t cps, int64_t crs, const int32_t* __restrict__ disp,
     const uint8_t* __restrict__ mask, const float* __restrict__ zinv, float* __restrict__ gleft,
     float* __restrict__ gright, double* __restrict__ gplane, double* __restrict__ loss) {
   constexpr int K = 2 * R + 1;
@@ -111,6 +128,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   const AdjLayout Ly = adj_layout(R, A, D);
   double* red = reinterpret_cast<double*>(smem + Ly.off_red);
+  float2* ts = reinterpret_cast<float2*>(smem + Ly.off_ts);
   float* lt = reinterpret_cast<float*>(smem + Ly.off_lt);
   float* wt = reinterpret_cast<float*>(smem + Ly.off_wt);
   float* zt = reinterpret_cast<float*>(smem + Ly.off_zt);
@@ -128,8 +146,8 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   const int lx0 = x0 - hl, ly0 = y0 - hl;                // left tile / grad-left origin
   const int wx0 = x0 - (D - 1) - R, wy0 = y0 - R;        // warped tile / grad-warped origin
   const int zx0 = x0 - A, zy0 = y0 - A;                  // Omega tile origin
-  const int64_t plane = static_cast<int64_t>(H) * W;
 
+  // Tiles hold clamp-to-edge reads at every position of the tile.
   for (int i = tid; i < Ly.ltw * Ly.lth; i += kAdjThreads) {
     const int r = i / Ly.ltw, c = i - r * Ly.ltw;
     lt[i] = left[static_cast<int64_t>(clampi(ly0 + r, 0, H - 1)) * lpitch + clampi(lx0 + c, 0, W - 1)];
@@ -151,29 +169,66 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   }
   __syncthreads();
 
-  // Left block of q (clamp-to-edge reads) and its statistics.
-  float lb[K][K];
+  // Statistics of every target block the tile's pixels meet: the block centred on
+  // tile row r, column x0 - (D - 1) + c (mean, and 1/sqrt(S_rr), or 0 where the block
+  // std-dev is below sigma_min and the correlation is the constant 0).
+  for (int i = tid; i < Ly.tsw * kAdjTY; i += kAdjThreads) {
+    const int r = i / Ly.tsw, c = i - r * Ly.tsw;
+    const float* tb = wt + r * Ly.wtw + c;
+    double S = 0.0, Q = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double x = tb[j * Ly.wtw + k];
+        S += x;
+        Q = fma(x, x, Q);
+      }
+    const double srr = fmax(Q - S * S / N, 0.0);
+    const bool ok = sqrt(srr / N) >= static_cast<double>(sigma_min);
+    ts[i] = make_float2(static_cast<float>(S / N), ok ? static_cast<float>(1.0 / sqrt(srr)) : 0.f);
+  }
+
+  // Left block of q (clamp-to-edge reads), centred, and its statistics.
+  float lc[K][K];
   double S = 0.0, Q = 0.0;
 #pragma unroll
   for (int j = 0; j < K; ++j)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float x = lt[(ty + hl - R + j) * Ly.ltw + tx + hl - R + k];
-      lb[j][k] = x;
+      lc[j][k] = x;
       S += x;
       Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
     }
-  const double mul = S / N;
   const double sll = fmax(Q - S * S / N, 0.0);
   const bool okl = sqrt(sll / N) >= static_cast<double>(sigma_min);
+  const float mul = static_cast<float>(S / N);
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) lc[j][k] -= mul;
+  const float inv_l = okl ? static_cast<float>(1.0 / sqrt(sll)) : 0.f;
   const float gq = lt[(ty + hl) * Ly.ltw + tx + hl];
 
-  // dL/dw terms (q in the role of p) and the loss.
+  // q in the role of p: A(q) at its selected disparity, the loss, and the dL/dw terms.
   double loss_part = 0.0;
   const int my_d = dt[(ty + A) * Ly.ztw + tx + A];
   if (in && my_d >= 0) {
-    const float Aq = agg[my_d * plane + static_cast<int64_t>(qy) * W + qx];
     const float zi = zt[(ty + A) * Ly.ztw + tx + A];
+    const float* cd = cost + my_d * cps;
+    float num = 0.f;
+#pragma unroll
+    for (int j = 0; j < KA; ++j)
+#pragma unroll
+      for (int k = 0; k < KA; ++k) {
+        const int Y = qy + j - A, X = qx + k - A;
+        if (X >= 0 && X < W && Y >= 0 && Y < H) {
+          const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
+          num = fmaf(bilateral_weight(gx, gq, j - A, k - A, bk), cd[Y * crs + X], num);
+        }
+      }
+    const float Aq = num * zi;
     loss_part = Aq;
     float s = 0.f;
 #pragma unroll
@@ -184,16 +239,25 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
         if (X >= 0 && X < W && Y >= 0 && Y < H) {
           const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
           const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
-          const float c = cost[my_d * plane + static_cast<int64_t>(Y) * W + X];
-          const float t = (c - Aq) * zi * bilateral_weight_dgq(w, gx, gq, bk);
+          const float t = (cd[Y * crs + X] - Aq) * zi * bilateral_weight_dgq(w, gx, gq, bk);
           atomicAdd(&gl[(Y - ly0) * Ly.ltw + X - lx0], t);
           s += t;
         }
       }
     atomicAdd(&gl[(qy - ly0) * Ly.ltw + qx - lx0], -s);
   }
+  __syncthreads();  // target statistics complete
 
-  // ZNCC adjoint, 64 disparities at a time.
+  // ZNCC adjoint, 64 disparities at a time.  The left-block gradient of q is the same
+  // 49 (81) positions for every d, so it stays in registers: sum_d a_d (r - mu_r) and
+  // the scalar sum_d b_d, which multiplies the centred left block once at the end.
+  float gacc[K][K];
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) gacc[j][k] = 0.f;
+  float bsum = 0.f;
+  const float* cq = cost + static_cast<int64_t>(qy) * crs + qx;
   for (int d0 = 0; d0 < D; d0 += kAdjDChunk) {
     for (int i = 0; i < kAdjDChunk; ++i) col[i * kAdjThreads + tid] = 0.f;
     if (in) {
@@ -216,55 +280,51 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
         const float G = col[i * kAdjThreads + tid];
         if (G == 0.f) continue;
         const int d = d0 + i;
-        const float* tb = wt + ty * Ly.wtw + tx - d + (D - 1);  // target block top-left
-        double Sr = 0.0, Qr = 0.0;
+        const int tc = tx - d + (D - 1);                  // target block column in the tile
+        const float2 st = ts[ty * Ly.tsw + tc];
+        if (st.y == 0.f) continue;                        // flat target block: c == 0
+        const float c = cq[static_cast<int64_t>(d) * cps];
+        const float a = G * inv_l * st.y;
+        const float g = G * c * st.y * st.y;
+        bsum = fmaf(G * c, inv_l * inv_l, bsum);
+        const float* tb = wt + ty * Ly.wtw + tc;
+        float* gb = gw + ty * Ly.wtw + tc;
 #pragma unroll
         for (int j = 0; j < K; ++j)
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            const double r = tb[j * Ly.wtw + k];
-            Sr += r;
-            Qr = fma(r, r, Qr);
+            const float r = tb[j * Ly.wtw + k] - st.x;
+            gacc[j][k] = fmaf(a, r, gacc[j][k]);
+            atomicAdd(&gb[j * Ly.wtw + k], fmaf(a, lc[j][k], -g * r));
           }
-        const double srr = fmax(Qr - Sr * Sr / N, 0.0);
-        if (!(sqrt(srr / N) >= static_cast<double>(sigma_min))) continue;
-        const double mur = Sr / N;
-        const double c = cost[d * plane + static_cast<int64_t>(qy) * W + qx];
-        const double a = G / sqrt(sll * srr);
-        const double b = G * c / sll;
-        const double g = G * c / srr;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int Yl = clampi(qy + j - R, 0, H - 1);
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const double l = static_cast<double>(lb[j][k]) - mul;
-            const double r = static_cast<double>(tb[j * Ly.wtw + k]) - mur;
-            const int Xl = clampi(qx + k - R, 0, W - 1);
-            const int Xw = clampi(qx - d + k - R, 0, W - 1);
-            atomicAdd(&gl[(Yl - ly0) * Ly.ltw + Xl - lx0], static_cast<float>(a * r - b * l));
-            atomicAdd(&gw[(Yl - wy0) * Ly.wtw + Xw - wx0], static_cast<float>(a * l - g * r));
-          }
-        }
       }
     }
   }
+  if (in && okl) {
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        atomicAdd(&gl[(ty + hl - R + j) * Ly.ltw + tx + hl - R + k], fmaf(-bsum, lc[j][k], gacc[j][k]));
+  }
   __syncthreads();
 
-  // Flush: left-image gradient.
+  // Flush: left-image gradient; positions outside the image belong to their
+  // clamp-to-edge pixel.
   for (int i = tid; i < Ly.ltw * Ly.lth; i += kAdjThreads) {
-    const int r = i / Ly.ltw, c = i - r * Ly.ltw;
-    const int Y = ly0 + r, X = lx0 + c;
     const float g = gl[i];
-    if (g != 0.f && X >= 0 && X < W && Y >= 0 && Y < H) atomicAdd(&gleft[static_cast<int64_t>(Y) * W + X], g);
+    if (g == 0.f) continue;
+    const int r = i / Ly.ltw, c = i - r * Ly.ltw;
+    const int Y = clampi(ly0 + r, 0, H - 1), X = clampi(lx0 + c, 0, W - 1);
+    atomicAdd(&gleft[static_cast<int64_t>(Y) * W + X], g);
   }
   // Flush: warped-image gradient through the warp transpose, and the plane gradient.
   double t0 = 0.0, t1 = 0.0, t2 = 0.0;
   for (int i = tid; i < Ly.wtw * Ly.wth; i += kAdjThreads) {
-    const int r = i / Ly.wtw, c = i - r * Ly.wtw;
-    const int Y = wy0 + r, X = wx0 + c;
     const float g = gw[i];
-    if (g == 0.f || X < 0 || X >= W || Y < 0 || Y >= H) continue;
+    if (g == 0.f) continue;
+    const int r = i / Ly.wtw, c = i - r * Ly.wtw;
+    const int Y = clampi(wy0 + r, 0, H - 1), X = clampi(wx0 + c, 0, W - 1);
     const WarpTap tap = warp_tap(pl, X, Y, W);
     const float* row = right + static_cast<int64_t>(Y) * rpitch;
     const double i0 = row[tap.c0], i1 = row[tap.c1];
@@ -293,17 +353,29 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   }
 }
 
+struct AdjointArgs {
+  rsv_image l, r;
+  rsv_plane pl;
+  const rsv_params* p;
+  const float* cost;
+  int64_t cps, crs;
+  const int32_t* disp;
+  const uint8_t* mask;
+  float *gl, *gr;
+  double *gp, *loss;
+  float* zinv;
+};
+
 template <int R, int A>
-int launch_adjoint(const rsv_image& l, const rsv_image& r, rsv_plane pl, const rsv_params* p,
-                   const float* cost, const float* agg, const int32_t* disp, const uint8_t* mask,
-                   float* gl, float* gr, double* gp, double* loss, float* zinv, hipStream_t st) {
-  const int H = l.height, W = l.width, D = p->D;
-  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+int launch_adjoint(const AdjointArgs& a, hipStream_t st) {
+  const int H = a.l.height, W = a.l.width, D = a.p->D;
+  const BilateralK bk = bilateral_constants(a.p->gamma_d, a.p->gamma_r);
   const int64_t n = static_cast<int64_t>(H) * W;
-  adjoint_zero_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st>>>(gl, gr, n, gp, loss);
+  adjoint_zero_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st>>>(a.gl, a.gr, n,
+                                                                                           a.gp, a.loss);
   if (int s = check_launch()) return s;
   zinv_kernel<A><<<dim3((W + 255) / 256, H), dim3(256), 0, st>>>(
-      static_cast<const float*>(l.data), l.pitch, H, W, bk, zinv);
+      static_cast<const float*>(a.l.data), a.l.pitch, H, W, bk, a.zinv);
   if (int s = check_launch()) return s;
   const AdjLayout Ly = adj_layout(R, A, D);
   auto kern = adjoint_kernel<R, A>;
@@ -318,24 +390,125 @@ int launch_adjoint(const rsv_image& l, const rsv_image& r, rsv_plane pl, const r
   }
   const dim3 grid((W + kAdjTX - 1) / kAdjTX, (H + kAdjTY - 1) / kAdjTY);
   kern<<<grid, dim3(kAdjThreads), Ly.bytes, st>>>(
-      static_cast<const float*>(l.data), l.pitch, static_cast<const float*>(r.data), r.pitch, H, W, D,
-      pl, bk, p->sigma_min, cost, agg, disp, mask, zinv, gl, gr, gp, loss);
+      static_cast<const float*>(a.l.data), a.l.pitch, static_cast<const float*>(a.r.data), a.r.pitch, H, W, D,
+      a.pl, bk, a.p->sigma_min, a.cost, a.cps, a.crs, a.disp, a.mask, a.zinv, a.gl, a.gr, a.gp, a.loss);
   return check_launch();
 }
 
 template <int R>
-int dispatch_adjoint_a(const rsv_image& l, const rsv_image& r, rsv_plane pl, const rsv_params* p,
-                       const float* cost, const float* agg, const int32_t* disp, const uint8_t* mask,
-                       float* gl, float* gr, double* gp, double* loss, float* zinv, hipStream_t st) {
-  switch (p->agg_radius) {
-    case 1: return launch_adjoint<R, 1>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
-    case 2: return launch_adjoint<R, 2>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
-    case 3: return launch_adjoint<R, 3>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
-    case 4: return launch_adjoint<R, 4>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
-    case 5: return launch_adjoint<R, 5>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
-    case 6: return launch_adjoint<R, 6>(l, r, pl, p, cost, agg, disp, mask, gl, gr, gp, loss, zinv, st);
+int dispatch_adjoint_a(const AdjointArgs& a, hipStream_t st) {
+  switch (a.p->agg_radius) {
+    case 1: return launch_adjoint<R, 1>(a, st);
+    case 2: return launch_adjoint<R, 2>(a, st);
+    case 3: return launch_adjoint<R, 3>(a, st);
+    case 4: return launch_adjoint<R, 4>(a, st);
+    case 5: return launch_adjoint<R, 5>(a, st);
+    case 6: return launch_adjoint<R, 6>(a, st);
     default: return RSV_E_PARAM;
   }
+}
+
+// Checks of a strided view cost(d, v, u) = cost[d*plane_stride + v*row_stride + u]
+// over D x H x W (32-bit offsets within a plane, 64-bit across planes).
+inline int validate_cost_view(const float* cost, int64_t plane_stride, int64_t row_stride, int H, int W,
+                              int D) {
+  if (!cost) return RSV_E_NULL;
+  if (row_stride < W || plane_stride < 1) return RSV_E_SHAPE;
+  if (static_cast<int64_t>(H - 1) * row_stride + W > INT32_MAX) return RSV_E_SHAPE;
+  if (plane_stride > INT64_MAX / (D > 0 ? D : 1)) return RSV_E_SHAPE;
+  if (!aligned(cost, 4)) return RSV_E_ALIGN;
+  return RSV_OK;
+}
+
+int validate_adjoint(const rsv_image& left, const rsv_image& right, const rsv_params* p, const float* cost,
+                     int64_t cps, int64_t crs, const int32_t* disp, const uint8_t* mask, const float* gl,
+                     const float* gr, const double* gp, const double* loss) {
+  if (int s = validate_image(left)) return s;
+  if (int s = validate_image(right)) return s;
+  if (int s = validate_cost_params(p)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (left.dtype != RSV_F32 || right.dtype != RSV_F32) return RSV_E_DTYPE;
+  if (!disp || !mask || !gl || !gr || !gp) return RSV_E_NULL;
+  if (left.height != right.height || left.width != right.width) return RSV_E_SHAPE;
+  if (p->D > kAdjMaxD) return RSV_E_SHAPE;
+  const int K = 2 * p->block_radius + 1;
+  if (left.height < K || left.width < K) return RSV_E_SHAPE;
+  if (int s = validate_cost_view(cost, cps, crs, left.height, left.width, p->D)) return s;
+  if (!aligned(disp, 4) || !aligned(gl, 4) || !aligned(gr, 4) || !aligned(gp, 8) || (loss && !aligned(loss, 8)))
+    return RSV_E_ALIGN;
+  return RSV_OK;
+}
+
+int run_adjoint(const AdjointArgs& a, hipStream_t st) {
+  switch (a.p->block_radius) {
+    case 1: return dispatch_adjoint_a<1>(a, st);
+    case 2: return dispatch_adjoint_a<2>(a, st);
+    case 3: return dispatch_adjoint_a<3>(a, st);
+    case 4: return dispatch_adjoint_a<4>(a, st);
+    default: return RSV_E_PARAM;
+  }
+}
+
+// Loss of the differentiable form from a cost volume: per pixel p in Omega the
+// aggregation of Eq. 8 at its one selected disparity (the weights of Eq. 9-10, the
+// same window sums as the adjoint), summed in double; one atomic per block.
+template <int A, typename T>
+__global__ __launch_bounds__(256) void selected_aggregate_sum_kernel(
+    const float* __restrict__ cost, int64_t cps, int64_t crs, const T* __restrict__ g, int64_t gpitch,
+    int H, int W, int D, BilateralK bk, const int32_t* __restrict__ disp, const uint8_t* __restrict__ mask,
+    double* __restrict__ out) {
+  constexpr int K = 2 * A + 1;
+  __shared__ double red[256];
+  const int u = blockIdx.x * 16 + threadIdx.x % 16;
+  const int v = blockIdx.y * 16 + threadIdx.x / 16;
+  double part = 0.0;
+  if (u < W && v < H) {
+    const int64_t i = static_cast<int64_t>(v) * W + u;
+    const int d = disp[i];
+    if (mask[i] && d >= 0 && d < D) {
+      const float gp = pixel(g, gpitch, v, u);
+      const float z = window_weight_sum<A>(g, gpitch, H, W, v, u, gp, bk);
+      const float* cd = cost + d * cps;
+      float num = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int y = v + j - A, x = u + k - A;
+          if (x >= 0 && x < W && y >= 0 && y < H)
+            num = fmaf(bilateral_weight(pixel(g, gpitch, y, x), gp, j - A, k - A, bk), cd[y * crs + x], num);
+        }
+      part = num * (1.f / z);
+    }
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+template <typename T>
+int launch_selected_aggregate_sum(const float* cost, int64_t cps, int64_t crs, const rsv_image& guide,
+                                  const rsv_params* p, const int32_t* disp, const uint8_t* mask, double* out,
+                                  hipStream_t st) {
+  const int H = guide.height, W = guide.width;
+  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+  const dim3 grid((W + 15) / 16, (H + 15) / 16);
+  const T* g = static_cast<const T*>(guide.data);
+#define RSV_SAS(A_)                                                                                   \
+  case A_:                                                                                            \
+    selected_aggregate_sum_kernel<A_, T><<<grid, 256, 0, st>>>(cost, cps, crs, g, guide.pitch, H, W,  \
+                                                               p->D, bk, disp, mask, out);            \
+    break;
+  switch (p->agg_radius) {
+    RSV_SAS(1) RSV_SAS(2) RSV_SAS(3) RSV_SAS(4) RSV_SAS(5) RSV_SAS(6)
+    default: return RSV_E_PARAM;
+  }
+#undef RSV_SAS
+  return check_launch();
 }
 
 // Sum of agg[disp(p)][p] over pixels with mask(p) != 0 (the loss of the
@@ -381,38 +554,41 @@ extern "C" int rsv_selected_cost_sum(const float* agg_ref, const int32_t* disp, 
   return check_launch();
 }
 
+extern "C" int rsv_selected_aggregate_sum(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                          rsv_image guide, const rsv_params* p, const int32_t* disp,
+                                          const uint8_t* mask, double* out, void* stream) {
+  using namespace rsv;
+  if (int s = validate_image(guide)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (!disp || !mask || !out) return RSV_E_NULL;
+  if (int s = validate_cost_view(cost, plane_stride, row_stride, guide.height, guide.width, p->D)) return s;
+  if (!aligned(disp, 4) || !aligned(out, 8)) return RSV_E_ALIGN;
+  hipStream_t st = as_stream(stream);
+  zero_double_kernel<<<1, 1, 0, st>>>(out);
+  if (int s = check_launch()) return s;
+  if (guide.dtype == RSV_U8)
+    return launch_selected_aggregate_sum<uint8_t>(cost, plane_stride, row_stride, guide, p, disp, mask, out, st);
+  return launch_selected_aggregate_sum<float>(cost, plane_stride, row_stride, guide, p, disp, mask, out, st);
+}
+
 extern "C" size_t rsv_cost_adjoint_workspace_bytes(int32_t height, int32_t width) {
   if (height < 1 || width < 1) return 0;
   return sizeof(float) * static_cast<size_t>(height) * static_cast<size_t>(width);
 }
 
 extern "C" int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
-                                const float* cost_ref, const float* agg_ref, const int32_t* disp,
-                                const uint8_t* mask, float* grad_left, float* grad_right,
-                                double* grad_plane, double* loss, void* workspace, void* stream) {
+                                const float* cost, int64_t plane_stride, int64_t row_stride,
+                                const int32_t* disp, const uint8_t* mask, float* grad_left,
+                                float* grad_right, double* grad_plane, double* loss, void* workspace,
+                                void* stream) {
   using namespace rsv;
-  if (int s = validate_image(left)) return s;
-  if (int s = validate_image(right)) return s;
-  if (int s = validate_cost_params(p)) return s;
-  if (int s = validate_agg_params(p)) return s;
-  if (left.dtype != RSV_F32 || right.dtype != RSV_F32) return RSV_E_DTYPE;
-  if (!cost_ref || !agg_ref || !disp || !mask || !grad_left || !grad_right || !grad_plane || !workspace)
-    return RSV_E_NULL;
-  if (left.height != right.height || left.width != right.width) return RSV_E_SHAPE;
-  if (p->D > kAdjMaxD) return RSV_E_SHAPE;
-  const int K = 2 * p->block_radius + 1;
-  if (left.height < K || left.width < K) return RSV_E_SHAPE;
-  if (!aligned(cost_ref, 4) || !aligned(agg_ref, 4) || !aligned(disp, 4) || !aligned(grad_left, 4) ||
-      !aligned(grad_right, 4) || !aligned(grad_plane, 8) || (loss && !aligned(loss, 8)) ||
-      !aligned(workspace, 4))
-    return RSV_E_ALIGN;
-  float* zinv = static_cast<float*>(workspace);
-  hipStream_t st = as_stream(stream);
-  switch (p->block_radius) {
-    case 1: return dispatch_adjoint_a<1>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
-    case 2: return dispatch_adjoint_a<2>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
-    case 3: return dispatch_adjoint_a<3>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
-    case 4: return dispatch_adjoint_a<4>(left, right, plane, p, cost_ref, agg_ref, disp, mask, grad_left, grad_right, grad_plane, loss, zinv, st);
-    default: return RSV_E_PARAM;
-  }
+  if (int s = validate_adjoint(left, right, p, cost, plane_stride, row_stride, disp, mask, grad_left,
+                               grad_right, grad_plane, loss))
+    return s;
+  if (!workspace) return RSV_E_NULL;
+  if (!aligned(workspace, 4)) return RSV_E_ALIGN;
+  const AdjointArgs a{left, right, plane, p, cost, plane_stride, row_stride, disp, mask,
+                      grad_left, grad_right, grad_plane, loss, static_cast<float*>(workspace)};
+  return run_adjoint(a, as_stream(stream));
 }
+

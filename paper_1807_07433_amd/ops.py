@@ -288,19 +288,44 @@ def selected_cost_sum(agg_ref: torch.Tensor, disp: torch.Tensor, mask: torch.Ten
     return out
 
 
+def _cost_view(cost: torch.Tensor, D: int, H: int, W: int):
+    _dev(cost, "cost", torch.float32, (D, H, W))
+    if cost.stride(2) != 1:
+        raise ValueError("cost views need unit column stride")
+    return cost.stride(0), cost.stride(1)
+
+
+def selected_aggregate_sum(cost: torch.Tensor, guide: torch.Tensor, params, disp: torch.Tensor,
+                           mask: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Loss of the differentiable form from a cost volume or view (rsv_selected_aggregate_sum):
+    the aggregation of Eq. 8 at disp(p), summed over mask(p) != 0, with no aggregated volume."""
+    lib = load()
+    H, W = guide.shape
+    D = int(params.D)
+    cps, crs = _cost_view(cost, D, H, W)
+    _contig(disp, "disp", torch.int32, (H, W))
+    _contig(mask, "mask", torch.uint8, (H, W))
+    out = out if out is not None else torch.empty((), dtype=torch.float64, device=cost.device)
+    _contig(out, "out", torch.float64, ())
+    p = _params(params)
+    check(lib.rsv_selected_aggregate_sum(cost.data_ptr(), cps, crs, image(guide, "guide"), C.byref(p),
+                                         disp.data_ptr(), mask.data_ptr(), out.data_ptr(),
+                                         _stream(cost.device)), "rsv_selected_aggregate_sum")
+    return out
+
+
 def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_ref: torch.Tensor,
-                 agg_ref: torch.Tensor, disp: torch.Tensor, mask: torch.Tensor,
-                 workspace: torch.Tensor | None = None):
-    """Gradients of selected_cost_sum(agg_ref, disp, mask) with respect to the left
-    image, the right image and the plane terms (a0, a1, a2); also returns the loss.
-    left/right are float32; cost_ref/agg_ref are the forward's volumes."""
+                 disp: torch.Tensor, mask: torch.Tensor, workspace: torch.Tensor | None = None):
+    """Gradients of the loss sum_{mask} A_ref(p, disp(p)) with respect to the left image,
+    the right image and the plane terms (a0, a1, a2); also returns the loss.  left/right
+    are float32; cost_ref is the forward's reference cost volume, dense or a view with
+    unit column stride (e.g. joint_views(...)[0])."""
     lib = load()
     H, W = left.shape
     D = int(params.D)
     _dev(left, "left", torch.float32)
     _dev(right, "right", torch.float32, (H, W))
-    _contig(cost_ref, "cost_ref", torch.float32, (D, H, W))
-    _contig(agg_ref, "agg_ref", torch.float32, (D, H, W))
+    cps, crs = _cost_view(cost_ref, D, H, W)
     _contig(disp, "disp", torch.int32, (H, W))
     _contig(mask, "mask", torch.uint8, (H, W))
     dev = left.device
@@ -313,9 +338,9 @@ def cost_adjoint(left: torch.Tensor, right: torch.Tensor, plane, params, cost_re
     loss = torch.empty((), dtype=torch.float64, device=dev)
     p = _params(params)
     check(lib.rsv_cost_adjoint(image(left, "left"), image(right, "right"), _plane(plane), C.byref(p),
-                               cost_ref.data_ptr(), agg_ref.data_ptr(), disp.data_ptr(),
-                               mask.data_ptr(), gl.data_ptr(), gr.data_ptr(), gp.data_ptr(),
-                               loss.data_ptr(), workspace.data_ptr(), _stream(dev)),
+                               cost_ref.data_ptr(), cps, crs, disp.data_ptr(), mask.data_ptr(),
+                               gl.data_ptr(), gr.data_ptr(), gp.data_ptr(), loss.data_ptr(),
+                               workspace.data_ptr(), _stream(dev)),
           "rsv_cost_adjoint")
     return gl, gr, gp, loss
 
@@ -361,4 +386,5 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
            "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select",
            "aggregate_select_supported", "select_subpixel",
-           "triangulate", "reconstruct", "selected_cost_sum", "cost_adjoint", "image", "load"]
+           "triangulate", "reconstruct", "selected_cost_sum", "selected_aggregate_sum", "cost_adjoint",
+           "image", "load"]

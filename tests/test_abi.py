@@ -130,7 +130,8 @@ def test_adjoint_validation(lib):
     pl = _lib.Plane(1.0, 0.1, 0.0, 2.0)
     p = _params(D=16)
     f32 = _img(dtype=_lib.RSV_F32)
-    args = [FAKE] * 8 + [FAKE, None]   # cost, agg, disp, mask, gl, gr, gp, loss, ws, stream
+    # cost, plane stride, row stride, disp, mask, gl, gr, gp, loss, ws, stream
+    args = [FAKE, 32 * 48, 48] + [FAKE] * 6 + [FAKE, None]
     assert lib.rsv_cost_adjoint_workspace_bytes(10, 20) == 800
     assert lib.rsv_cost_adjoint_workspace_bytes(0, 20) == 0
     assert lib.rsv_cost_adjoint(_img(), f32, pl, C.byref(p), *args) == -4     # u8 left
@@ -138,11 +139,31 @@ def test_adjoint_validation(lib):
     assert lib.rsv_cost_adjoint(f32, _img(h=31, dtype=_lib.RSV_F32), pl, C.byref(p), *args) == -2
     assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(_params(agg_radius=9)), *args) == -3
     a = list(args)
-    a[8] = None
+    a[9] = None                      # workspace
     assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -1
     a = list(args)
-    a[6] = FAKE + 4                  # grad_plane must be 8-byte aligned
+    a[0] = None                      # cost
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -1
+    a = list(args)
+    a[2] = 47                        # row stride shorter than a row
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -2
+    a = list(args)
+    a[1] = 0                         # no plane stride
+    assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -2
+    a = list(args)
+    a[7] = FAKE + 4                  # grad_plane must be 8-byte aligned
     assert lib.rsv_cost_adjoint(f32, f32, pl, C.byref(p), *a) == -5
+
+
+def test_selected_aggregate_sum_validation(lib):
+    p = _params(D=16)
+    f = lib.rsv_selected_aggregate_sum
+    assert f(None, 32 * 48, 48, _img(), C.byref(p), FAKE, FAKE, FAKE, None) == -1
+    assert f(FAKE, 32 * 48, 48, _img(), C.byref(p), None, FAKE, FAKE, None) == -1
+    assert f(FAKE, 32 * 48, 47, _img(), C.byref(p), FAKE, FAKE, FAKE, None) == -2
+    assert f(FAKE, 32 * 48, 48, _img(), C.byref(_params(agg_radius=0)), FAKE, FAKE, FAKE, None) == -3
+    assert f(FAKE, 32 * 48, 48, _img(), C.byref(p), FAKE, FAKE, FAKE + 4, None) == -5
+    assert f(FAKE, 32 * 48, 48, _img(dtype=7), C.byref(p), FAKE, FAKE, FAKE, None) == -4
 
 
 @pytest.mark.parametrize("stride", [48 + 32 - 2, 2**31 // 32 + 1])

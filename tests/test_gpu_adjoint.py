@@ -2,9 +2,10 @@
 gradient (itself pinned to central differences in test_oracle_adjoint.py), the loss
 against the oracle loss, and the plane refinement on the 8-pair 1280x720 workload.
 
-Tolerance: the GPU computes in FP32 with float atomics, so gradients are compared
-with rtol 1e-3: |g_gpu - g_ref| <= 1e-3 * max|g_ref| elementwise for the images and
-|g_gpu - g_ref| <= 1e-3 * |g_ref| + 1e-6 * max|g_ref| for the three plane terms.
+Tolerance: the GPU computes in FP32 with float atomics.  Image gradients are held
+elementwise to |g_gpu - g_ref| <= 1e-3 * |g_ref| + 2e-5 * max|g_ref| (every pixel,
+the clamped border pixels included, which also get their own report); the three
+plane terms to |g_gpu - g_ref| <= 1e-3 * |g_ref| + 1e-6 * max|g_ref|.
 """
 import numpy as np
 import pytest
@@ -25,12 +26,21 @@ def _gpu(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _compare(tag, gpu, ref, rtol=1e-3):
+def _compare(tag, gpu, ref, rtol=1e-3, atol=2e-5, border=0):
     gpu = np.asarray(gpu, np.float64)
     scale = np.abs(ref).max()
-    err = np.abs(gpu - ref).max()
-    _say(f"  {tag}: max|err| {err:.3e}  scale {scale:.3e}")
-    assert err <= rtol * scale, f"{tag}: {err:.3e} > {rtol} * {scale:.3e}"
+    err = np.abs(gpu - ref)
+    bound = rtol * np.abs(ref) + atol * scale
+    worst = float((err / bound).max())
+    _say(f"  {tag}: max|err| {err.max():.3e}  scale {scale:.3e}  worst err/bound {worst:.3f}")
+    if border:
+        edge = np.ones(ref.shape, bool)
+        edge[border:-border, border:-border] = False
+        rel = err[edge] / np.maximum(np.abs(ref[edge]), 1e-30)
+        big = np.abs(ref[edge]) >= 1e-3 * scale
+        _say(f"  {tag} border ({border} px): max|err| {err[edge].max():.3e}  "
+             f"max rel err where |g| >= 1e-3 max: {rel[big].max() if big.any() else 0.0:.3e}")
+    assert worst <= 1.0, f"{tag}: elementwise error exceeds {rtol}*|g| + {atol}*max|g| (x{worst:.2f})"
 
 
 CASES = [
@@ -55,15 +65,26 @@ def test_adjoint_matches_oracle_gradient(rsv_gpu, H, W, D, r, rho, seed, plane):
     wp = rsv.warp(R, plane)
     cref, _ = rsv.cost_volume(L, wp, prm, want_tar=False)
     aref = rsv.aggregate(cref, L, prm)
-    gl, gr, gp, loss = rsv.cost_adjoint(L, R, plane, prm, cref, aref, _gpu(disp), _gpu(mask))
+    gl, gr, gp, loss = rsv.cost_adjoint(L, R, plane, prm, cref, _gpu(disp), _gpu(mask))
     lsum = rsv.selected_cost_sum(aref, _gpu(disp), _gpu(mask))
+    lagg = rsv.selected_aggregate_sum(cref, L, prm, _gpu(disp), _gpu(mask))
+    jref, _ = rsv.joint_views(rsv.cost_volume_joint(L, wp, prm), W)
+    gl2, gr2, gp2, loss2 = rsv.cost_adjoint(L, R, plane, prm, jref, _gpu(disp), _gpu(mask))
     torch.cuda.synchronize()
     ref_loss, rgl, rgr, rgp = OA.grad(p.left, p.right, plane, disp, mask.astype(bool), r, rho, 2.5,
                                       0.1)
-    assert abs(float(loss) - ref_loss) <= 1e-4 * mask.sum()
-    assert abs(float(lsum) - float(loss)) <= 1e-9 * max(1.0, abs(ref_loss))
-    _compare("grad_left", gl.cpu().numpy(), rgl)
-    _compare("grad_right", gr.cpu().numpy(), rgr)
+    nm = mask.sum()
+    assert abs(float(loss) - ref_loss) <= 1e-4 * nm
+    # the three forms of the loss: aggregated volume, cost volume, in the adjoint
+    assert abs(float(lsum) - float(loss)) <= 1e-5 * nm
+    assert abs(float(lagg) - float(loss)) <= 1e-5 * nm
+    # the joint volume's reference view is the same cost volume
+    assert abs(float(loss2) - float(loss)) <= 1e-9 * nm
+    torch.testing.assert_close(gl2, gl, rtol=1e-5, atol=1e-6 * float(gl.abs().max()))
+    torch.testing.assert_close(gr2, gr, rtol=1e-5, atol=1e-6 * float(gr.abs().max()))
+    torch.testing.assert_close(gp2, gp, rtol=1e-6, atol=0.0)
+    _compare("grad_left", gl.cpu().numpy(), rgl, border=r + rho)
+    _compare("grad_right", gr.cpu().numpy(), rgr, border=r + rho)
     g = gp.cpu().numpy()
     _say(f"  grad_plane gpu {g}  oracle {rgp}")
     assert np.all(np.abs(g - rgp) <= 1e-3 * np.abs(rgp) + 1e-6 * np.abs(rgp).max())
@@ -76,7 +97,6 @@ def test_adjoint_out_of_range_disparity_is_ignored(rsv_gpu):
     L, R = _gpu(p.left), _gpu(p.right)
     wp = rsv.warp(R, (4.0, 0.0, 0.0, 2.0))
     cref, _ = rsv.cost_volume(L, wp, prm, want_tar=False)
-    aref = rsv.aggregate(cref, L, prm)
     disp = torch.full((24, 40), 2, dtype=torch.int32, device="cuda")
     mask = torch.ones((24, 40), dtype=torch.uint8, device="cuda")
     bad = disp.clone()
@@ -86,8 +106,11 @@ def test_adjoint_out_of_range_disparity_is_ignored(rsv_gpu):
     keep[5:9, 10:20] = 0
     keep[12, :] = 0
     _say("[adjoint] out-of-range disparities leave the loss")
-    a = rsv.cost_adjoint(L, R, (4.0, 0.0, 0.0, 2.0), prm, cref, aref, bad, mask)
-    b = rsv.cost_adjoint(L, R, (4.0, 0.0, 0.0, 2.0), prm, cref, aref, disp, keep)
+    a = rsv.cost_adjoint(L, R, (4.0, 0.0, 0.0, 2.0), prm, cref, bad, mask)
+    b = rsv.cost_adjoint(L, R, (4.0, 0.0, 0.0, 2.0), prm, cref, disp, keep)
+    la = rsv.selected_aggregate_sum(cref, L, prm, bad, mask)
+    lb = rsv.selected_aggregate_sum(cref, L, prm, disp, keep)
+    assert abs(float(la) - float(lb)) < 1e-9
     assert abs(float(a[3]) - float(b[3])) < 1e-9
     assert torch.allclose(a[0], b[0], atol=1e-5) and torch.allclose(a[1], b[1], atol=1e-5)
 
@@ -107,16 +130,15 @@ def test_adjoint_full_size_sampled_omega(rsv_gpu):
     mask = np.zeros((H, W), np.uint8)
     mask.flat[rng.choice(H * W, 2000, replace=False)] = 1
     wp = rsv.warp(R, plane)
-    cref, _ = rsv.cost_volume(L, wp, prm, want_tar=False)
-    aref = rsv.aggregate(cref, L, prm)
-    gl, gr, gp, loss = rsv.cost_adjoint(L, R, plane, prm, cref, aref, d, _gpu(mask))
+    cref, _ = rsv.joint_views(rsv.cost_volume_joint(L, wp, prm), W)
+    gl, gr, gp, loss = rsv.cost_adjoint(L, R, plane, prm, cref, d, _gpu(mask))
     torch.cuda.synchronize()
     dn = d.cpu().numpy()
     ref_loss, rgl, rgr, rgp = OA.grad(c.pair.left, c.pair.right, plane, dn, mask.astype(bool),
                                       prm.block_radius, prm.agg_radius, prm.gamma_d, prm.gamma_r)
     assert abs(float(loss) - ref_loss) <= 1e-4 * mask.sum()
-    _compare("grad_left", gl.cpu().numpy(), rgl)
-    _compare("grad_right", gr.cpu().numpy(), rgr)
+    _compare("grad_left", gl.cpu().numpy(), rgl, border=prm.block_radius + prm.agg_radius)
+    _compare("grad_right", gr.cpu().numpy(), rgr, border=prm.block_radius + prm.agg_radius)
     g = gp.cpu().numpy()
     _say(f"  grad_plane gpu {g}  oracle {rgp}")
     assert np.all(np.abs(g - rgp) <= 1e-3 * np.abs(rgp) + 1e-6 * np.abs(rgp).max())
@@ -138,9 +160,8 @@ def test_autograd_function_matches_adjoint(rsv_gpu):
     plane = (6.2, 0.05, 0.001, 5.0)
     wp = rsv.warp(R.detach(), plane)
     cref, _ = rsv.cost_volume(L.detach(), wp, prm, want_tar=False)
-    aref = rsv.aggregate(cref, L.detach(), prm)
-    gl, gr, gp, l2 = rsv.cost_adjoint(L.detach(), R.detach(), plane, prm, cref, aref, disp, mask)
-    assert abs(float(loss) - float(l2)) < 1e-9
+    gl, gr, gp, l2 = rsv.cost_adjoint(L.detach(), R.detach(), plane, prm, cref, disp, mask)
+    assert abs(float(loss.detach()) - float(l2)) < 1e-5 * 40 * 90
     assert torch.allclose(L.grad, 2 * gl, rtol=1e-4, atol=1e-6)
     assert torch.allclose(R.grad, 2 * gr, rtol=1e-4, atol=1e-6)
     assert torch.allclose(theta.grad, 2 * gp.cpu(), rtol=1e-6)
