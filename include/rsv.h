@@ -358,6 +358,25 @@ int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane, const rsv
                      float* grad_right, double* grad_plane, double* loss, void* workspace,
                      void* stream);
 
+/* rsv_cost_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same arguments
+ * without `workspace`, and the same results (to float rounding, as any two runs).
+ * The workspace lives in a static device array inside the library, of
+ * RSV_ADJOINT_NOALLOC_MAX_PIXELS floats (8 MiB); every GPU the library runs this call
+ * on keeps its copy until the process ends.  The call uses the array of the calling
+ * thread's current device, so `stream` must belong to that device.  It allocates and
+ * frees nothing; its first call on a device resolves the array's device address.
+ * All calls on one GPU share that array, and nothing in it needs clearing between
+ * calls (every element a call reads it first writes), so calls that overlap on one
+ * GPU (concurrent streams or threads) race and must be serialised by the caller.
+ * Errors: as rsv_cost_adjoint; RSV_E_SHAPE also for H*W > RSV_ADJOINT_NOALLOC_MAX_PIXELS;
+ * RSV_E_HIP if the current device or the array's address cannot be obtained. */
+enum { RSV_ADJOINT_NOALLOC_MAX_PIXELS = 1 << 21 };
+int rsv_cost_adjoint_noalloc(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
+                             const float* cost, int64_t plane_stride, int64_t row_stride,
+                             const int32_t* disp, const uint8_t* mask, float* grad_left,
+                             float* grad_right, double* grad_plane, double* loss, void* stream);
+
 /* --------------------------------------------------------------- diagnostics */
 
 /* Text for a status code (static storage, never NULL). */

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_PKG, "librsv.so")
 
 RSV_U8, RSV_F32 = 0, 1
 RSV_MAX_D = 512
+RSV_ADJOINT_NOALLOC_MAX_PIXELS = 1 << 21
 
 STATUS = {0: "RSV_OK", -1: "RSV_E_NULL", -2: "RSV_E_SHAPE", -3: "RSV_E_PARAM",
           -4: "RSV_E_DTYPE", -5: "RSV_E_ALIGN", -6: "RSV_E_HIP", -7: "RSV_E_NOMEM"}
@@ -65,6 +66,8 @@ _SIGNATURES = {
                                              _P, _P]),
     "rsv_cost_adjoint": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, C.c_int64, C.c_int64, _P,
                                    _P, _P, _P, _P, _P, _P, _P]),
+    "rsv_cost_adjoint_noalloc": (C.c_int, [Image, Image, Plane, C.POINTER(Params), _P, C.c_int64, C.c_int64,
+                                           _P, _P, _P, _P, _P, _P, _P]),
     "rsv_tuning_default": (None, [_P]),
     "rsv_batch_plan_create": (C.c_int, [_P, C.c_int32, C.POINTER(Params), _P, _P]),
     "rsv_batch_run": (C.c_int, [_P, _P]),

@@ -23,6 +23,8 @@
 // edge pixel only at the flush.  The warped-image gradient goes through the transpose
 // of the interpolation into the right image, and its shift derivative
 // -(I1 - I0) (1, v, u) into the plane gradient.
+#include <mutex>
+
 #include "bilateral_math.hpp"
 #include "warp_math.hpp"
 
@@ -592,3 +594,62 @@ extern "C" int rsv_cost_adjoint(rsv_image left, rsv_image right, rsv_plane plane
   return run_adjoint(a, as_stream(stream));
 }
 
+// ------------------------------------------------------- no-allocation variant
+// rsv_cost_adjoint_noalloc keeps the adjoint's workspace (1 / sum of the window
+// weights per pixel) in a file-scope device array instead of a caller buffer.  Each
+// GPU holds its own copy for the life of the process.  In host code `scratch` names
+// only a host-side stand-in, so its device address is resolved with
+// hipGetSymbolAddress, once per device with that device current, and only that
+// address is passed to kernels.
+namespace rsv {
+namespace {
+constexpr size_t kAdjScratchBytes = RSV_ADJOINT_NOALLOC_MAX_PIXELS * sizeof(float);
+static __device__ __align__(256) float scratch[RSV_ADJOINT_NOALLOC_MAX_PIXELS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of the current device's scratch array (resolved on first use).
+int current_scratch(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RSV_E_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_hip_error(hipErrorInvalidDevice);
+    return RSV_E_HIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return RSV_E_HIP;
+    }
+    g_scratch_dev[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return RSV_OK;
+}
+}  // namespace
+}  // namespace rsv
+
+extern "C" int rsv_cost_adjoint_noalloc(rsv_image left, rsv_image right, rsv_plane plane, const rsv_params* p,
+                                        const float* cost, int64_t plane_stride, int64_t row_stride,
+                                        const int32_t* disp, const uint8_t* mask, float* grad_left,
+                                        float* grad_right, double* grad_plane, double* loss, void* stream) {
+  using namespace rsv;
+  if (int s = validate_adjoint(left, right, p, cost, plane_stride, row_stride, disp, mask, grad_left,
+                               grad_right, grad_plane, loss))
+    return s;
+  if (rsv_cost_adjoint_workspace_bytes(left.height, left.width) > kAdjScratchBytes) return RSV_E_SHAPE;
+  float* ws = nullptr;
+  if (int s = current_scratch(&ws)) return s;
+  const AdjointArgs a{left, right, plane, p, cost, plane_stride, row_stride, disp, mask,
+                      grad_left, grad_right, grad_plane, loss, ws};
+  return run_adjoint(a, as_stream(stream));
+}
