@@ -118,10 +118,12 @@ def test_batch_pair_against_oracle(rsv_gpu):
 
 
 def test_batch_realistic_sizes_equal_plain(rsv_gpu):
-    """Four pairs drawn like the 64-pair workload (640x360 and 1280x720, D 32/64/128)."""
+    """Five pairs drawn like the 64-pair workload: four of 640x360 and 1280x720 (D 32/64/128)
+    and one 1920x1080 pair with D = 128, the largest the workload draws."""
     rsv = rsv_gpu
     from paper_1807_07433_amd.batch import BatchPlan
     cases = synth.batch64_mixed(n_pairs=4, sizes=((360, 640), (720, 1280)))
+    cases += synth.batch64_mixed(n_pairs=1, sizes=((1080, 1920),), ds=(128,))
     pairs = _pairs(cases)
     _say(f"[batch] realistic sizes {[c.pair.left.shape + (c.params.D,) for c in cases]}")
     plan = BatchPlan(pairs, PRM)
