@@ -11,7 +11,10 @@
 // after Eq. 5.  The joint layout (ref_cols = W + D - 1, no tar) holds both volumes
 // in one: the target one is its view with plane stride ref_plane + 1.
 // The warped tile is stored minus 128 (kWarpShift): the centred left values sum to
-// zero, so the dot product is unchanged while its FP32 terms stay small.  Its row
+// zero, so the dot product is unchanged while its FP32 terms stay small.  Entries
+// whose target block is nearly flat (std-dev below 1 grey level, see zncc_math.hpp)
+// are recomputed exactly in FP64 from the images, since there the FP32 sum's
+// rounding, divided by a small e_r, could reach 1e-4.  Its row
 // stride is a compile-time constant so the column reads use immediate offsets.
 #pragma once
 
@@ -52,7 +55,8 @@ __host__ __device__ inline CostOut cost_out_joint(float* joint, int64_t row, int
 
 __host__ __device__ inline size_t cost_tile_lds_floats(int D, int R, int TH) {
   const size_t rows = TH + 2 * R;
-  return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1);
+  // warped tile, left tile, 1/e_r of the target centres, one flag word
+  return rows * kWarpStride + rows * (kCostTW + 2 * R) + static_cast<size_t>(TH) * (kCostTW + D - 1) + 1;
 }
 
 // The volume is written through a global-address-space pointer.  Where the output
@@ -81,7 +85,9 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   float* wt = smem;
   float* lt = wt + rows * wtw;
   float* ir = lt + rows * ltw;
+  int* flat = reinterpret_cast<int*>(ir + TH * nt);  // any target block on the exact path
   const int cw0 = u0 - (D - 1) - R;  // global column of warped tile column 0
+  if (tid == 0) *flat = 0;
 
   // Thread (tx, ty) fills columns tx, tx + 64, ... of rows ty, ty + TH, ...
   for (int r = ty; r < rows; r += TH) {
@@ -97,8 +103,13 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   static_assert(TH % 2 == 0 && NT / (TH / 2) == 128, "target rows are taken in pairs");
   {
     const int r = 2 * (tid >> 7);
-    for (int c = tid & 127; c < nt; c += 128)
-      target_inv_pair<R>(wt + r * wtw + c, wtw, sigma_min, ir[r * nt + c], ir[(r + 1) * nt + c]);
+    for (int c = tid & 127; c < nt; c += 128) {
+      float i0, i1;
+      target_inv_pair<R>(wt + r * wtw + c, wtw, sigma_min, i0, i1);
+      ir[r * nt + c] = i0;
+      ir[(r + 1) * nt + c] = i1;
+      if (i0 < 0.f || i1 < 0.f) *flat = 1;
+    }
   }
 
   LeftBlock<R, std::is_same<TL, uint8_t>::value> lb;
@@ -121,6 +132,29 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
   const bool tar_ok = TAR && row_ok && cost_tar != nullptr;
   const float* wrow = wt + ty * wtw + tx + (D - 1);  // window column k at step d: wrow[k - d]
   const float* irow = ir + ty * nt + tx + (D - 1);   // 1/e_r of centre u - d: irow[-d]
+
+  // The entry recomputed in FP64 from the unshifted images: (n l - S_l) and the
+  // products are exact for uint8 and float images alike, so only the final scaling
+  // rounds.  Used for target blocks marked by target_inv (std-dev below kExactSigma).
+  auto exact = [&](int d, float inv_r) -> float {
+    const float* lb0 = lt + ty * ltw + tx;
+    double S = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < K; ++j)
+#pragma unroll 1
+      for (int k = 0; k < K; ++k) S += static_cast<double>(lb0[j * ltw + k]);
+    double num = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < K; ++j) {
+      const int y = clampi(v - R + j, 0, H - 1);
+#pragma unroll 1
+      for (int k = 0; k < K; ++k) {
+        const double l = fma(static_cast<double>(K * K), static_cast<double>(lb0[j * ltw + k]), -S);
+        num = fma(l, static_cast<double>(warped_at(y, clampi(u - d - R + k, 0, W - 1))), num);
+      }
+    }
+    return static_cast<float>(num * (static_cast<double>(lb.inv) * static_cast<double>(inv_r)));
+  };
 
   float win[K][K];  // ring: window column k at step d0 + t lives in slot (k - t) mod K
 #pragma unroll
@@ -147,7 +181,21 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
       for (int j = 0; j < K; ++j)
 #pragma unroll
         for (int k = 0; k < K; ++k) num = fmaf(lb.c[j][k], win[j][(k - t + K) % K], num);
+      // (negative 1/e_r: a nearly flat target block, rewritten below)
       const float c = (num * lb.inv) * irow[-d];
+      if (ref_ok) to_global(cost_ref + d * ref_plane)[roff] = c;
+      if constexpr (TAR) {
+        const int64_t pd = d * plane;
+        if (tar_ok && static_cast<unsigned>(u - d) < static_cast<unsigned>(W)) to_global(cost_tar + (pd - d))[toff] = c;
+      }
+    }
+  }
+  if (*flat) {  // uniform; never taken on textured images
+#pragma unroll 1
+    for (int d = 0; d < D; ++d) {
+      const float inv_r = irow[-d];
+      if (!(inv_r < 0.f)) continue;
+      const float c = exact(d, -inv_r);
       if (ref_ok) to_global(cost_ref + d * ref_plane)[roff] = c;
       if constexpr (TAR) {
         const int64_t pd = d * plane;

@@ -7,6 +7,12 @@
 // zero, so mu_r drops out).  For uint8 images n l_i - S_l is an exact integer.
 // Any constant may be subtracted from the r_i without changing the sum (the cost
 // tile subtracts 128), which keeps the FP32 products small.
+//
+// The FP32 sum's rounding error grows with sum_i |n l_i - S_l| |r_i| <= 128 n e_l, so
+// its error in c scales as 1 / e_r: it stays near 1e-7 for textured target blocks and
+// reaches 1e-4 only for nearly flat ones.  Target blocks with sigma below
+// kExactSigma are therefore marked (their 1/e_r is stored negated) and their entries
+// are recomputed exactly in FP64 (cost_tile.hpp).
 #pragma once
 
 #include "rsv_internal.hpp"
@@ -72,8 +78,19 @@ struct LeftBlock {
   }
 };
 
-// 1/e_r of two vertically adjacent target blocks: the one whose top-left corner is
-// tile[0] and the one a row below.  They share 2R rows, which are summed once.
+// Target blocks with a std-dev below this (grey levels) take the exact FP64 path.
+constexpr double kExactSigma = 1.0;
+
+// 1/e_r of a target block, negated where its std-dev is below kExactSigma (the
+// entries that pair with it are recomputed in FP64); 0 below sigma_min.
+__device__ __forceinline__ float target_inv(double n, double S, double Q, float sigma_min) {
+  const float inv = inv_block_norm(n, S, Q, sigma_min);
+  return (inv > 0.f && static_cast<double>(inv) * n * kExactSigma > 1.0) ? -inv : inv;
+}
+
+// Signed 1/e_r (target_inv) of two vertically adjacent target blocks: the one whose
+// top-left corner is tile[0] and the one a row below.  They share 2R rows, which are
+// summed once.
 template <int R>
 __device__ __forceinline__ void target_inv_pair(const float* tile, int stride, float sigma_min,
                                                 float& inv0, float& inv1) {
@@ -96,8 +113,8 @@ __device__ __forceinline__ void target_inv_pair(const float* tile, int stride, f
       Sm += x;
       Qm = fma(x, x, Qm);
     }
-  inv0 = inv_block_norm(static_cast<double>(K * K), St + Sm, Qt + Qm, sigma_min);
-  inv1 = inv_block_norm(static_cast<double>(K * K), Sm + Sb, Qm + Qb, sigma_min);
+  inv0 = target_inv(static_cast<double>(K * K), St + Sm, Qt + Qm, sigma_min);
+  inv1 = target_inv(static_cast<double>(K * K), Sm + Sb, Qm + Qb, sigma_min);
 }
 
 }  // namespace rsv

@@ -412,3 +412,40 @@ def test_full_road1920_d128_sampled(rsv_gpu):
     case = synth.road1920_d128()
     out = _sampled_full(rsv_gpu, case, 10000, 600, 60, 8)
     _fused_target_matches(rsv_gpu, case, out)
+
+
+def test_cost_near_flat_bright_and_dark_target_blocks(rsv_gpu):
+    """Target blocks that are almost flat on a bright or dark plateau (250, 255, 5), where
+    one warped pixel lies a fraction of a grey level off (linear warp of an isolated
+    level step), so sigma_r is just above sigma_min and Eq. 3 divides a numerator of
+    nearly cancelling terms by a tiny e_r: every entry of both volumes within the cost
+    tolerance of the oracle."""
+    rsv = rsv_gpu
+    H, W, D = 48, 190, 24
+    rng = np.random.default_rng(77)
+    left = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    right = np.full((H, W), 250, np.uint8)
+    right[:, 70:130] = 255
+    right[:, 130:] = 5
+    spots = rng.random((H, W)) < 1.0 / 40
+    right[spots] = np.where(right[spots] == 255, 254, np.where(rng.random(spots.sum()) < 0.5,
+                                                              right[spots] + 1, right[spots] - 1))
+    plane = synth.Plane(6.37, 0.0131, 0.0, 12.0)   # fractional shifts that vary by row
+    prm = rsv.StereoParams(D=D, block_radius=3, agg_radius=2, gamma_d=2.0)
+    _say(f"[near-flat] {W}x{H} D={D}: {int(spots.sum())} isolated level steps on plateaus")
+    Wp = S.warp(right, plane.as_tuple())
+    CL, CR = S.cost_volumes(left, Wp, D, prm.block_radius, prm.sigma_min)
+    L, R = _gpu(left), _gpu(right)
+    wp = rsv.warp(R, plane)
+    cref, ctar = rsv.cost_volume(L, wp, prm)
+    e1 = P.check_close("cost_ref", P.to_np(cref), CL, P.COST_TOL)
+    e2 = P.check_close("cost_tar", P.to_np(ctar), CR, P.COST_TOL)
+    n = 49
+    bw = S.block_values(Wp, *np.meshgrid(np.arange(W), np.arange(H)), 3)
+    sig = bw.std(-1)
+    low = (sig >= prm.sigma_min) & (sig < 0.1)
+    _say(f"  max |err| cost_ref {e1:.2e} cost_tar {e2:.2e}; {int(low.sum())} target blocks with "
+         f"sigma_min <= sigma_r < 0.1 (n = {n})")
+    assert low.sum() > 100
+    jref, jtar = rsv.joint_views(rsv.cost_volume_joint(L, wp, prm), W)
+    assert torch.equal(jref, cref) and torch.equal(jtar, ctar)
