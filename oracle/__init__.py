@@ -9,8 +9,10 @@ no arithmetic of the method).
   oracle.stereo   forward path (warp, ZNCC volumes, bilateral aggregation, WTA,
                   left-right check, parabola subpixel, post-processing, 3-D points)
   oracle.adjoint  loss of the differentiable form and its exact gradient
+  oracle.restricted  restricted-search aggregation (Sec. IV): windows around the
+                  unaggregated WTA, windowed WTA, the rest of the full path
 
 Pins (tests marked "not gpu") tie every function to facts fixed by the paper or
 by mathematics rather than to itself; see tests/test_oracle_*.py.
 """
-from . import stereo, adjoint  # noqa: F401
+from . import stereo, adjoint, restricted  # noqa: F401
