@@ -211,6 +211,44 @@ int rsv_aggregate_select(const float* cost, int64_t plane_stride, int64_t row_st
                          rsv_image guide, const rsv_params* p, const int32_t* disp_tar,
                          int32_t* disp_ref, float* disp_sub, uint8_t* valid, void* stream);
 
+/* ------------------------------------------- restricted search (Sec. IV)
+ * The paper's proposed speed-up: bilateral filtering only on the disparities around
+ * an already calculated disparity instead of on the whole cost volume.  Here the
+ * calculated disparity of a pixel is the winner-take-all of its unaggregated
+ * correlation (rsv_cost_argmax), and its window is the width = min(2*radius + 1, D)
+ * disparities lo .. lo + width - 1, lo = clamp(coarse - radius, 0, D - width).  The
+ * aggregated values in a window are the full method's floats; the winner is the first
+ * maximum inside the window. */
+
+/* Winner-take-all of an unaggregated cost view (Sec. II-B.3's rule on Eq. 3's c):
+ *   disp[v][u] = argmax_d cost[d*plane_stride + v*row_stride + u], ties -> lowest d
+ * (e.g. the reference and target views of rsv_cost_volume_joint's volume).
+ *   disp  out, int32 [H][W]
+ * Errors: RSV_E_NULL, RSV_E_SHAPE (H, W, D < 1, D > RSV_MAX_D, row_stride < W,
+ * plane_stride < 1), RSV_E_ALIGN. */
+int rsv_cost_argmax(const float* cost, int64_t plane_stride, int64_t row_stride, int32_t height,
+                    int32_t width, int32_t D, int32_t* disp, void* stream);
+
+/* rsv_aggregate_argmax restricted to each pixel's window around coarse[v][u]: the
+ * first maximum over the window of the aggregation of Eq. 8-10.
+ *   coarse  int32 [H][W], read (any values; clamped into the range as above)
+ *   radius  >= 0;  disp out, int32 [H][W]
+ * Runs where the LDS-loaded tile does (agg_radius <= 5, W >= 4).
+ * Errors: as rsv_aggregate_argmax; RSV_E_PARAM also for radius < 0 or agg_radius > 5,
+ * RSV_E_SHAPE also for W < 4. */
+int rsv_aggregate_restricted_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                    rsv_image guide, const rsv_params* p, const int32_t* coarse,
+                                    int32_t radius, int32_t* disp, void* stream);
+
+/* rsv_aggregate_select restricted to each pixel's window around coarse[v][u]: the
+ * winner inside the window, Eq. 12 on it with the aggregated values at d - 1 and d + 1
+ * (also computed where they leave the window), Eq. 11 against disp_tar.
+ * Errors: as rsv_aggregate_select; RSV_E_PARAM also for radius < 0. */
+int rsv_aggregate_restricted_select(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                    rsv_image guide, const rsv_params* p, const int32_t* coarse,
+                                    int32_t radius, const int32_t* disp_tar, int32_t* disp_ref,
+                                    float* disp_sub, uint8_t* valid, void* stream);
+
 /* Post-processing (Sec. II-C) and 3-D reconstruction (Sec. II-D):
  *   disp_final = disp_sub + s(u - disp_sub, v)            (every pixel)
  *   xyz[v][u]  = (x, y, z), z = f*baseline/disp_final, x = (u-u0) z/f, y = (v-v0) z/f,

@@ -15,7 +15,10 @@ Reading (Sec. IV states the idea only):
     d + 1 of the winner, for Eq. 12), so wherever it is evaluated it equals the full
     method's value; the winner is the first maximum inside the window;
   * the left-right check (Eq. 11), Eq. 12 on the reference values and the
-    post-processing are those of the full method, applied to the restricted winners.
+    post-processing are those of the full method, applied to the restricted winners;
+    Eq. 12 fits a parabola through a discrete maximum, so a winner at a window edge
+    whose neighbour just outside the window is larger stays unrefined (the full
+    method's winner is the maximum of the whole range and never meets this case).
 """
 from __future__ import annotations
 
@@ -42,6 +45,18 @@ def windowed_wta(A: np.ndarray, lo: np.ndarray, width: int) -> np.ndarray:
     return np.argmax(masked, axis=0).astype(np.int64)
 
 
+def subpixel_at_maximum(A: np.ndarray, disp: np.ndarray) -> np.ndarray:
+    """Eq. 12 (S.subpixel) where the winner is a maximum of its two neighbours; the
+    winner itself where a neighbour is larger."""
+    D, H, W = A.shape
+    v, u = np.mgrid[0:H, 0:W]
+    c0 = A[disp, v, u]
+    higher = (A[np.clip(disp - 1, 0, D - 1), v, u] > c0) | (A[np.clip(disp + 1, 0, D - 1), v, u] > c0)
+    with np.errstate(divide="ignore", invalid="ignore"):   # Eq. 12's value is discarded there
+        fit = S.subpixel(A, disp)
+    return np.where(higher, disp.astype(np.float64), fit)
+
+
 def reconstruct_restricted(left, right, plane, D, block_radius, agg_radius, gamma_d, gamma_r,
                            lr_threshold, sigma_min, radius):
     """Warp -> both cost volumes -> calculated (unaggregated WTA) disparities -> the
@@ -59,7 +74,7 @@ def reconstruct_restricted(left, right, plane, D, block_radius, agg_radius, gamm
     dref = windowed_wta(AL, lo_ref, width)
     dtar = windowed_wta(AR, lo_tar, width)
     valid = S.lr_check(dref, dtar, lr_threshold)
-    dsub = S.subpixel(AL, dref)
+    dsub = subpixel_at_maximum(AL, dref)
     dfin = S.postprocess(dsub, plane)
     return dict(warped=Wp, cost_ref=CL, cost_tar=CR, coarse_ref=coarse_ref, coarse_tar=coarse_tar,
                 agg_ref=AL, agg_tar=AR, lo_ref=lo_ref, lo_tar=lo_tar, width=width, disp_ref=dref,

@@ -7,7 +7,8 @@ refinement, post-processing and triangulation.  This package is the thin Python
 binding; PyTorch supplies device memory and streams.
 """
 from ._lib import RsvError, load, LIB_PATH  # noqa: F401
-from .ops import (StereoParams, aggregate, aggregate_argmax, aggregate_select,  # noqa: F401
+from .ops import (StereoParams, aggregate, aggregate_argmax, aggregate_restricted_argmax,  # noqa: F401
+                  aggregate_restricted_select, aggregate_select, cost_argmax, reconstruct_restricted,
                   aggregate_select_supported, cost_adjoint, cost_volume, cost_volume_joint, image, joint_row_stride, joint_views, reconstruct,
                   select_subpixel, selected_aggregate_sum, selected_cost_sum, triangulate, warp)
 

@@ -59,6 +59,11 @@ _SIGNATURES = {
                                       _P, _P, _P]),
     "rsv_select_subpixel_ref": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(Params), _P, _P, _P, _P,
                                           _P]),
+    "rsv_cost_argmax": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "rsv_aggregate_restricted_argmax": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P,
+                                                  C.c_int32, _P, _P]),
+    "rsv_aggregate_restricted_select": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P,
+                                                  C.c_int32, _P, _P, _P, _P, _P]),
     "rsv_triangulate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, Plane, Camera, _P, _P, _P]),
     "rsv_selected_cost_sum": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "rsv_cost_adjoint_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),

@@ -92,9 +92,12 @@ template <int A, typename GuideAt, typename Sink>
 __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int64_t cps, int crs, int H,
                                              int W, int D,
                                              const BilateralK& bk, int by, int bx, GuideAt guide_at,
-                                             Sink& sink, unsigned char* smem, uint32_t smem_lds) {
+                                             Sink& sink, unsigned char* smem, uint32_t smem_lds,
+                                             int t_first = 0, int t_count = -1) {
   // smem_lds: LDS byte address of smem (lds_address in the kernel), so that device
-  // functions holding smem as a generic pointer can address the DMA destinations
+  // functions holding smem as a generic pointer can address the DMA destinations.
+  // t_first, t_count: the disparity tiles to aggregate (uniform over the block), by
+  // default all of them; the sink is called with each tile's absolute index.
   using G = AggGeo<A, 16>;
   constexpr int NT = G::NT;                      // 1024
   constexpr int NITEM = 16 * G::NCH;             // (disparity, chunk) items per tile
@@ -196,9 +199,9 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
     }
   };
 
-  const int ndt = (D + 15) >> 4;
-  issue(0, raw0);
-  if (ndt > 1) issue(1, raw1);
+  const int ndt = t_count < 0 ? (D + 15) >> 4 : t_count;  // tiles t_first .. t_first + ndt - 1
+  issue(t_first, raw0);
+  if (ndt > 1) issue(t_first + 1, raw1);
   // The guide and spatial tables are staged while the first tiles load (the wait
   // for the guide loads may also wait for those tiles).
   for (int i = tid; i < G::RAW; i += NT) {
@@ -215,9 +218,9 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
     wait_older();
   else
     wait_vm<0>();
-  convert(0, raw0);
-  __syncthreads();  // hi / lo of tile 0 ready; raw0 is free
-  if (ndt > 2) issue(2, raw0);
+  convert(t_first, raw0);
+  __syncthreads();  // hi / lo of the first tile ready; raw0 is free
+  if (ndt > 2) issue(t_first + 2, raw0);
 
   PatchPos pp;
   half8_t whi[G::KS], wlo[G::KS];
@@ -240,11 +243,11 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
         wait_older();
       else
         wait_vm<0>();
-      convert(t + 1, (t + 1) & 1 ? raw1 : raw0);
+      convert(t_first + t + 1, (t + 1) & 1 ? raw1 : raw0);
     }
     __syncthreads();  // output t and hi / lo of tile t+1 ready
-    sink(t, static_cast<const float*>(out));
-    if (t + 3 < ndt) issue(t + 3, (t + 1) & 1 ? raw1 : raw0);
+    sink(t_first + t, static_cast<const float*>(out));
+    if (t + 3 < ndt) issue(t_first + t + 3, (t + 1) & 1 ? raw1 : raw0);
   }
   wait_vm<0>();  // nothing may be in flight into LDS when the block's LDS is reused
 }

@@ -10,6 +10,8 @@
 // (agg_tile_dma.hpp; rho <= 5, W >= 4) or through registers (agg_tile.hpp), and its
 // results leave one 16-disparity tile at a time through a sink: the volume's planes
 // (non-temporal stores) or the running argmax (argmax_sink.hpp).
+#include <climits>
+
 #include "agg_tile_dma.hpp"
 #include "argmax_sink.hpp"
 #include "select_math.hpp"
@@ -190,6 +192,170 @@ int dispatch_agg_select(const float* cost, int64_t cps, int crs, const rsv_image
   }
 }
 
+// ------------------------------------------------- restricted search (Sec. IV)
+// Each pixel aggregates only the window of `width` disparities around its calculated
+// (unaggregated winner-take-all) disparity, lo = clamp(coarse - radius, 0, D - width).
+// A block aggregates the consecutive 16-disparity tiles that cover all its pixels'
+// windows widened by one on each side (Eq. 12's neighbours; clamped to the range),
+// and the sinks take each pixel's winner inside its own window.  Every aggregated
+// value is the full method's float (same tile, same arithmetic).
+
+// The window of the thread's pixel (thread i covers pixel i / 4 of the 16 x 16 block),
+// and the block's tile range [t_first, t_first + t_count).  Pixels outside the image
+// do not widen the range.
+__device__ __forceinline__ void restricted_tiles(const int32_t* __restrict__ coarse, int H, int W, int D,
+                                                 int radius, int width, int by, int bx, int* s_range, int& lo,
+                                                 int& hi, int& t_first, int& t_count) {
+  const int p = threadIdx.x >> 2;
+  const int Y = by + (p >> 4), X = bx + (p & 15);
+  const bool in = Y < H && X < W;
+  const int c = in ? coarse[static_cast<int64_t>(Y) * W + X] : 0;
+  lo = clampi(c - radius, 0, D - width);
+  hi = lo + width - 1;
+  int mn = in ? lo : INT_MAX, mx = in ? hi : -1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, __shfl_xor(mn, off));
+    mx = max(mx, __shfl_xor(mx, off));
+  }
+  if (threadIdx.x == 0) {
+    s_range[0] = INT_MAX;
+    s_range[1] = -1;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&s_range[0], mn);
+    atomicMax(&s_range[1], mx);
+  }
+  __syncthreads();
+  const int dlo = max(s_range[0] - 1, 0), dhi = min(s_range[1] + 1, D - 1);
+  t_first = __builtin_amdgcn_readfirstlane(dlo >> 4);
+  t_count = __builtin_amdgcn_readfirstlane((dhi >> 4) - (dlo >> 4) + 1);
+}
+
+template <int A, typename TG>
+__global__ __launch_bounds__(1024) void aggregate_restricted_argmax_kernel(
+    const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch, int H,
+    int W, int D, BilateralK bk, const int32_t* __restrict__ coarse, int radius, int width,
+    int32_t* __restrict__ disp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_range[2];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
+  int lo, hi, t_first, t_count;
+  restricted_tiles(coarse, H, W, D, radius, width, by, bx, s_range, lo, hi, t_first, t_count);
+  if (t_count <= 0) return;  // no pixel of the block in the image
+  auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
+  ArgmaxSink sink{D};
+  sink.lo = lo;
+  sink.hi = hi;
+  agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem, lds_address(smem), t_first, t_count);
+  sink.finish(disp, H, W, by, bx);
+}
+
+template <int A, typename TG>
+__global__ __launch_bounds__(1024) void aggregate_restricted_select_kernel(
+    const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch, int H,
+    int W, int D, BilateralK bk, const int32_t* __restrict__ coarse, int radius, int width, int tau,
+    const int32_t* __restrict__ dtar, int32_t* __restrict__ dref, float* __restrict__ dsub,
+    uint8_t* __restrict__ valid) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_range[2];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
+  int lo, hi, t_first, t_count;
+  restricted_tiles(coarse, H, W, D, radius, width, by, bx, s_range, lo, hi, t_first, t_count);
+  if (t_count <= 0) return;
+  auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
+  RefQuadSink sink{D};
+  sink.lo = lo;
+  sink.hi = hi;
+  agg_tile_dma<A>(cost, cps, crs, H, W, D, bk, by, bx, guide_at, sink, smem, lds_address(smem), t_first, t_count);
+  if ((threadIdx.x & 3) != 0) return;
+  const int q = threadIdx.x >> 2;
+  const int Y = by + (q >> 4), X = bx + (q & 15);
+  if (Y >= H || X >= W) return;
+  const int64_t row = static_cast<int64_t>(Y) * W, i = row + X;
+  const int a = sink.arg, x = X - a;
+  dref[i] = a;
+  dsub[i] = parabola(a, sink.best, sink.am, sink.ap, D);
+  valid[i] = (x >= 0 && abs(a - dtar[row + (x < 0 ? 0 : x)]) <= tau) ? 1 : 0;
+}
+
+template <int A, typename TG, bool SEL>
+int launch_restricted(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                      const int32_t* coarse, int radius, const int32_t* dtar, int32_t* dref, float* dsub,
+                      uint8_t* valid, hipStream_t st) {
+  if constexpr (agg_dma_fits<A>()) {
+    const int tiles = ((g.width + 15) / 16) * ((g.height + 15) / 16);
+    const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+    const size_t lds = agg_tile_dma_lds_bytes<A>();
+    const int width = 2 * radius + 1 < p->D ? 2 * radius + 1 : p->D;
+    auto kern_sel = aggregate_restricted_select_kernel<A, TG>;
+    auto kern_arg = aggregate_restricted_argmax_kernel<A, TG>;
+    const void* kern = SEL ? reinterpret_cast<const void*>(kern_sel) : reinterpret_cast<const void*>(kern_arg);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return RSV_E_HIP;
+    }
+    const TG* gd = static_cast<const TG*>(g.data);
+    if constexpr (SEL)
+      kern_sel<<<dim3(tiles), dim3(1024), lds, st>>>(cost, cps, crs, gd, g.pitch, g.height, g.width, p->D, bk,
+                                                     coarse, radius, width, p->lr_threshold, dtar, dref, dsub,
+                                                     valid);
+    else
+      kern_arg<<<dim3(tiles), dim3(1024), lds, st>>>(cost, cps, crs, gd, g.pitch, g.height, g.width, p->D, bk,
+                                                     coarse, radius, width, dref);
+    return check_launch();
+  } else {
+    return RSV_E_PARAM;  // the LDS-loaded tile does not fit this radius
+  }
+}
+
+template <typename TG, bool SEL>
+int dispatch_restricted(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
+                        const int32_t* coarse, int radius, const int32_t* dtar, int32_t* dref, float* dsub,
+                        uint8_t* valid, hipStream_t st) {
+  switch (p->agg_radius) {
+    case 1: return launch_restricted<1, TG, SEL>(cost, cps, crs, g, p, coarse, radius, dtar, dref, dsub, valid, st);
+    case 2: return launch_restricted<2, TG, SEL>(cost, cps, crs, g, p, coarse, radius, dtar, dref, dsub, valid, st);
+    case 3: return launch_restricted<3, TG, SEL>(cost, cps, crs, g, p, coarse, radius, dtar, dref, dsub, valid, st);
+    case 4: return launch_restricted<4, TG, SEL>(cost, cps, crs, g, p, coarse, radius, dtar, dref, dsub, valid, st);
+    case 5: return launch_restricted<5, TG, SEL>(cost, cps, crs, g, p, coarse, radius, dtar, dref, dsub, valid, st);
+    default: return RSV_E_PARAM;
+  }
+}
+
+// SEL: the reference form (winner, Eq. 12, Eq. 11 against dtar); else the target
+// argmax written to dref.
+int run_restricted(bool sel, const float* cost, int64_t cps, int64_t crs, const rsv_image& guide,
+                   const rsv_params* p, const int32_t* coarse, int radius, const int32_t* dtar, int32_t* dref,
+                   float* dsub, uint8_t* valid, void* stream) {
+  if (int s = validate_image(guide)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (sel)
+    if (int s = validate_select_params(p)) return s;
+  if (!cost || !coarse || !dref || (sel && (!dtar || !dsub || !valid))) return RSV_E_NULL;
+  if (!aligned(cost, 4) || !aligned(coarse, 4) || !aligned(dref, 4) || (sel && (!aligned(dtar, 4) ||
+                                                                              !aligned(dsub, 4))))
+    return RSV_E_ALIGN;
+  if (radius < 0) return RSV_E_PARAM;
+  if (p->agg_radius > 5) return RSV_E_PARAM;
+  if (guide.width < 4 || crs < guide.width || cps < 1 || cps > kAggMaxPixels ||
+      static_cast<int64_t>(guide.height - 1) * crs + guide.width > kAggMaxPixels)
+    return RSV_E_SHAPE;
+  hipStream_t st = as_stream(stream);
+  const int rs = static_cast<int>(crs);
+  if (guide.dtype == RSV_U8)
+    return sel ? dispatch_restricted<uint8_t, true>(cost, cps, rs, guide, p, coarse, radius, dtar, dref, dsub, valid, st)
+               : dispatch_restricted<uint8_t, false>(cost, cps, rs, guide, p, coarse, radius, dtar, dref, dsub, valid, st);
+  return sel ? dispatch_restricted<float, true>(cost, cps, rs, guide, p, coarse, radius, dtar, dref, dsub, valid, st)
+             : dispatch_restricted<float, false>(cost, cps, rs, guide, p, coarse, radius, dtar, dref, dsub, valid, st);
+}
+
 template <int A, typename TG, bool ARG>
 int launch_agg(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
                float* agg, int32_t* disp, hipStream_t st) {
@@ -291,4 +457,19 @@ extern "C" int rsv_aggregate_select(const float* cost, int64_t plane_stride, int
   if (guide.dtype == RSV_U8)
     return dispatch_agg_select<uint8_t>(cost, plane_stride, rs, guide, p, disp_tar, disp_ref, disp_sub, valid, st);
   return dispatch_agg_select<float>(cost, plane_stride, rs, guide, p, disp_tar, disp_ref, disp_sub, valid, st);
+}
+
+extern "C" int rsv_aggregate_restricted_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                               rsv_image guide, const rsv_params* p, const int32_t* coarse,
+                                               int32_t radius, int32_t* disp, void* stream) {
+  return rsv::run_restricted(false, cost, plane_stride, row_stride, guide, p, coarse, radius, nullptr, disp,
+                             nullptr, nullptr, stream);
+}
+
+extern "C" int rsv_aggregate_restricted_select(const float* cost, int64_t plane_stride, int64_t row_stride,
+                                               rsv_image guide, const rsv_params* p, const int32_t* coarse,
+                                               int32_t radius, const int32_t* disp_tar, int32_t* disp_ref,
+                                               float* disp_sub, uint8_t* valid, void* stream) {
+  return rsv::run_restricted(true, cost, plane_stride, row_stride, guide, p, coarse, radius, disp_tar, disp_ref,
+                             disp_sub, valid, stream);
 }

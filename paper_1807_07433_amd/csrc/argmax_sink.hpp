@@ -2,38 +2,83 @@
 // winner-take-all results (Sec. II-B.3): the target volume's argmax (rsv_aggregate_argmax
 // and the batch kernel's target items) and the reference volume's winner with its
 // neighbours for Eq. 12 (rsv_aggregate_select and the batch kernel's reference tiles).
+// Both take, per pixel, a window [lo, hi] of candidate disparities: the whole range
+// for the full method, or the restricted search of Sec. IV (rsv_aggregate_restricted_*).
 #pragma once
 
 #include "aggregate_mfma.hpp"
+#include "select_math.hpp"
 
 namespace rsv {
 
-// (b, a) <- the better of (b, a) and the quad lane selected by the DPP quad_perm
-// pattern PERM: the larger value, the lower d on ties.
-template <int PERM>
-__device__ __forceinline__ void quad_merge(float& b, int& a) {
+// The first maximum (wta_beats order) over the candidates among the four disparities
+// 16 t + 4 q .. + 3 of tile t held in the output tile o for pixel p; a < 0 when none of
+// them lies in [lo, hi].
+__device__ __forceinline__ void lane_scan(const float* o, int t, int q, int p, int lo, int hi, float& b,
+                                          int& a) {
+  using G = AggGeo<1, 16>;
+  b = 0.f;
+  a = -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int d = 16 * t + 4 * q + k;
+    if (d >= lo && d <= hi) {
+      const float v = o[(4 * q + k) * G::OST + p];
+      if (a < 0 || wta_beats(v, b)) {
+        b = v;
+        a = d;
+      }
+    }
+  }
+}
+
+// (b, a) <- the merge with quad lane q ^ M (DPP quad_perm PERM) over consecutive
+// disparity ranges: the lower range's winner stands unless the upper one beats it
+// (wta_beats), so both lanes end with the winner one scan over both ranges gives.
+template <int PERM, int M>
+__device__ __forceinline__ void quad_merge(float& b, int& a, int q) {
   const float ob = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(b), PERM, 0xF, 0xF, false));
   const int oa = __builtin_amdgcn_mov_dpp(a, PERM, 0xF, 0xF, false);
-  if (ob > b || (ob == b && oa < a)) {
+  const bool other_lower = (q & M) != 0;
+  bool take;
+  if (oa < 0)
+    take = false;
+  else if (a < 0)
+    take = true;
+  else
+    take = other_lower ? !wta_beats(b, ob) : wta_beats(ob, b);
+  if (take) {
     b = ob;
     a = oa;
   }
 }
 
+// The candidates of tile t for this thread's pixel, merged over its quad: thread i
+// covers pixel i / 4 and disparities 4 (i % 4) .. + 3; all four lanes of a quad end
+// with the tile's winner (a < 0: no candidate in this tile).
+__device__ __forceinline__ void tile_winner(const float* o, int t, int lo, int hi, float& b, int& a) {
+  const int i = threadIdx.x, p = i >> 2, q = i & 3;
+  lane_scan(o, t, q, p, lo, hi, b, a);
+  quad_merge<0xB1, 1>(b, a, q);
+  quad_merge<0x4E, 2>(b, a, q);
+}
+
 // agg_tile sink for a volume that is only needed through its argmax over d (the
 // target volume of Sec. II-B.3): the 16 x 16 pixels' running winner, nothing written
-// until the end; the select kernel's order (the first maximum over d).  Two forms:
-// * state null (the LDS-loaded tile): thread i covers pixel i / 4 and disparities
-//   4 (i % 4) .. + 3 of the tile: its first maximum, then the quad's (lower d on
-//   ties), then against the earlier tiles' winner (replaced only when strictly
-//   greater).  All four threads of a quad keep the same winner in registers.
+// until the end; the select kernel's order (the first maximum over d, wta_beats).
+// Two forms:
+// * state null (the LDS-loaded tile): the quad lanes of a pixel take the tile's
+//   winner (tile_winner), then the running winner is replaced only when beaten; the
+//   candidates are d in [lo, hi] (lo = 0, hi = D - 1 for the full method).
 // * state in LDS (the register-staged tile, whose registers are full): thread p <
-//   256 scans pixel p's 16 values in order against the winner kept in LDS.
+//   256 scans pixel p's 16 values in order against the winner kept in LDS (full
+//   range only).
 struct ArgmaxSink {
   int D;
   float* state = nullptr;  // [2][256]: best, then arg bits
-  float best = -INFINITY;
-  int arg = 0;
+  int lo = 0, hi = D - 1;
+  float best = 0.f;
+  int arg = -1;
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
     using G = AggGeo<1, 16>;
@@ -45,7 +90,7 @@ struct ArgmaxSink {
       const int n = min(16, D - 16 * t);
       for (int dd = 0; dd < n; ++dd) {
         const float v = o[dd * G::OST + p];
-        if ((t == 0 && dd == 0) || v > b) {
+        if ((t == 0 && dd == 0) || wta_beats(v, b)) {
           b = v;
           a = 16 * t + dd;
         }
@@ -54,22 +99,10 @@ struct ArgmaxSink {
       state[256 + p] = __int_as_float(a);
       return;
     }
-    const int i = threadIdx.x, p = i >> 2, q = i & 3;
-    float b = -INFINITY;
-    int a = 0x7fffffff;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int d = 16 * t + 4 * q + k;
-      const float v = o[(4 * q + k) * G::OST + p];
-      if (d < D && v > b) {
-        b = v;
-        a = d;
-      }
-    }
-    // the quad's lanes i ^ 1, then i ^ 2 (DPP quad permutations, no LDS traffic)
-    quad_merge<0xB1>(b, a);
-    quad_merge<0x4E>(b, a);
-    if (t == 0 || b > best) {
+    float b;
+    int a;
+    tile_winner(o, t, lo, hi, b, a);
+    if (a >= 0 && (arg < 0 || wta_beats(b, best))) {
       best = b;
       arg = a;
     }
@@ -94,43 +127,34 @@ struct ArgmaxSink {
 };
 
 // agg_tile_dma sink for the reference volume: the select kernel's scan result (first
-// maximum over d, ties to the lowest d, and the values at d - 1 and d + 1) from all
-// 1024 threads, in registers; shared by rsv_aggregate_select and the batch kernel's
-// reference tiles.  Thread i covers pixel i / 4 and disparities 4 (i % 4) .. + 3 of
-// each 16-disparity tile: its first maximum, then two quad permutations merge the four
-// (larger value, lower d on ties).  When the tile's winner replaces the running one,
-// its neighbours are read from the output tile, still in LDS; at the tile's edges they
-// are the previous tile's last value and the next tile's first.  The winner, its value
-// and the values at d - 1 and d + 1 are exactly the scan's wherever Eq. 12 uses them
-// (0 < d < D - 1).
+// maximum over d, wta_beats, and the values at d - 1 and d + 1) from all 1024
+// threads, in registers; shared by rsv_aggregate_select, the restricted search and
+// the batch kernel's reference tiles.  The quad lanes of a pixel take the tile's
+// winner among the candidates d in [lo, hi] (tile_winner).  When it replaces the
+// running one, its neighbours are read from the output tile, still in LDS; at the
+// tile's edges they are the previous tile's last value and the next tile's first
+// (the caller's tiles are consecutive and reach one disparity past every window on
+// both sides, or the range's ends).  The winner, its value and the values at d - 1
+// and d + 1 are exactly the scan's wherever Eq. 12 uses them (0 < d < D - 1).
 struct RefQuadSink {
   int D;
-  float best = -INFINITY, am = 0.f, ap = 0.f, lastv = 0.f;
-  int arg = 0;
+  int lo = 0, hi = D - 1;
+  float best = 0.f, am = 0.f, ap = 0.f, lastv = 0.f;
+  int arg = -1;
   bool pend = false;
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
     using G = AggGeo<1, 16>;
-    const int i = threadIdx.x, p = i >> 2, q = i & 3;
-    float b = -INFINITY;
-    int a = 0x7fffffff;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int d = 16 * t + 4 * q + k;
-      const float v = o[(4 * q + k) * G::OST + p];
-      if (d < D && v > b) {
-        b = v;
-        a = d;
-      }
-    }
-    quad_merge<0xB1>(b, a);
-    quad_merge<0x4E>(b, a);
+    const int p = threadIdx.x >> 2;
+    float b;
+    int a;
+    tile_winner(o, t, lo, hi, b, a);
     if (pend) {  // the running winner sat at d = 16 t - 1: its right neighbour is d = 16 t
       ap = o[p];
       pend = false;
     }
-    if (t == 0 || b > best) {
-      const int k = a - 16 * t;  // the winner's place in the tile
+    if (a >= 0 && (arg < 0 || wta_beats(b, best))) {
+      const int k = a - 16 * t;  // the winner's place in the tile, 0 .. 15
       best = b;
       arg = a;
       am = k > 0 ? o[(k - 1) * G::OST + p] : lastv;

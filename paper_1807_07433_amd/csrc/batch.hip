@@ -126,7 +126,7 @@ struct WtaSink {
           scan_init(s, need_next, prev, a);
         else
           scan_step<false>(s, need_next, prev, a, d);
-      } else if (d == 0 || a > s.best) {
+      } else if (d == 0 || wta_beats(a, s.best)) {
         s.best = a;
         s.arg = d;
       }

@@ -35,7 +35,7 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
       targ = 0;
     } else {
       scan_step<TOP2>(s, need_next, prev, a, d);
-      if (TAR && b > tbest) {
+      if (TAR && wta_beats(b, tbest)) {
         tbest = b;
         targ = d;
       }
@@ -102,6 +102,41 @@ __global__ __launch_bounds__(kSelThreads) void lr_check_kernel(const int32_t* __
   valid[row + u] = (x >= 0 && abs(a - dtar[row + (x < 0 ? 0 : x)]) <= tau) ? 1 : 0;
 }
 
+// Winner-take-all of an unaggregated cost view, the disparities the restricted
+// search of Sec. IV centres its windows on: first maximum over d (wta_beats) of
+// cost[d * cps + v * crs + u], one thread per pixel, loads in chunks of kSelUnroll
+// ahead of the compare chain (coalesced across the row).
+__global__ __launch_bounds__(kSelThreads) void cost_argmax_kernel(const float* __restrict__ cost, int64_t cps,
+                                                                 int64_t crs, int W, int D,
+                                                                 int32_t* __restrict__ disp) {
+  const int u = blockIdx.x * kSelThreads + threadIdx.x;
+  if (u >= W) return;
+  const int v = blockIdx.y;
+  const float* c = cost + static_cast<int64_t>(v) * crs + u;
+  float b = c[0];
+  int a = 0;
+  int d = 1;
+  for (; d + kSelUnroll <= D; d += kSelUnroll) {
+    float x[kSelUnroll];
+#pragma unroll
+    for (int i = 0; i < kSelUnroll; ++i) x[i] = c[(d + i) * cps];
+#pragma unroll
+    for (int i = 0; i < kSelUnroll; ++i)
+      if (wta_beats(x[i], b)) {
+        b = x[i];
+        a = d + i;
+      }
+  }
+  for (; d < D; ++d) {
+    const float x = c[d * cps];
+    if (wta_beats(x, b)) {
+      b = x;
+      a = d;
+    }
+  }
+  disp[static_cast<int64_t>(v) * W + u] = a;
+}
+
 }  // namespace rsv
 
 namespace rsv {
@@ -144,4 +179,17 @@ extern "C" int rsv_select_subpixel_ref(const float* agg_ref, const int32_t* disp
                                        uint8_t* valid, float* top2, void* stream) {
   return rsv::run_select(agg_ref, nullptr, height, width, p, disp_ref, const_cast<int32_t*>(disp_tar),
                          disp_sub, valid, top2, stream);
+}
+
+extern "C" int rsv_cost_argmax(const float* cost, int64_t plane_stride, int64_t row_stride, int32_t height,
+                               int32_t width, int32_t D, int32_t* disp, void* stream) {
+  using namespace rsv;
+  if (!cost || !disp) return RSV_E_NULL;
+  if (height < 1 || width < 1 || D < 1 || D > RSV_MAX_D || row_stride < width || plane_stride < 1)
+    return RSV_E_SHAPE;
+  if (!aligned(cost, 4) || !aligned(disp, 4)) return RSV_E_ALIGN;
+  const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
+  cost_argmax_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(cost, plane_stride, row_stride, width, D,
+                                                                        disp);
+  return check_launch();
 }

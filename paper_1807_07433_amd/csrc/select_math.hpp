@@ -9,9 +9,18 @@
 
 namespace rsv {
 
+// The winner-take-all order (Sec. II-B.3): a later value v replaces the running best
+// b when it is strictly greater; a NaN (from non-finite inputs) never replaces a
+// number, and a number replaces a NaN.  So a pixel's winner is the first maximum of
+// its non-NaN values (d = 0 if all are NaN), and since this order is a total
+// preorder, merging the winners of consecutive disparity ranges (lower range first,
+// the upper one replacing it only when it beats it) gives the same winner as one
+// scan: the tile sinks' parallel merges match the select kernel's scan.
+__device__ __forceinline__ bool wta_beats(float v, float b) { return v > b || (b != b && v == v); }
+
 // Running state of the reference-volume scan over d = 0, 1, ... of one pixel: the
 // best value and its d, the second best, and the best's neighbours.  Ties keep the
-// lowest d: a later d replaces the best only when strictly greater.
+// lowest d: a later d replaces the best only when strictly greater (wta_beats).
 struct Scan {
   float best, second, am, ap;
   int arg;
@@ -37,21 +46,25 @@ __device__ __forceinline__ void scan_step(Scan& s, bool& need_next, float& prev,
     s.ap = a;
     need_next = false;
   }
-  if (a > s.best) {
+  if (wta_beats(a, s.best)) {
     if (SECOND) s.second = s.best;
     s.best = a;
     s.arg = d;
     s.am = prev;
     need_next = true;
-  } else if (SECOND && a > s.second) {
+  } else if (SECOND && wta_beats(a, s.second)) {
     s.second = a;
   }
   prev = a;
 }
 
-// Eq. 12: d + (a(d-1) - a(d+1)) / (2a(d-1) + 2a(d+1) - 4a(d)); ends of the range unrefined.
+// Eq. 12: d + (a(d-1) - a(d+1)) / (2a(d-1) + 2a(d+1) - 4a(d)); ends of the range unrefined,
+// and so is a winner that is not a maximum of its neighbours (the restricted search's
+// winner at a window edge can have a larger value just outside; the full method's
+// winner never does, so there this test never fires).
 __device__ __forceinline__ float parabola(int arg, float best, float am, float ap, int D) {
   if (arg <= 0 || arg >= D - 1) return static_cast<float>(arg);
+  if (am > best || ap > best) return static_cast<float>(arg);
   // Eq. 12 written with the gaps below the peak, x = c(d) - c(d-1) and
   // y = c(d) - c(d+1): the offset (x - y) / (2 (x + y)) equals
   // (c(d-1) - c(d+1)) / (2c(d-1) + 2c(d+1) - 4c(d)), and since x, y >= 0 at a

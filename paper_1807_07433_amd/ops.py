@@ -215,6 +215,88 @@ def aggregate_select(cost: torch.Tensor, guide: torch.Tensor, params, disp_tar: 
     return o
 
 
+def cost_argmax(cost: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """First argmax over d of an unaggregated [D][H][W] cost volume or view
+    (rsv_cost_argmax): the calculated disparities of the restricted search (Sec. IV)."""
+    lib = load()
+    D, H, W = cost.shape
+    _dev(cost, "cost", torch.float32)
+    if cost.stride(2) != 1:
+        raise ValueError("cost views need unit column stride")
+    out = out if out is not None else torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    _contig(out, "disp", torch.int32, (H, W))
+    check(lib.rsv_cost_argmax(cost.data_ptr(), cost.stride(0), cost.stride(1), H, W, D, out.data_ptr(),
+                              _stream(cost.device)), "rsv_cost_argmax")
+    return out
+
+
+def aggregate_restricted_argmax(cost: torch.Tensor, guide: torch.Tensor, params, coarse: torch.Tensor,
+                                radius: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """rsv_aggregate_argmax inside each pixel's window of min(2 radius + 1, D) disparities
+    around coarse (rsv_aggregate_restricted_argmax, Sec. IV)."""
+    lib = load()
+    D, H, W = cost.shape
+    _dev(cost, "cost", torch.float32, (int(params.D), H, W))
+    if tuple(guide.shape) != (H, W) or cost.stride(2) != 1:
+        raise ValueError("guide must match the volume's H, W; cost views need unit column stride")
+    _contig(coarse, "coarse", torch.int32, (H, W))
+    out = out if out is not None else torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    _contig(out, "disp", torch.int32, (H, W))
+    p = _params(params)
+    check(lib.rsv_aggregate_restricted_argmax(cost.data_ptr(), cost.stride(0), cost.stride(1), image(guide, "guide"),
+                                              C.byref(p), coarse.data_ptr(), int(radius), out.data_ptr(),
+                                              _stream(cost.device)), "rsv_aggregate_restricted_argmax")
+    return out
+
+
+def aggregate_restricted_select(cost: torch.Tensor, guide: torch.Tensor, params, coarse: torch.Tensor,
+                                radius: int, disp_tar: torch.Tensor, out: dict | None = None) -> dict:
+    """rsv_aggregate_select inside each pixel's window around coarse
+    (rsv_aggregate_restricted_select, Sec. IV): disp_ref, disp_sub, valid."""
+    lib = load()
+    D, H, W = cost.shape
+    _dev(cost, "cost", torch.float32, (int(params.D), H, W))
+    if tuple(guide.shape) != (H, W) or cost.stride(2) != 1:
+        raise ValueError("guide must match the volume's H, W; cost views need unit column stride")
+    _contig(coarse, "coarse", torch.int32, (H, W))
+    _contig(disp_tar, "disp_tar", torch.int32, (H, W))
+    dev = cost.device
+    o = dict(out) if out else {}
+    shapes = {"disp_ref": ((H, W), torch.int32), "disp_sub": ((H, W), torch.float32),
+              "valid": ((H, W), torch.uint8)}
+    for k, (shp, dt) in shapes.items():
+        if k not in o:
+            o[k] = torch.empty(shp, dtype=dt, device=dev)
+        _contig(o[k], k, dt, shp)
+    o["disp_tar"] = disp_tar
+    p = _params(params)
+    check(lib.rsv_aggregate_restricted_select(cost.data_ptr(), cost.stride(0), cost.stride(1),
+                                              image(guide, "guide"), C.byref(p), coarse.data_ptr(), int(radius),
+                                              disp_tar.data_ptr(), o["disp_ref"].data_ptr(),
+                                              o["disp_sub"].data_ptr(), o["valid"].data_ptr(), _stream(dev)),
+          "rsv_aggregate_restricted_select")
+    return o
+
+
+def reconstruct_restricted(left: torch.Tensor, right: torch.Tensor, plane, camera, params, radius: int,
+                           out: dict | None = None) -> dict:
+    """The plain path with the restricted search of Sec. IV: warp -> joint cost volume ->
+    calculated disparities of both views (rsv_cost_argmax) -> target argmax and the
+    reference aggregation with the selection folded in, each over the windows of
+    min(2 radius + 1, D) disparities -> post-processing + 3-D points."""
+    wp = warp(right, plane)
+    cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
+    cc_ref = cost_argmax(cref)
+    cc_tar = cost_argmax(ctar)
+    dtar = aggregate_restricted_argmax(ctar, wp, params, cc_tar, radius)
+    sel = aggregate_restricted_select(cref, left, params, cc_ref, radius, dtar, out=out)
+    dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
+    res = dict(warped=wp, cost_ref=cref, cost_tar=ctar, coarse_ref=cc_ref, coarse_tar=cc_tar,
+               disp_final=dfin, xyz=xyz)
+    res.update(sel)
+    return res
+
+
 def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor | None, params, want_top2: bool = False,
                     out: dict | None = None) -> dict:
     """WTA, left-right check and Eq. 12.  With agg_tar None, out["disp_tar"] must hold
@@ -387,4 +469,5 @@ __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint
            "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select",
            "aggregate_select_supported", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "selected_aggregate_sum", "cost_adjoint",
+           "cost_argmax", "aggregate_restricted_argmax", "aggregate_restricted_select", "reconstruct_restricted",
            "image", "load"]

@@ -237,3 +237,29 @@ def test_lds_probe_library_loads_and_rejects_bad_arguments():
     assert fn(16, 0, 1, FAKE, None) == -1   # at least one block
     assert fn(16, 1, 0, FAKE, None) == -1   # at least one iteration
     assert fn(8, 1, 1, None, None) == -1    # output buffer required
+
+
+def test_restricted_search_validation(lib):
+    """rsv_cost_argmax and the restricted aggregations reject bad arguments before
+    launching: nulls, alignment, shapes, a negative radius, radius 6 windows and W < 4."""
+    p = _params()
+    A, B, Cc, Dd, E = FAKE, FAKE + 4096, FAKE + 8192, FAKE + 12288, FAKE + 16384
+    assert lib.rsv_cost_argmax(None, 32 * 48, 48, 32, 48, 32, A, None) == -1
+    assert lib.rsv_cost_argmax(A, 32 * 48, 48, 32, 48, 32, None, None) == -1
+    assert lib.rsv_cost_argmax(A, 32 * 48, 47, 32, 48, 32, B, None) == -2
+    assert lib.rsv_cost_argmax(A, 32 * 48, 48, 32, 48, 0, B, None) == -2
+    assert lib.rsv_cost_argmax(A, 32 * 48, 48, 32, 48, 513, B, None) == -2
+    assert lib.rsv_cost_argmax(A + 2, 32 * 48, 48, 32, 48, 32, B, None) == -5
+    f = lib.rsv_aggregate_restricted_argmax
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), None, 3, B, None) == -1
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), B, 3, None, None) == -1
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), B, -1, Cc, None) == -3
+    assert f(A, 32 * 48, 48, _img(), C.byref(_params(agg_radius=6)), B, 3, Cc, None) == -3
+    assert f(A, 32 * 3, 3, _img(w=3), C.byref(p), B, 3, Cc, None) == -2
+    assert f(A, 32 * 48, 47, _img(), C.byref(p), B, 3, Cc, None) == -2
+    assert f(A, 32 * 48, 48, _img(), C.byref(p), B + 2, 3, Cc, None) == -5
+    g = lib.rsv_aggregate_restricted_select
+    assert g(A, 32 * 48, 48, _img(), C.byref(p), B, 3, None, Cc, Dd, E, None) == -1
+    assert g(A, 32 * 48, 48, _img(), C.byref(p), B, 3, Cc, Dd, None, E, None) == -1
+    assert g(A, 32 * 48, 48, _img(), C.byref(_params(lr_threshold=-1)), B, 3, Cc, Dd, E, A, None) == -3
+    assert g(A, 32 * 48, 48, _img(), C.byref(p), B, -2, Cc, Dd, E, A, None) == -3

@@ -65,3 +65,18 @@ def test_agrees_wherever_the_full_winner_is_inside_the_window():
     assert np.array_equal(res["disp_ref"][inside], full_d[inside])
     # the calculated disparity is the unaggregated volume's first argmax
     assert np.array_equal(res["coarse_ref"], np.argmax(res["cost_ref"], axis=0))
+
+
+def test_subpixel_only_at_a_discrete_maximum():
+    """Eq. 12 through a maximum equals the full method's; next to a larger neighbour the
+    winner stays unrefined."""
+    A = np.zeros((7, 1, 3))
+    A[:, 0, 0] = [0, 1, 3, 2, 0, 0, 0]     # maximum at 2
+    A[:, 0, 1] = [0, 1, 2, 5, 4, 0, 0]     # window winner 2, neighbour 3 larger
+    A[:, 0, 2] = [9, 8, 7, 6, 5, 4, 3]     # winner 3 inside a descending slope
+    d = np.array([[2, 2, 3]])
+    got = RS.subpixel_at_maximum(A, d)
+    with np.errstate(divide="ignore", invalid="ignore"):  # the slope pixel's Eq. 12 divides by 0
+        full = S.subpixel(A, d)
+    assert got[0, 0] == full[0, 0] and abs(got[0, 0] - (2 + (1 - 2) / (2 + 4 - 12))) < 1e-12
+    assert got[0, 1] == 2.0 and got[0, 2] == 3.0
