@@ -1,7 +1,7 @@
 """Benchmark of the road-surface stereo path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload road1280_d64]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-batch] [--no-diff] [--no-restricted] [--no-sweep]
 
 One step = one full frame of the plain path on the 1280x720, D = 64 road pair
 (warp -> ZNCC reference + target volumes -> bilateral aggregation of both ->
@@ -10,9 +10,10 @@ resident in HBM.  Prints ONE JSON line.  `value` is Eq. 13's Mde/s over the cost
 volume and both aggregations, W*H*D / t_(cost + 2 x aggregate) * 1e-6 (the metric);
 `fps` and `mde_full_frame` cover the whole frame.  Per-kernel durations come from HIP
 events on the stream the kernels run on; the roofline object covers the frame's
-dominant kernel.  The line also carries the batched form on the 64-pair uneven
-workload against 64 sequential plain calls (--no-batch skips it), the differentiable
-form on 8 float32 pairs (--no-diff skips it) and the FP64 oracle's CPU rate.
+dominant kernel (one launch).  The line also carries the batched form on the 64-pair
+uneven workload against 64 sequential plain calls, the differentiable form on 8
+float32 pairs, the restricted search of Sec. IV, a block / window radius sweep, and
+the FP64 oracle's CPU rate in one process and over a process pool.
 """
 from __future__ import annotations
 
@@ -48,6 +49,10 @@ def parse():
     ap.add_argument("--diff-pairs", type=int, default=8)
     ap.add_argument("--diff-reps", type=int, default=10)
     ap.add_argument("--diff-steps", type=int, default=50)
+    ap.add_argument("--no-restricted", action="store_true", help="skip the restricted search (Sec. IV)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the block / window radius sweep")
+    ap.add_argument("--sweep-steps", type=int, default=5)
+    ap.add_argument("--cpu-pool-rows", type=int, default=24, help="rows per worker in the pooled oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy one 512 MiB buffer (reads 512 MiB, writes "
                          "512 MiB) so counter runs can scale FETCH_SIZE / WRITE_SIZE")
@@ -72,10 +77,12 @@ def source_sha(paths):
 
 
 CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
+_AGG_SOURCES = ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
+                "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"]
 KERNEL_SOURCES = {
     "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
-    "aggregate": ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
-                  "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"],
+    "aggregate_ref": _AGG_SOURCES,
+    "aggregate_tar": _AGG_SOURCES,
     "select_subpixel": ["select.hip", "select_math.hpp", "rsv_internal.hpp"],
 }
 
@@ -134,33 +141,54 @@ def cost_lds_bytes(W, H, D, r):
     return bx * by * per_block
 
 
+def agg_entry(stage_ms, key, W, H, D, prm, fused):
+    """One aggregation launch against the FP32 arithmetic roofline: 2m + 2 FLOP per
+    entry (m = (2 rho + 1)^2 weighted terms, the weight sum and the normalisation).
+    Also its HBM rate (4 B per entry read; 4 B written as well where an unfused
+    reference launch writes its volume), the matrix-core work it issues (3 split-fp16
+    MFMAs per K-step over the padded window union) against the fp16 matrix peak, and
+    its LDS traffic from the tile's design."""
+    n = W * H * D
+    m = (2 * prm.agg_radius + 1) ** 2
+    ms = stage_ms[key]
+    flops = (2 * m + 2) * n
+    tf = flops / (ms * 1e-3) / 1e12
+    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    issued = tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
+    itf = issued / (ms * 1e-3) / 1e12
+    writes = key == "aggregate_ref" and not fused
+    gbs = (8 if writes else 4) * n / (ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+            "flops_per_launch": flops, "ms": round(ms, 5),
+            "hbm_view": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)},
+            "mfma_view": {"issued_flops_per_launch": issued, "achieved_tflops": round(itf, 1),
+                          "peak": PEAK_FP16_MFMA_TFLOPS, "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)},
+            "lds_view": lds_view(agg_lds_bytes(W, H, D, prm.agg_radius), ms)}
+
+
+def lds_view(nbytes, ms):
+    tbs = nbytes / (ms * 1e-3) / 1e12
+    return {"bytes_per_launch": nbytes, "achieved_tbs": round(tbs, 2), "peak_tbs": round(PEAK_LDS_TBS, 1),
+            "frac": round(tbs / PEAK_LDS_TBS, 4)}
+
+
 def kernel_rooflines(stage_ms, W, H, D, prm, fused=False):
     """Per-launch algorithmic work / average launch time for the volume kernels, each
     against the resource that bounds it at these sizes (fused: the selection runs
     inside the reference aggregation, so there is no select kernel):
-      cost_volume: HBM, writes the joint volume that holds C_ref and C_tar (the
-                   identity after Eq. 5): every distinct cost value once, 4 B each,
-                   H (D W + D (D - 1) / 2) values (image reads are O(1/D));
-      aggregate:   FP32 arithmetic, 2m + 2 FLOP per entry (m = (2 rho + 1)^2 weighted
-                   terms, weight sum and normalisation), against the FP32 vector peak.
-                   Also reported: its HBM rate (per launch, averaged over the two:
-                   4 B per entry read, plus 4 B written by an unfused reference
-                   launch) and the matrix-core work
-                   it issues (3 split-fp16 MFMAs per K-step, padded window union)
-                   against the fp16 matrix peak;
-      select:      HBM, reads the reference aggregated volume, 4 B per entry (the
-                   target volume is reduced to its argmax inside its aggregation).
-    The cost and aggregation kernels also carry their LDS traffic (agg_lds_bytes,
-    cost_lds_bytes) against the LDS peak."""
+      cost_volume:    HBM, writes the joint volume that holds C_ref and C_tar (the
+                      identity after Eq. 5): every distinct cost value once, 4 B each,
+                      H (D W + D (D - 1) / 2) values (image reads are O(1/D));
+      aggregate_ref,  FP32 arithmetic (agg_entry), each launch on its own: the reference
+      aggregate_tar:  aggregation (with the selection folded in where fused) and the
+                      target aggregation reduced to its argmax;
+      select:         HBM, reads the reference aggregated volume, 4 B per entry (the
+                      target volume is reduced to its argmax inside its aggregation).
+    The cost kernel also carries its LDS traffic (cost_lds_bytes) against the LDS peak."""
     n = W * H * D
-    m = (2 * prm.agg_radius + 1) ** 2
     out = {}
     joint_bytes = 4 * H * (D * W + D * (D - 1) // 2)
-    def lds_view(nbytes, ms):
-        tbs = nbytes / (ms * 1e-3) / 1e12
-        return {"bytes_per_launch": nbytes, "achieved_tbs": round(tbs, 2), "peak_tbs": round(PEAK_LDS_TBS, 1),
-                "frac": round(tbs / PEAK_LDS_TBS, 4)}
-
     hbm_kernels = [("cost_volume", joint_bytes)] + ([] if fused else [("select_subpixel", 4 * n)])
     for k, nbytes in hbm_kernels:
         ms = stage_ms[k]
@@ -169,21 +197,8 @@ def kernel_rooflines(stage_ms, W, H, D, prm, fused=False):
                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes, "ms": round(ms, 5)}
     out["cost_volume"]["lds_view"] = lds_view(cost_lds_bytes(W, H, D, prm.block_radius),
                                               stage_ms["cost_volume"])
-    ms = 0.5 * (stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"])
-    flops = (2 * m + 2) * n
-    tf = flops / (ms * 1e-3) / 1e12
-    tiles = ((W + 15) // 16) * ((H + 15) // 16)
-    issued = tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
-    itf = issued / (ms * 1e-3) / 1e12
-    gbs = (4 * n if fused else 6 * n) / (ms * 1e-3) / 1e9
-    out["aggregate"] = {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
-                        "flops_per_launch": flops, "ms": round(ms, 5),
-                        "hbm_view": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)},
-                        "mfma_view": {"issued_flops_per_launch": issued, "achieved_tflops": round(itf, 1),
-                                      "peak": PEAK_FP16_MFMA_TFLOPS,
-                                      "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)},
-                        "lds_view": lds_view(agg_lds_bytes(W, H, D, prm.agg_radius), ms)}
+    for key in ("aggregate_ref", "aggregate_tar"):
+        out[key] = agg_entry(stage_ms, key, W, H, D, prm, fused)
     return out
 
 
@@ -260,6 +275,13 @@ def bench_batch(a, rsv, torch):
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1) / a.batch_steps
     sizes = sorted({(c.pair.left.shape[1], c.pair.left.shape[0], c.params.D) for c in cases})
+    m = (2 * prm0.agg_radius + 1) ** 2
+    agg_flops = 2 * (2 * m + 2) * work
+    tf = agg_flops / (ms_batch * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP32_TFLOPS, 4), "flops_per_batch": agg_flops,
+            "scope": "both aggregations' 2m + 2 FLOP per entry of every pair, over the whole graph's time "
+                     "(warp, cost, tail included)"}
     return {"workload": f"batch64_mixed: {len(cases)} uint8 pairs, sizes/D drawn from "
                         f"{{640x360, 1280x720, 1920x1080}} x {{32, 64, 128}}, NCC 7x7, bilateral 11x11",
             "sum_whd": work, "distinct_w_h_d": len(sizes),
@@ -267,15 +289,38 @@ def bench_batch(a, rsv, torch):
             "value": round(work / (ms_batch * 1e-3) * 1e-6, 2), "unit": "Mpix·disp/s",
             "plain_sequential_ms": round(ms_plain, 4),
             "plain_sequential_value": round(work / (ms_plain * 1e-3) * 1e-6, 2),
-            "speedup_vs_plain": round(ms_plain / ms_batch, 4),
+            "speedup_vs_plain": round(ms_plain / ms_batch, 4), "roofline": roof,
             "tuning": tuning.as_dict(), "plan": info, "steps": a.batch_steps}
+
+
+def adjoint_flops(torch, disp, mask, prm):
+    """Algorithmic FLOPs of one adjoint (rsv_cost_adjoint) for the selected disparities
+    disp and the pixel set mask: per pixel q and each distinct selected disparity d of
+    the Omega pixels in its window (the (q, d) pairs with dL/dc(q, d) != 0), the left-
+    and warped-block gradients, 2 multiply-adds per block tap (4 n); per Omega pixel,
+    A(p) and dL/dw over its window (4 m); per pixel, the gather of dL/dc over its
+    window (2 m).  n = (2 block_radius + 1)^2, m = (2 agg_radius + 1)^2."""
+    import torch.nn.functional as F
+    H, W = disp.shape
+    A = prm.agg_radius
+    K = 2 * A + 1
+    n = (2 * prm.block_radius + 1) ** 2
+    m = K * K
+    dm = torch.where(mask.bool() & (disp >= 0) & (disp < prm.D), disp, torch.full_like(disp, -1)).float()
+    win = F.unfold(F.pad(dm[None, None], (A, A, A, A), value=-1.0), K)[0]  # [m, H*W]
+    srt, _ = torch.sort(win, dim=0)
+    distinct = (srt[0] >= 0).sum() + ((srt[1:] != srt[:-1]) & (srt[1:] >= 0)).sum()
+    n_qd = int(distinct)
+    omega = int(mask.bool().sum())
+    return n_qd * 4 * n + omega * 4 * m + H * W * 2 * m, n_qd
 
 
 def bench_diff(a, rsv, torch):
     """The differentiable form on 8 float32 1280x720 pairs (D = 64): per pair, the
-    forward of the loss (warp, reference volume, aggregation, selected sum) and the
-    adjoint; then 50 steps of plane refinement over the 8 pairs from a plane perturbed
-    by <= 0.4 px, with the RMS shift error before and after."""
+    forward of the loss (warp, joint cost volume, the aggregation at the selected
+    disparities) and the adjoint, with the adjoint's roofline (adjoint_flops); then 50
+    steps of plane refinement over the 8 pairs from a plane perturbed by <= 0.4 px,
+    with the RMS shift error before and after."""
     import numpy as np
     import synth
     from paper_1807_07433_amd import ops
@@ -318,11 +363,16 @@ def bench_diff(a, rsv, torch):
                                steps=a.diff_steps, lr=0.02)
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
+    fl, n_qd = adjoint_flops(torch, d, m, prm)
+    tf = fl / (float(np.median(bwd)) * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP32_TFLOPS, 4), "flops_per_launch": fl, "nonzero_q_d_pairs": n_qd,
+            "scope": "the adjoint of one pair (adjoint_flops) over its median time"}
     return {"workload": f"diff8_road1280: {len(cases)} float32 {W}x{H} road pairs, D={prm.D}, "
                         f"NCC 7x7, bilateral 11x11; loss = sum over valid pixels of the aggregated "
                         f"reference correlation at the selected disparity",
             "forward_ms": round(float(np.median(fwd)), 4), "adjoint_ms": round(float(np.median(bwd)), 4),
-            "adjoint_over_forward": round(float(np.median(bwd) / np.median(fwd)), 3),
+            "adjoint_over_forward": round(float(np.median(bwd) / np.median(fwd)), 3), "roofline": roof,
             "refine_steps": a.diff_steps, "refine_s": round(t_ref, 3),
             "refine_ms_per_step": round(t_ref / a.diff_steps * 1e3, 2),
             "shift_rms_px": [round(e0, 4), round(shift_err(theta.numpy()), 4)],
@@ -388,27 +438,216 @@ def plain_graph(torch, step, steps, outputs):
     return {"ms_per_step": round(ms, 5), "fps": round(1000.0 / ms, 2), "replay_equals_eager": same}
 
 
-def cpu_baseline(case, rows: int):
-    """The FP64 oracle, as it stands, on a band of `rows` full-width rows of the same pair
-    (same D and windows): warp -> both volumes -> both aggregations -> select -> 3-D."""
+def _oracle_band(args):
+    """The oracle's whole plain path on rows [v0, v0 + rows) of a workload, computed on
+    those rows plus a halo of block_radius + agg_radius rows on each side (every stage
+    reads at most that far across rows; the warp, WTA and Eq. 11 never do), with the
+    plane re-based to the band's first row.  Returns the band's seconds."""
+    name, v0, rows = args
     import numpy as np
+    import synth
     from oracle import stereo as S
+    case = {"road1280_d64": synth.road1280_d64, "road320_d32": synth.road320_d32,
+            "road1920_d128": synth.road1920_d128}[name]()
+    p, prm = case.pair, case.params
+    H = p.left.shape[0]
+    halo = prm.block_radius + prm.agg_radius
+    s0, s1 = max(0, v0 - halo), min(H, v0 + rows + halo)
+    pl = case.plane
+    plane = (pl.a0 + pl.a1 * s0, pl.a1, pl.a2, pl.delta)
+    cam = (case.camera.f, case.camera.baseline, case.camera.u0, case.camera.v0 - s0)
+    L = np.ascontiguousarray(p.left[s0:s1])
+    R = np.ascontiguousarray(p.right[s0:s1])
+    t0 = time.perf_counter()
+    S.reconstruct(L, R, plane, cam, prm.D, prm.block_radius, prm.agg_radius, prm.gamma_d, prm.gamma_r,
+                  prm.lr_threshold, prm.sigma_min)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, case, rows: int, pool_rows: int):
+    """The FP64 oracle, as it stands (NumPy, FP64, the whole plain path: warp -> both
+    volumes -> both aggregations -> select -> 3-D), on the host's cores in two modes:
+    one process on a band of `rows` full-width rows (plus its halo), and a process pool
+    with one band of `pool_rows` rows per core (at most 16 cores, the host share of one
+    GPU) over consecutive bands.  Rates are W x rows x D per wall second (the halo rows
+    are computed but not counted)."""
+    import concurrent.futures as cf
     p, prm = case.pair, case.params
     H, W = p.left.shape
     v0 = H // 2 - rows // 2
-    L = np.ascontiguousarray(p.left[v0:v0 + rows])
-    R = np.ascontiguousarray(p.right[v0:v0 + rows])
-    pl = case.plane
-    plane = (pl.a0 + pl.a1 * v0, pl.a1, pl.a2, pl.delta)   # same rows of the same plane
-    cam = (case.camera.f, case.camera.baseline, case.camera.u0, case.camera.v0 - v0)
+    t1 = _oracle_band((workload, v0, rows))
+    one = W * rows * prm.D / t1 * 1e-6
+    cores = max(1, min(16, os.cpu_count() or 1))
+    n = min(cores, H // pool_rows)
+    b0 = H // 2 - n * pool_rows // 2
+    jobs = [(workload, b0 + k * pool_rows, pool_rows) for k in range(n)]
     t0 = time.perf_counter()
-    S.reconstruct(L, R, plane, cam, prm.D, prm.block_radius, prm.agg_radius, prm.gamma_d,
-                  prm.gamma_r, prm.lr_threshold, prm.sigma_min)
-    dt = time.perf_counter() - t0
-    return {"value": round(W * rows * prm.D / dt * 1e-6, 4), "unit": "Mpix·disp/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"rows {v0}..{v0 + rows - 1} of the {W}x{H} pair (full width, D={prm.D}), "
-                      f"whole plain path in FP64 NumPy, {dt:.1f} s, single thread"}
+    with cf.ProcessPoolExecutor(n) as ex:
+        list(ex.map(_oracle_band, jobs))
+    tp = time.perf_counter() - t0
+    pooled = W * n * pool_rows * prm.D / tp * 1e-6
+    return {"value": round(pooled, 4), "unit": "Mpix·disp/s", "cores": n, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "sample": f"{n} bands of {pool_rows} full-width rows (rows {b0}..{b0 + n * pool_rows - 1}) of the "
+                      f"{W}x{H} pair, D={prm.D}, each with its {prm.block_radius + prm.agg_radius}-row halo, "
+                      f"whole plain path in FP64 NumPy, one process per band, {tp:.1f} s wall",
+            "single_process": {"value": round(one, 4), "cores": 1,
+                               "sample": f"rows {v0}..{v0 + rows - 1}, {t1:.1f} s"}}
+
+
+def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_full):
+    """The restricted search of Sec. IV on the same frame: calculated disparities of
+    both views (rsv_cost_argmax on the joint volume's views), then the target argmax
+    and the reference aggregation with the selection folded in, each over windows of
+    2r + 1 disparities, for r = 2, 4, 8.  Per radius: stage times, the rate over cost +
+    calculated disparities + both aggregations (the full method's W*H*D in the
+    numerator, so it compares with `value`), agreement with the full method, and the
+    accuracy of both against the generator's ground truth (mean |d_f - d_gt| over the
+    pixels each keeps valid, away from the borders)."""
+    import numpy as np
+    p, prm = case.pair, case.params
+    H, W = p.left.shape
+    D = prm.D
+    dev = L.device
+    f32 = dict(dtype=torch.float32, device=dev)
+    wp = torch.empty((H, W), **f32)
+    joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
+    cref, ctar = rsv.joint_views(joint, W)
+    i32 = dict(dtype=torch.int32, device=dev)
+    cc_ref, cc_tar, dtar = torch.empty((H, W), **i32), torch.empty((H, W), **i32), torch.empty((H, W), **i32)
+    sel = {"disp_ref": torch.empty((H, W), **i32), "disp_sub": torch.empty((H, W), **f32),
+           "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
+    dfin, xyz = torch.empty((H, W), **f32), torch.empty((H, W, 3), **f32)
+    stages = ["warp", "cost_volume", "cost_argmax", "aggregate_tar", "aggregate_ref", "triangulate"]
+    gt = p.disp_gt
+    edge = prm.block_radius + prm.agg_radius
+    inner = np.zeros((H, W), bool)
+    inner[edge:H - edge, edge:W - edge] = True
+
+    def accuracy(df, valid):
+        m = inner & valid
+        return round(float(np.abs(df[m] - gt[m]).mean()), 4), round(float(m.mean()), 4)
+
+    full_acc = accuracy(full_dfin.cpu().numpy().astype(np.float64), full_sel["valid"].cpu().numpy().astype(bool))
+    out = {"full": {"mean_abs_err_px": full_acc[0], "valid_frac": full_acc[1],
+                    "cost_plus_agg_ms": round(stage_full["cost_volume"] + stage_full["aggregate_ref"] +
+                                              stage_full["aggregate_tar"], 5)},
+           "radii": {}}
+    for radius in (2, 4, 8):
+        def step(ev=None):
+            marks = iter(ev) if ev is not None else None
+
+            def mark():
+                if marks is not None:
+                    next(marks).record()
+            mark()
+            rsv.warp(R, case.plane, out=wp)
+            mark()
+            rsv.cost_volume_joint(L, wp, prm, out=joint)
+            mark()
+            rsv.cost_argmax(cref, out=cc_ref)
+            rsv.cost_argmax(ctar, out=cc_tar)
+            mark()
+            rsv.aggregate_restricted_argmax(ctar, wp, prm, cc_tar, radius, out=dtar)
+            mark()
+            rsv.aggregate_restricted_select(cref, L, prm, cc_ref, radius, dtar, out=sel)
+            mark()
+            rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
+            mark()
+        for _ in range(max(1, a.warmup)):
+            step()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        for i in range(a.steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        st = {k: sum(e[j].elapsed_time(e[j + 1]) for e in evs) / a.steps for j, k in enumerate(stages)}
+        t_ca = st["cost_volume"] + st["cost_argmax"] + st["aggregate_tar"] + st["aggregate_ref"]
+        frame = sum(st.values())
+        acc = accuracy(dfin.cpu().numpy().astype(np.float64), sel["valid"].cpu().numpy().astype(bool))
+        out["radii"][str(radius)] = {
+            "window": min(2 * radius + 1, D),
+            "stage_ms": {k: round(v, 5) for k, v in st.items()},
+            "value": round(mde_per_s(W, H, D, t_ca * 1e-3), 2), "unit": "Mpix·disp/s",
+            "ms_per_frame": round(frame, 5),
+            "speedup_cost_plus_agg_vs_full": round(out["full"]["cost_plus_agg_ms"] / t_ca, 3),
+            "disp_ref_equal_to_full": round(float((sel["disp_ref"] == full_sel["disp_ref"]).float().mean()), 5),
+            "disp_tar_equal_to_full": round(float((dtar == full_sel["disp_tar"]).float().mean()), 5),
+            "valid_equal_to_full": round(float((sel["valid"] == full_sel["valid"]).float().mean()), 5),
+            "mean_abs_err_px": acc[0], "valid_frac": acc[1]}
+    return out
+
+
+def bench_sweep(a, rsv, torch, case, L, R):
+    """Throughput against the NCC block radius and the bilateral window radius on the
+    same 1280x720 frame and D (the shape of Sec. III's runtime figure): for block radius
+    1..4 and window radius 1..6, the rate over cost + both aggregations (fused selection
+    where the window radius is <= 5, the volume path and the select kernel at 6)."""
+    import dataclasses
+    p, prm0 = case.pair, case.params
+    H, W = p.left.shape
+    D = prm0.D
+    dev = L.device
+    f32 = dict(dtype=torch.float32, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    wp = torch.empty((H, W), **f32)
+    joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
+    cref, ctar = rsv.joint_views(joint, W)
+    aref = None
+    sel = {"disp_ref": torch.empty((H, W), **i32), "disp_tar": torch.empty((H, W), **i32),
+           "disp_sub": torch.empty((H, W), **f32), "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
+    grid = {}
+    for r in (1, 2, 3, 4):
+        for rho in (1, 2, 3, 4, 5, 6):
+            prm = dataclasses.replace(prm0, block_radius=r, agg_radius=rho)
+            fused = rsv.aggregate_select_supported(W, prm)
+            if not fused and aref is None:
+                aref = torch.empty((D, H, W), **f32)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+            def run(record):
+                if record:
+                    ev[0].record()
+                rsv.cost_volume_joint(L, wp, prm, out=joint)
+                if record:
+                    ev[1].record()
+                rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
+                if record:
+                    ev[2].record()
+                if fused:
+                    rsv.aggregate_select(cref, L, prm, sel["disp_tar"], out=sel)
+                else:
+                    rsv.aggregate(cref, L, prm, out=aref)
+                    rsv.select_subpixel(aref, None, prm, out=sel)
+                if record:
+                    ev[3].record()
+            rsv.warp(R, case.plane, out=wp)
+            run(False)
+            tc = ta = 0.0
+            torch.cuda.synchronize()
+            for _ in range(a.sweep_steps):
+                run(True)
+                torch.cuda.synchronize()
+                tc += ev[0].elapsed_time(ev[1])
+                ta += ev[1].elapsed_time(ev[3])
+            tc /= a.sweep_steps
+            ta /= a.sweep_steps
+            grid[f"{r},{rho}"] = {"ms_cost": round(tc, 4), "ms_aggregate_select": round(ta, 4),
+                                  "value": round(mde_per_s(W, H, D, (tc + ta) * 1e-3), 1)}
+    g = lambda r, rho: grid[f"{r},{rho}"]["ms_cost"] + grid[f"{r},{rho}"]["ms_aggregate_select"]
+    return {"workload": f"{W}x{H} uint8 road pair, D={D}; keys 'block_radius,agg_radius'",
+            "unit": "Mpix·disp/s", "grid": grid,
+            "time_ratio_agg_radius_4_over_2_at_block_radius_3": round(g(3, 4) / g(3, 2), 3)}
 
 
 def main():
@@ -504,7 +743,7 @@ def main():
     kernels = kernel_rooflines(stage_ms, W, H, D, prm, fused)
     if probe:
         measured = max(probe["b64_tbs"], probe["b128_tbs"])
-        for k in ("cost_volume", "aggregate"):
+        for k in ("cost_volume", "aggregate_ref", "aggregate_tar"):
             v = kernels[k]["lds_view"]
             v["measured_peak_tbs"] = measured
             v["frac_of_measured"] = round(v["achieved_tbs"] / measured, 4)
@@ -556,8 +795,12 @@ def main():
         out["batched"] = bench_batch(a, rsv, torch)
     if not a.no_diff:
         out["differentiable"] = bench_diff(a, rsv, torch)
+    if not a.no_restricted and fused:
+        out["restricted"] = bench_restricted(a, rsv, torch, case, L, R, cam, sel, dfin, stage_ms)
+    if not a.no_sweep and a.workload == "road1280_d64":
+        out["sweep"] = bench_sweep(a, rsv, torch, case, L, R)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, a.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(a.workload, case, a.cpu_rows, a.cpu_pool_rows)
     print(json.dumps(out))
 
 

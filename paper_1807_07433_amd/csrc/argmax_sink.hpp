@@ -11,43 +11,43 @@
 
 namespace rsv {
 
-// The first maximum (wta_beats order) over the candidates among the four disparities
-// 16 t + 4 q .. + 3 of tile t held in the output tile o for pixel p; a < 0 when none of
-// them lies in [lo, hi].
+// Winners are compared as (key, d) pairs, key = wta_key(value): the larger key, and
+// the lower d between equal keys.  (-inf, INT_MAX) stands for "no candidate".  This
+// order is total, so the lanes' winners of consecutive disparity ranges merge in any
+// grouping into the winner of one scan over d (the select kernel's).
+__device__ __forceinline__ bool wta_better(float kb, int db, float ka, int da) {
+  return kb > ka || (kb == ka && db < da);
+}
+
+// The first maximum (wta_key order) over the candidates among the four disparities
+// 16 t + 4 q .. + 3 of tile t held in the output tile o for pixel p: the key and d,
+// (-inf, INT_MAX) when none of them lies in [lo, hi].
 __device__ __forceinline__ void lane_scan(const float* o, int t, int q, int p, int lo, int hi, float& b,
                                           int& a) {
   using G = AggGeo<1, 16>;
-  b = 0.f;
-  a = -1;
+  float v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = o[(4 * q + k) * G::OST + p];  // all read, then compared
+  b = -INFINITY;
+  a = 0x7fffffff;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int d = 16 * t + 4 * q + k;
-    if (d >= lo && d <= hi) {
-      const float v = o[(4 * q + k) * G::OST + p];
-      if (a < 0 || wta_beats(v, b)) {
-        b = v;
-        a = d;
-      }
+    const float key = wta_key(v[k]);
+    if (d >= lo && d <= hi && (key > b || a == 0x7fffffff)) {
+      b = key;
+      a = d;
     }
   }
 }
 
-// (b, a) <- the merge with quad lane q ^ M (DPP quad_perm PERM) over consecutive
-// disparity ranges: the lower range's winner stands unless the upper one beats it
-// (wta_beats), so both lanes end with the winner one scan over both ranges gives.
-template <int PERM, int M>
-__device__ __forceinline__ void quad_merge(float& b, int& a, int q) {
+// (b, a) <- the better of (b, a) and the quad lane selected by the DPP quad_perm
+// pattern PERM (wta_better).
+template <int PERM>
+__device__ __forceinline__ void quad_merge(float& b, int& a) {
   const float ob = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(b), PERM, 0xF, 0xF, false));
   const int oa = __builtin_amdgcn_mov_dpp(a, PERM, 0xF, 0xF, false);
-  const bool other_lower = (q & M) != 0;
-  bool take;
-  if (oa < 0)
-    take = false;
-  else if (a < 0)
-    take = true;
-  else
-    take = other_lower ? !wta_beats(b, ob) : wta_beats(ob, b);
-  if (take) {
+  if (wta_better(ob, oa, b, a)) {
     b = ob;
     a = oa;
   }
@@ -55,17 +55,17 @@ __device__ __forceinline__ void quad_merge(float& b, int& a, int q) {
 
 // The candidates of tile t for this thread's pixel, merged over its quad: thread i
 // covers pixel i / 4 and disparities 4 (i % 4) .. + 3; all four lanes of a quad end
-// with the tile's winner (a < 0: no candidate in this tile).
+// with the tile's winner ((-inf, INT_MAX): no candidate in this tile).
 __device__ __forceinline__ void tile_winner(const float* o, int t, int lo, int hi, float& b, int& a) {
   const int i = threadIdx.x, p = i >> 2, q = i & 3;
   lane_scan(o, t, q, p, lo, hi, b, a);
-  quad_merge<0xB1, 1>(b, a, q);
-  quad_merge<0x4E, 2>(b, a, q);
+  quad_merge<0xB1>(b, a);  // lanes i ^ 1, then i ^ 2 (no LDS traffic)
+  quad_merge<0x4E>(b, a);
 }
 
 // agg_tile sink for a volume that is only needed through its argmax over d (the
 // target volume of Sec. II-B.3): the 16 x 16 pixels' running winner, nothing written
-// until the end; the select kernel's order (the first maximum over d, wta_beats).
+// until the end; the select kernel's order (the first maximum over d of wta_key).
 // Two forms:
 // * state null (the LDS-loaded tile): the quad lanes of a pixel take the tile's
 //   winner (tile_winner), then the running winner is replaced only when beaten; the
@@ -77,8 +77,8 @@ struct ArgmaxSink {
   int D;
   float* state = nullptr;  // [2][256]: best, then arg bits
   int lo = 0, hi = D - 1;
-  float best = 0.f;
-  int arg = -1;
+  float best = -INFINITY;
+  int arg = 0x7fffffff;
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
     using G = AggGeo<1, 16>;
@@ -89,8 +89,8 @@ struct ArgmaxSink {
       int a = t == 0 ? 0 : __float_as_int(state[256 + p]);
       const int n = min(16, D - 16 * t);
       for (int dd = 0; dd < n; ++dd) {
-        const float v = o[dd * G::OST + p];
-        if ((t == 0 && dd == 0) || wta_beats(v, b)) {
+        const float v = wta_key(o[dd * G::OST + p]);
+        if ((t == 0 && dd == 0) || v > b) {
           b = v;
           a = 16 * t + dd;
         }
@@ -102,7 +102,7 @@ struct ArgmaxSink {
     float b;
     int a;
     tile_winner(o, t, lo, hi, b, a);
-    if (a >= 0 && (arg < 0 || wta_beats(b, best))) {
+    if (wta_better(b, a, best, arg)) {
       best = b;
       arg = a;
     }
@@ -127,7 +127,7 @@ struct ArgmaxSink {
 };
 
 // agg_tile_dma sink for the reference volume: the select kernel's scan result (first
-// maximum over d, wta_beats, and the values at d - 1 and d + 1) from all 1024
+// maximum over d of wta_key, and the values at d - 1 and d + 1) from all 1024
 // threads, in registers; shared by rsv_aggregate_select, the restricted search and
 // the batch kernel's reference tiles.  The quad lanes of a pixel take the tile's
 // winner among the candidates d in [lo, hi] (tile_winner).  When it replaces the
@@ -139,8 +139,8 @@ struct ArgmaxSink {
 struct RefQuadSink {
   int D;
   int lo = 0, hi = D - 1;
-  float best = 0.f, am = 0.f, ap = 0.f, lastv = 0.f;
-  int arg = -1;
+  float best = -INFINITY, am = 0.f, ap = 0.f, lastv = 0.f;
+  int arg = 0x7fffffff;
   bool pend = false;
 
   __device__ __forceinline__ void operator()(int t, const float* o) {
@@ -153,7 +153,7 @@ struct RefQuadSink {
       ap = o[p];
       pend = false;
     }
-    if (a >= 0 && (arg < 0 || wta_beats(b, best))) {
+    if (wta_better(b, a, best, arg)) {  // a real candidate: a is in tile t
       const int k = a - 16 * t;  // the winner's place in the tile, 0 .. 15
       best = b;
       arg = a;

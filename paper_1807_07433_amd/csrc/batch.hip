@@ -126,8 +126,8 @@ struct WtaSink {
           scan_init(s, need_next, prev, a);
         else
           scan_step<false>(s, need_next, prev, a, d);
-      } else if (d == 0 || wta_beats(a, s.best)) {
-        s.best = a;
+      } else if (d == 0 || wta_key(a) > s.best) {
+        s.best = wta_key(a);
         s.arg = d;
       }
     }

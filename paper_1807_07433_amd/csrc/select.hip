@@ -31,12 +31,12 @@ __device__ __forceinline__ void scan_pair(const float* __restrict__ pr, const fl
   auto consume = [&](float a, float b, int d) {
     if (d == 0) {
       scan_init(s, need_next, prev, a);
-      tbest = b;
+      tbest = wta_key(b);
       targ = 0;
     } else {
       scan_step<TOP2>(s, need_next, prev, a, d);
-      if (TAR && wta_beats(b, tbest)) {
-        tbest = b;
+      if (TAR && wta_key(b) > tbest) {
+        tbest = wta_key(b);
         targ = d;
       }
     }
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kSelThreads) void lr_check_kernel(const int32_t* __
 }
 
 // Winner-take-all of an unaggregated cost view, the disparities the restricted
-// search of Sec. IV centres its windows on: first maximum over d (wta_beats) of
+// search of Sec. IV centres its windows on: first maximum over d (wta_key order) of
 // cost[d * cps + v * crs + u], one thread per pixel, loads in chunks of kSelUnroll
 // ahead of the compare chain (coalesced across the row).
 __global__ __launch_bounds__(kSelThreads) void cost_argmax_kernel(const float* __restrict__ cost, int64_t cps,
@@ -113,23 +113,23 @@ __global__ __launch_bounds__(kSelThreads) void cost_argmax_kernel(const float* _
   if (u >= W) return;
   const int v = blockIdx.y;
   const float* c = cost + static_cast<int64_t>(v) * crs + u;
-  float b = c[0];
+  float b = wta_key(c[0]);
   int a = 0;
   int d = 1;
   for (; d + kSelUnroll <= D; d += kSelUnroll) {
     float x[kSelUnroll];
 #pragma unroll
-    for (int i = 0; i < kSelUnroll; ++i) x[i] = c[(d + i) * cps];
+    for (int i = 0; i < kSelUnroll; ++i) x[i] = wta_key(c[(d + i) * cps]);
 #pragma unroll
     for (int i = 0; i < kSelUnroll; ++i)
-      if (wta_beats(x[i], b)) {
+      if (x[i] > b) {
         b = x[i];
         a = d + i;
       }
   }
   for (; d < D; ++d) {
-    const float x = c[d * cps];
-    if (wta_beats(x, b)) {
+    const float x = wta_key(c[d * cps]);
+    if (x > b) {
       b = x;
       a = d;
     }

@@ -9,18 +9,18 @@
 
 namespace rsv {
 
-// The winner-take-all order (Sec. II-B.3): a later value v replaces the running best
-// b when it is strictly greater; a NaN (from non-finite inputs) never replaces a
-// number, and a number replaces a NaN.  So a pixel's winner is the first maximum of
-// its non-NaN values (d = 0 if all are NaN), and since this order is a total
-// preorder, merging the winners of consecutive disparity ranges (lower range first,
-// the upper one replacing it only when it beats it) gives the same winner as one
-// scan: the tile sinks' parallel merges match the select kernel's scan.
-__device__ __forceinline__ bool wta_beats(float v, float b) { return v > b || (b != b && v == v); }
+// The winner-take-all order (Sec. II-B.3) compares keys: the value itself, or -inf
+// for a NaN (from non-finite inputs), so a NaN never beats a number.  A later d
+// replaces the running best only when its key is strictly greater, so a pixel's
+// winner is the first maximum of its non-NaN values (the first d if all are NaN).
+// The order is a total preorder on (key, lower d first), so merging the winners of
+// disparity ranges in any grouping gives the same winner as one scan: the tile sinks'
+// parallel merges match the select kernel's scan.
+__device__ __forceinline__ float wta_key(float v) { return v == v ? v : -INFINITY; }
 
 // Running state of the reference-volume scan over d = 0, 1, ... of one pixel: the
-// best value and its d, the second best, and the best's neighbours.  Ties keep the
-// lowest d: a later d replaces the best only when strictly greater (wta_beats).
+// best key (wta_key) and its d, the second best, and the best's neighbours (values).
+// Ties keep the lowest d: a later d replaces the best only when its key is greater.
 struct Scan {
   float best, second, am, ap;
   int arg;
@@ -29,7 +29,7 @@ struct Scan {
 // The scan after d = 0 with value a.  need_next: the next value is the best's right
 // neighbour; prev: the value at the previous d.
 __device__ __forceinline__ void scan_init(Scan& s, bool& need_next, float& prev, float a) {
-  s.best = a;
+  s.best = wta_key(a);
   s.second = -INFINITY;
   s.am = 0.f;
   s.ap = 0.f;
@@ -46,14 +46,15 @@ __device__ __forceinline__ void scan_step(Scan& s, bool& need_next, float& prev,
     s.ap = a;
     need_next = false;
   }
-  if (wta_beats(a, s.best)) {
+  const float k = wta_key(a);
+  if (k > s.best) {
     if (SECOND) s.second = s.best;
-    s.best = a;
+    s.best = k;
     s.arg = d;
     s.am = prev;
     need_next = true;
-  } else if (SECOND && wta_beats(a, s.second)) {
-    s.second = a;
+  } else if (SECOND && k > s.second) {
+    s.second = k;
   }
   prev = a;
 }

@@ -31,10 +31,12 @@ def test_kernel_roofline_units():
     distinct = sum(720 * (1280 + d) for d in range(64))
     assert k["cost_volume"]["bound"] == "hbm" and k["cost_volume"]["bytes_per_launch"] == 4 * distinct
     assert abs(k["select_subpixel"]["achieved"] - 4 * n / 0.05e-3 / 1e9) < 1.0
-    agg = k["aggregate"]
+    agg = k["aggregate_ref"]
     assert agg["bound"] == "alu" and agg["flops_per_launch"] == (2 * 121 + 2) * n
     assert abs(agg["achieved"] - (2 * 121 + 2) * n / 0.2e-3 / 1e12) < 0.01
     assert abs(agg["frac"] - agg["achieved"] / 157.3) < 1e-3
+    # the unfused reference launch also writes its volume
+    assert abs(agg["hbm_view"]["achieved_gbs"] - 8 * n / 0.2e-3 / 1e9) < 0.1
     # issued matrix work: 80 x 45 tiles, 4 disparity tiles, 16 patches, 7 K-steps, 3 MFMAs
     assert agg["mfma_view"]["issued_flops_per_launch"] == 80 * 45 * 4 * 16 * 7 * 3 * 16384
 
@@ -68,14 +70,36 @@ def test_lds_traffic_of_the_tiles():
 
 def test_kernel_rooflines_with_the_selection_folded_in():
     """With the selection folded into the reference aggregation there is no select
-    kernel to report, and each aggregation launch reads 4 B per entry and writes maps."""
+    kernel to report, each aggregation launch is reported on its own, and each reads
+    4 B per entry and writes maps."""
     class P:
         agg_radius = 5
         block_radius = 3
     st = {"cost_volume": 0.1, "aggregate_ref": 0.25, "aggregate_tar": 0.24}
     k = bench.kernel_rooflines(st, 1280, 720, 64, P, fused=True)
-    assert set(k) == {"cost_volume", "aggregate"}
+    assert set(k) == {"cost_volume", "aggregate_ref", "aggregate_tar"}
     n = 1280 * 720 * 64
-    ms = 0.5 * (0.25 + 0.24)
-    assert abs(k["aggregate"]["hbm_view"]["achieved_gbs"] - 4 * n / (ms * 1e-3) / 1e9) < 0.1
-    assert k["aggregate"]["flops_per_launch"] == (2 * 121 + 2) * n
+    for key, ms in (("aggregate_ref", 0.25), ("aggregate_tar", 0.24)):
+        assert abs(k[key]["hbm_view"]["achieved_gbs"] - 4 * n / (ms * 1e-3) / 1e9) < 0.1
+        assert k[key]["flops_per_launch"] == (2 * 121 + 2) * n
+        assert abs(k[key]["achieved"] - (2 * 121 + 2) * n / (ms * 1e-3) / 1e12) < 0.01
+
+
+def test_adjoint_flop_count_by_hand():
+    """adjoint_flops on a 3 x 4 map, window radius 1 (m = 9), block radius 1 (n = 9):
+    distinct selected disparities of the Omega pixels in each 3 x 3 window, counted by
+    hand."""
+    import torch
+
+    class P:
+        agg_radius = 1
+        block_radius = 1
+        D = 8
+    d = torch.tensor([[1, 1, 2, 9], [3, 1, 2, 2], [5, 5, 5, 5]], dtype=torch.int32)
+    mask = torch.tensor([[1, 1, 1, 1], [1, 0, 1, 1], [0, 0, 0, 1]], dtype=torch.uint8)
+    # Omega: (0,0)=1 (0,1)=1 (0,2)=2 (1,0)=3 (1,2)=2 (1,3)=2 (2,3)=5; (0,3) has d = 9 >= D
+    # distinct Omega disparities per window (row-major over the 12 pixels)
+    per_q = [2, 3, 2, 1, 2, 3, 3, 2, 1, 2, 2, 2]
+    fl, n_qd = bench.adjoint_flops(torch, d, mask, P)
+    assert n_qd == sum(per_q)
+    assert fl == n_qd * 4 * 9 + 7 * 4 * 9 + 12 * 2 * 9
