@@ -306,12 +306,13 @@ def adjoint_flops(torch, disp, mask, prm):
     K = 2 * A + 1
     n = (2 * prm.block_radius + 1) ** 2
     m = K * K
-    dm = torch.where(mask.bool() & (disp >= 0) & (disp < prm.D), disp, torch.full_like(disp, -1)).float()
+    om = mask.bool() & (disp >= 0) & (disp < prm.D)   # Omega: out-of-range disparities are not in the loss
+    dm = torch.where(om, disp, torch.full_like(disp, -1)).float()
     win = F.unfold(F.pad(dm[None, None], (A, A, A, A), value=-1.0), K)[0]  # [m, H*W]
     srt, _ = torch.sort(win, dim=0)
     distinct = (srt[0] >= 0).sum() + ((srt[1:] != srt[:-1]) & (srt[1:] >= 0)).sum()
     n_qd = int(distinct)
-    omega = int(mask.bool().sum())
+    omega = int(om.sum())
     return n_qd * 4 * n + omega * 4 * m + H * W * 2 * m, n_qd
 
 
