@@ -506,6 +506,19 @@ def cpu_baseline(workload, case, rows: int, pool_rows: int):
                                "sample": f"rows {v0}..{v0 + rows - 1}, {t1:.1f} s"}}
 
 
+def accuracy_block(case, cam, xyz):
+    """Sec. III's accuracy measurement on the frame's 3-D points (accuracy.bump_study):
+    per synthetic bump, the plane through the region's four corners and the heights of
+    random bump points above it, against the same on the generator's ground truth."""
+    import numpy as np
+    from paper_1807_07433_amd import accuracy as ACC
+    r = ACC.bump_study(xyz.cpu().numpy().astype(np.float64), case.pair.disp_gt, cam, case.pair.extra["bumps"],
+                       np.random.default_rng(0))
+    r["method"] = ("plane through the 3-D points at the 4 corners of a 61x61 region around each bump; "
+                   "40 random points on the bump's upper half; |measured - true height| in mm")
+    return r
+
+
 def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_full):
     """The restricted search of Sec. IV on the same frame: calculated disparities of
     both views (rsv_cost_argmax on the joint volume's views), then the target argmax
@@ -576,7 +589,9 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
         t_ca = st["cost_volume"] + st["cost_argmax"] + st["aggregate_tar"] + st["aggregate_ref"]
         frame = sum(st.values())
         acc = accuracy(dfin.cpu().numpy().astype(np.float64), sel["valid"].cpu().numpy().astype(bool))
+        mm = accuracy_block(case, cam, xyz) if case.pair.extra.get("bumps") else {}
         out["radii"][str(radius)] = {
+            "bump_mean_abs_err_mm": mm.get("mean_abs_err_mm"),
             "window": min(2 * radius + 1, D),
             "stage_ms": {k: round(v, 5) for k, v in st.items()},
             "value": round(mde_per_s(W, H, D, t_ca * 1e-3), 2), "unit": "Mpix·disp/s",
@@ -796,6 +811,8 @@ def main():
         out["batched"] = bench_batch(a, rsv, torch)
     if not a.no_diff:
         out["differentiable"] = bench_diff(a, rsv, torch)
+    if case.pair.extra.get("bumps"):
+        out["accuracy"] = accuracy_block(case, cam, xyz)
     if not a.no_restricted and fused:
         out["restricted"] = bench_restricted(a, rsv, torch, case, L, R, cam, sel, dfin, stage_ms)
     if not a.no_sweep and a.workload == "road1280_d64":

@@ -159,3 +159,19 @@ def test_road1280_d64_every_pixel(rsv_gpu):
     edge = agree & ~((ref_d > 0) & (ref_d < D - 1))
     assert np.array_equal(gsub[edge], ref_sub[edge].astype(np.float32))
     P.check_subpixel_range("disp_sub (whole frame)", gsub, gd)
+
+
+def test_road1280_d64_reconstruction_accuracy_mm(rsv_gpu):
+    """Sec. III's accuracy measurement on the GPU's 3-D points of the 1280x720 road
+    (accuracy.bump_study): every bump region in the image is measured, and the mean
+    height error stays at the millimetre level (the oracle's own maps give 2.8 mm)."""
+    from paper_1807_07433_amd import accuracy as ACC
+    rsv = rsv_gpu
+    case = synth.road1280_d64()
+    out = rsv.reconstruct(_gpu(case.pair.left), _gpu(case.pair.right), case.plane, _camera(case), case.params,
+                          tar_volume=False, ref_volume=False)
+    r = ACC.bump_study(P.to_np(out["xyz"]).astype(np.float64), case.pair.disp_gt, _camera(case),
+                       case.pair.extra["bumps"], np.random.default_rng(0))
+    _say(f"[accuracy] {r}")
+    assert r["bumps_used"] >= 6
+    assert r["mean_abs_err_mm"] < 4.0
