@@ -11,8 +11,10 @@ no arithmetic of the method).
   oracle.adjoint  loss of the differentiable form and its exact gradient
   oracle.restricted  restricted-search aggregation (Sec. IV): windows around the
                   unaggregated WTA, windowed WTA, the rest of the full path
+  oracle.plane    road-plane estimation (Sec. II-A): RANSAC over given draws,
+                  least-squares refit, roll angle
 
 Pins (tests marked "not gpu") tie every function to facts fixed by the paper or
 by mathematics rather than to itself; see tests/test_oracle_*.py.
 """
-from . import stereo, adjoint, restricted  # noqa: F401
+from . import stereo, adjoint, restricted, plane  # noqa: F401
