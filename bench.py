@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-restricted", action="store_true", help="skip the restricted search (Sec. IV)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the block / window radius sweep")
     ap.add_argument("--sweep-steps", type=int, default=5)
+    ap.add_argument("--no-plane", action="store_true", help="skip the road-plane fit (Sec. II-A)")
+    ap.add_argument("--plane-draws", type=int, default=512)
     ap.add_argument("--cpu-pool-rows", type=int, default=24, help="rows per worker in the pooled oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy one 512 MiB buffer (reads 512 MiB, writes "
@@ -666,6 +668,54 @@ def bench_sweep(a, rsv, torch, case, L, R):
             "time_ratio_agg_radius_4_over_2_at_block_radius_3": round(g(3, 4) / g(3, 2), 3)}
 
 
+PEAK_FP64_TFS = 78.6   # MI355X FP64 vector, TFLOP/s
+
+
+def bench_plane(a, rsv, torch, disp_final, valid):
+    """Road-plane fit of Sec. II-A (rsv_plane_ransac) on the frame's post-processed
+    disparities: K RANSAC draws over the valid pixels, threshold 0.5 px.  The four
+    launches are timed together with HIP events; the roofline entry prices them at the
+    scoring's algorithmic FP64 work, 5 FLOP (two FMAs and a subtraction) per valid
+    pixel and hypothesis, against the FP64 vector peak.  The oracle's time per
+    hypothesis (one process) is measured on 8 of the same draws."""
+    import numpy as np
+    import synth
+    H, W = disp_final.shape
+    K = a.plane_draws
+    v_np = valid.cpu().numpy()
+    samples = torch.from_numpy(synth.ransac_draws(v_np, K, np.random.default_rng(3))).to(disp_final.device)
+    ws = torch.empty((rsv.load().rsv_plane_ransac_workspace_bytes(K) + 7) // 8, dtype=torch.float64,
+                     device=disp_final.device)
+    for _ in range(max(1, a.warmup)):
+        res = rsv.plane_ransac(disp_final, valid, samples, 0.5, workspace=ws)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(a.steps):
+        res = rsv.plane_ransac(disp_final, valid, samples, 0.5, workspace=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / a.steps
+    n_valid = int(v_np.astype(bool).sum())
+    flops = 5.0 * n_valid * K
+    achieved = flops / (ms * 1e-3) / 1e12
+    pl = res["plane"].cpu().numpy()
+    out = {"workload": f"{W}x{H} post-processed disparities, {n_valid} valid, K={K} draws, threshold 0.5 px",
+           "ms": round(ms, 5), "plane": [float(x) for x in pl], "roll_rad": float(np.arctan(-pl[2] / pl[1])),
+           "best": [int(x) for x in res["best"].cpu()],
+           "roofline": {"bound": "alu", "kernel": "rsv_plane_ransac (4 launches, scoring dominant)",
+                        "achieved": round(achieved, 3), "peak": PEAK_FP64_TFS, "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_FP64_TFS, 4), "traffic": None}}
+    if not a.no_cpu_baseline:
+        from oracle import plane as PL
+        d64 = disp_final.cpu().numpy().astype(np.float64)
+        sub = samples[:8].cpu().numpy()
+        t0 = time.perf_counter()
+        PL.ransac_plane(d64, v_np.astype(bool), sub, 0.5)
+        out["oracle_s_per_hypothesis"] = round((time.perf_counter() - t0) / len(sub), 5)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -815,6 +865,8 @@ def main():
         out["accuracy"] = accuracy_block(case, cam, xyz)
     if not a.no_restricted and fused:
         out["restricted"] = bench_restricted(a, rsv, torch, case, L, R, cam, sel, dfin, stage_ms)
+    if not a.no_plane:
+        out["plane"] = bench_plane(a, rsv, torch, dfin, sel["valid"])
     if not a.no_sweep and a.workload == "road1280_d64":
         out["sweep"] = bench_sweep(a, rsv, torch, case, L, R)
     if not a.no_cpu_baseline:

@@ -249,6 +249,31 @@ int rsv_aggregate_restricted_select(const float* cost, int64_t plane_stride, int
                                     int32_t radius, const int32_t* disp_tar, int32_t* disp_ref,
                                     float* disp_sub, uint8_t* valid, void* stream);
 
+/* Road-plane estimation (Sec. II-A): the plane of disparities d = a0 + a1 v + a2 u
+ * that the warp of Eq. 2 uses (a0, a1 as in Eq. 2; a2 the term of the roll-fitted
+ * plane), fitted by least squares inside RANSAC to the valid pixels of a disparity
+ * map (e.g. the previous frame's post-processed disparities).
+ *   disp     float32 [H][W], read; valid uint8 [H][W] (nonzero = a correspondence)
+ *   samples  int32 [K][3], the random draws: linear pixel indices v*W + u, 1 <= K <=
+ *            RSV_PLANE_MAX_K (drawing them is the caller's; an index out of range or
+ *            three pixels on one line of the image make the hypothesis degenerate)
+ *   threshold  inlier bound |d - (a0 + a1 v + a2 u)| <= threshold (>= 0), in FP64
+ *   plane    out, double[3] (a0, a1, a2): the least-squares plane of the inliers of
+ *            the best hypothesis (most inliers, ties to the lowest index)
+ *   counts   out, int32 [K]: inliers per hypothesis, -1 where degenerate
+ *   best     out, int32[2]: the best hypothesis and its inlier count
+ *   workspace  device, rsv_plane_ransac_workspace_bytes(K) bytes, 8-byte aligned
+ * All outputs are device memory written on the stream.  With no non-degenerate
+ * hypothesis or fewer than 3 non-collinear inliers the plane holds non-finite values.
+ * The roll angle is atan(-a2 / a1).
+ * Errors: RSV_E_NULL, RSV_E_SHAPE (H or W < 1, H*W > 2^31 - 1, K out of range),
+ * RSV_E_PARAM (threshold < 0 or NaN), RSV_E_ALIGN. */
+enum { RSV_PLANE_MAX_K = 1024 };
+size_t rsv_plane_ransac_workspace_bytes(int32_t K);
+int rsv_plane_ransac(const float* disp, const uint8_t* valid, int32_t height, int32_t width,
+                     const int32_t* samples, int32_t K, float threshold, double* plane, int32_t* counts,
+                     int32_t* best, void* workspace, void* stream);
+
 /* Post-processing (Sec. II-C) and 3-D reconstruction (Sec. II-D):
  *   disp_final = disp_sub + s(u - disp_sub, v)            (every pixel)
  *   xyz[v][u]  = (x, y, z), z = f*baseline/disp_final, x = (u-u0) z/f, y = (v-v0) z/f,

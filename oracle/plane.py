@@ -12,7 +12,8 @@ d = a0 + a1 v + a2 u (Eq. 2 with the u-term of the roll-fitted plane of Sec. II-
 RANSAC draws K hypotheses, each the plane through 3 of the points (the random draws
 are an input, so the oracle and the kernels use the same ones), keeps the hypothesis
 with the most inliers |d - a0 - a1 v - a2 u| <= threshold (ties to the lowest
-hypothesis index; hypotheses whose 3 points do not determine a plane score -1), and
+hypothesis index; hypotheses whose 3 points do not determine a plane, or that draw
+an index outside the image, score -1), and
 refits that hypothesis's inliers by least squares.  The roll angle is
 gamma = arctan(-a2 / a1) (Sec. II-A, with gamma_1 = a2 and gamma_2 = a1).
 """
@@ -59,12 +60,17 @@ def ransac_plane(disp, valid, samples, threshold):
     counts = np.full(len(samples), -1, np.int64)
     planes = []
     for k, s in enumerate(samples):
+        if np.any((s < 0) | (s >= H * W)):     # a draw outside the image: no hypothesis
+            planes.append(None)
+            continue
         sv, su = s // W, s % W
         pl = plane_through_three(su, sv, disp[sv, su])
         planes.append(pl)
         if pl is not None:
             counts[k] = int(inliers(pl, pu, pv, pd, threshold).sum())
     best = int(np.argmax(counts))          # first maximum: ties to the lowest index
+    if planes[best] is None:               # every hypothesis degenerate
+        return np.full(3, np.nan), counts, best, np.zeros_like(ok)
     inl = ok & inliers(planes[best], uu, vv, disp, threshold)
     plane = least_squares_plane(uu[inl], vv[inl], disp[inl])
     return plane, counts, best, inl

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "librsv.so")
 RSV_U8, RSV_F32 = 0, 1
 RSV_MAX_D = 512
 RSV_ADJOINT_NOALLOC_MAX_PIXELS = 1 << 21
+RSV_PLANE_MAX_K = 1024
 
 STATUS = {0: "RSV_OK", -1: "RSV_E_NULL", -2: "RSV_E_SHAPE", -3: "RSV_E_PARAM",
           -4: "RSV_E_DTYPE", -5: "RSV_E_ALIGN", -6: "RSV_E_HIP", -7: "RSV_E_NOMEM"}
@@ -64,6 +65,9 @@ _SIGNATURES = {
                                                   C.c_int32, _P, _P]),
     "rsv_aggregate_restricted_select": (C.c_int, [_P, C.c_int64, C.c_int64, Image, C.POINTER(Params), _P,
                                                   C.c_int32, _P, _P, _P, _P, _P]),
+    "rsv_plane_ransac_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "rsv_plane_ransac": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_float, _P, _P, _P, _P,
+                                   _P]),
     "rsv_triangulate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, Plane, Camera, _P, _P, _P]),
     "rsv_selected_cost_sum": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "rsv_cost_adjoint_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),

@@ -297,6 +297,36 @@ def reconstruct_restricted(left: torch.Tensor, right: torch.Tensor, plane, camer
     return res
 
 
+def plane_ransac(disp: torch.Tensor, valid: torch.Tensor, samples: torch.Tensor, threshold: float,
+                 workspace: torch.Tensor | None = None) -> dict:
+    """Road-plane estimation of Sec. II-A (rsv_plane_ransac): RANSAC over the draws
+    samples [K][3] (linear pixel indices v*W + u) on the valid pixels of disp, then
+    the least-squares plane (a0, a1, a2) of d = a0 + a1 v + a2 u through the best
+    hypothesis's inliers.  Returns device tensors: plane float64 [3], counts int32 [K]
+    (-1 for degenerate draws), best int32 [2] (hypothesis, inlier count)."""
+    lib = load()
+    H, W = disp.shape
+    _contig(disp, "disp", torch.float32, (H, W))
+    _contig(valid, "valid", torch.uint8, (H, W))
+    if samples.dim() != 2 or samples.shape[1] != 3:
+        raise ValueError("samples must be [K][3]")
+    K = int(samples.shape[0])
+    _contig(samples, "samples", torch.int32, (K, 3))
+    if not 1 <= K <= _lib.RSV_PLANE_MAX_K:
+        raise ValueError(f"K = {K} outside 1..{_lib.RSV_PLANE_MAX_K}")
+    dev = disp.device
+    nbytes = lib.rsv_plane_ransac_workspace_bytes(K)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+    plane = torch.empty(3, dtype=torch.float64, device=dev)
+    counts = torch.empty(K, dtype=torch.int32, device=dev)
+    best = torch.empty(2, dtype=torch.int32, device=dev)
+    check(lib.rsv_plane_ransac(disp.data_ptr(), valid.data_ptr(), H, W, samples.data_ptr(), K,
+                               float(threshold), plane.data_ptr(), counts.data_ptr(), best.data_ptr(),
+                               workspace.data_ptr(), _stream(dev)), "rsv_plane_ransac")
+    return dict(plane=plane, counts=counts, best=best)
+
+
 def select_subpixel(agg_ref: torch.Tensor, agg_tar: torch.Tensor | None, params, want_top2: bool = False,
                     out: dict | None = None) -> dict:
     """WTA, left-right check and Eq. 12.  With agg_tar None, out["disp_tar"] must hold

@@ -12,6 +12,9 @@ Workloads (sizes in pixels, D = residual disparity search range):
   batch64_mixed    64 pairs, sizes from {640x360, 1280x720, 1920x1080}, D from {32, 64, 128};
                    NCC 7x7, bilateral 11x11.
   diff8_road1280   8 float32 pairs of the road1280_d64 kind with a perturbed starting plane.
+  plane_fit_input  a disparity map for the road-plane fit: a plane with a roll term plus
+                   N(0, noise), a fraction of gross outliers, invalid holes, and the RANSAC
+                   draws (3 distinct valid pixels each).
 """
 from __future__ import annotations
 
@@ -151,3 +154,26 @@ def small_case(height: int, width: int, D: int, block_radius: int, agg_radius: i
     params = MethodParams(D=D, block_radius=block_radius, agg_radius=agg_radius,
                           gamma_d=gamma_d, gamma_r=gamma_r)
     return _case(f"small_{height}x{width}_d{D}", scene, params, seed)
+
+
+def ransac_draws(valid: np.ndarray, n_draws: int, rng: np.random.Generator) -> np.ndarray:
+    """n_draws x 3 linear indices (v * W + u) of distinct valid pixels, int32."""
+    idx = np.flatnonzero(np.asarray(valid).ravel())
+    return np.stack([idx[rng.choice(idx.size, 3, replace=False)] for _ in range(n_draws)]).astype(np.int32)
+
+
+def plane_fit_input(height: int, width: int, seed: int, plane=(10.0, 0.15, -0.004), noise: float = 0.05,
+                    outliers: float = 0.3, holes: float = 0.1, n_draws: int = 256,
+                    base: np.ndarray | None = None):
+    """(disp float32 [H][W], valid uint8 [H][W], draws int32 [K][3]) for the road-plane
+    fit: base (0 if None) + a0 + a1 v + a2 u + N(0, noise); a fraction `outliers` of the
+    pixels replaced by U(0, max); a fraction `holes` marked invalid."""
+    rng = np.random.default_rng(seed)
+    v, u = np.mgrid[0:height, 0:width].astype(np.float64)
+    d = plane[0] + plane[1] * v + plane[2] * u + rng.normal(0.0, noise, (height, width))
+    if base is not None:
+        d = d + base
+    out = rng.random((height, width)) < outliers
+    d[out] = rng.uniform(0.0, float(d.max()), int(out.sum()))
+    valid = rng.random((height, width)) >= holes
+    return d.astype(np.float32), valid.astype(np.uint8), ransac_draws(valid, n_draws, rng)

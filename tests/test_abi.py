@@ -263,3 +263,23 @@ def test_restricted_search_validation(lib):
     assert g(A, 32 * 48, 48, _img(), C.byref(p), B, 3, Cc, Dd, None, E, None) == -1
     assert g(A, 32 * 48, 48, _img(), C.byref(_params(lr_threshold=-1)), B, 3, Cc, Dd, E, A, None) == -3
     assert g(A, 32 * 48, 48, _img(), C.byref(p), B, -2, Cc, Dd, E, A, None) == -3
+
+
+def test_plane_ransac_validation(lib):
+    """rsv_plane_ransac rejects bad arguments before launching: nulls, image and K
+    ranges, a negative or NaN threshold, misalignment; the workspace size is 3K + 9
+    doubles and 0 for K out of range."""
+    A, B, Cc, Dd, E, F, G = (FAKE + i * 4096 for i in range(7))
+    f = lib.rsv_plane_ransac
+    assert lib.rsv_plane_ransac_workspace_bytes(16) == 8 * (3 * 16 + 9)
+    assert lib.rsv_plane_ransac_workspace_bytes(0) == 0
+    assert lib.rsv_plane_ransac_workspace_bytes(1025) == 0
+    assert f(None, B, 32, 48, Cc, 16, 0.5, Dd, E, F, G, None) == -1
+    assert f(A, B, 32, 48, Cc, 16, 0.5, Dd, E, F, None, None) == -1
+    assert f(A, B, 0, 48, Cc, 16, 0.5, Dd, E, F, G, None) == -2
+    assert f(A, B, 32, 48, Cc, 0, 0.5, Dd, E, F, G, None) == -2
+    assert f(A, B, 32, 48, Cc, 1025, 0.5, Dd, E, F, G, None) == -2
+    assert f(A, B, 32, 48, Cc, 16, -0.5, Dd, E, F, G, None) == -3
+    assert f(A, B, 32, 48, Cc, 16, float("nan"), Dd, E, F, G, None) == -3
+    assert f(A + 2, B, 32, 48, Cc, 16, 0.5, Dd, E, F, G, None) == -5
+    assert f(A, B, 32, 48, Cc, 16, 0.5, Dd + 4, E, F, G, None) == -5

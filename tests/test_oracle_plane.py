@@ -49,6 +49,11 @@ def test_degenerate_draws_and_ties():
     assert counts[0] == -1 and counts[1] == counts[2] == H * W
     assert best == 1                                 # equal counts: the lowest index
     assert PL.plane_through_three([0, 1, 2], [0, 1, 2], [1, 2, 3]) is None
+    # draws outside the image are degenerate; with no hypothesis left the plane is NaN
+    plane, counts, best, inl = PL.ransac_plane(d, valid, np.array([[0, 5, H * W], [-1, 3, 40], good]), 0.1)
+    assert list(counts) == [-1, -1, H * W] and best == 2
+    plane, counts, best, inl = PL.ransac_plane(d, valid, np.array([collinear, [0, 1, H * W]]), 0.1)
+    assert list(counts) == [-1, -1] and np.isnan(plane).all() and not inl.any()
 
 
 def test_least_squares_refit_and_roll():
