@@ -7,9 +7,12 @@
  * (Sec. II-B.1, Eq. 3-5), bilateral cost aggregation (Sec. II-B.2, Eq. 8-10),
  * winner-take-all with the left-right check (Sec. II-B.3/4, Eq. 11), parabola
  * subpixel refinement (Eq. 12), post-processing (Sec. II-C) and triangulation
- * (Sec. II-D).  Two further forms sit on the same kernels: a batched, persistent,
- * fused form over many pairs of uneven size and disparity range, and the adjoint
- * of the aggregated reference cost for gradient-based refinement of the plane.
+ * (Sec. II-D).  Two further forms sit on the same kernels: a batched form (one
+ * graph launch over many pairs of uneven size and disparity range, no aggregated
+ * volume in memory), and the adjoint of the aggregated reference cost for
+ * gradient-based refinement of the plane.  Also: the restricted search of Sec. IV
+ * (aggregation only around a calculated disparity) and the road-plane fit of
+ * Sec. II-A (RANSAC with a least-squares refit).
  *
  * Conventions for every call
  *   - All array pointers are DEVICE pointers (hipMalloc'd or torch tensors) unless
@@ -324,13 +327,18 @@ void rsv_tuning_default(rsv_tuning* t);
 /* Builds a plan for the whole batch: device workspace for every pair's warped image,
  * joint cost volume (rsv_cost_volume_joint's layout, row stride W + D - 1 rounded up
  * to 64) and selection state, two work lists, and a hipGraph of
- *   [reset queue counters] -> [warp every pair] -> [cost kernel] -> [persistent
- *   aggregate + winner-take-all kernel] -> [per-pixel tail].
+ *   [reset queue counters] -> [warp every pair] -> [cost kernel] -> [tile kernel]
+ *   -> [per-pixel tail].
  * The cost kernel runs ZNCC (the arithmetic of rsv_cost_volume_joint), persistent
- * over a work queue or one workgroup per tile (see rsv_tuning).  The second kernel
- * pulls work items from atomic counters and runs bilateral aggregation (that of
- * rsv_aggregate on the two views) with winner-take-all fused in, writing no
- * aggregated volume.  The tail runs the left-right check, Eq. 12, post-processing
+ * over a work queue or one workgroup per tile (see rsv_tuning); with per-pair
+ * launches the graph runs each pair's cost launch and then its tile launch.  Where
+ * agg_radius <= 5 and W >= 4 the tile kernel takes one workgroup per (pair, 16 x 16
+ * block, view), the LDS-loaded aggregation tile of rsv_aggregate_select (reference
+ * view: winner, its value and neighbours) or of rsv_aggregate_argmax (target view);
+ * otherwise a persistent kernel pulls (pair, block, view) items from per-XCD atomic
+ * counters and runs rsv_aggregate's tile with winner-take-all fused in.  No
+ * aggregated volume is written.  The tail runs the left-right check, Eq. 12,
+ * post-processing
  * and triangulation (those of rsv_select_subpixel and rsv_triangulate).  Every
  * output equals the plain path's bit for bit.
  *   pairs, n   the batch (host array, copied)

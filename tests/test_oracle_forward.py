@@ -17,7 +17,8 @@ RNG = np.random.default_rng(12345)
 
 # --------------------------------------------------------------------- warp (Sec. II-A)
 def test_warp_moves_points_to_the_right():
-    """'each point on row v ... is shifted alpha0+alpha1*v-delta pixels to the right'."""
+    """Sec. II-A: the warp moves every point of row v to the right by the shift
+    alpha0 + alpha1 v - delta."""
     R = np.zeros((3, 30))
     R[:, 10] = 100.0
     out = S.warp(R, (5.0, 0.0, 0.0, 2.0))  # s = 3
