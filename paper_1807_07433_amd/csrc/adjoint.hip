@@ -23,6 +23,7 @@
 // edge pixel only at the flush.  The warped-image gradient goes through the transpose
 // of the interpolation into the right image, and its shift derivative
 // -(I1 - I0) (1, v, u) into the plane gradient.
+#include <climits>
 #include <mutex>
 
 #include "bilateral_math.hpp"
@@ -31,9 +32,9 @@
 namespace rsv {
 
 constexpr int kAdjTX = 16;
-constexpr int kAdjTY = 8;
+constexpr int kAdjTY = 16;
 constexpr int kAdjThreads = kAdjTX * kAdjTY;
-constexpr int kAdjDChunk = 64;
+constexpr int kAdjSlots = 16;  // disparities gathered per pass over a pixel's window
 constexpr int kAdjMaxD = 256;
 
 __global__ void adjoint_zero_kernel(float* __restrict__ a, float* __restrict__ b, int64_t n,
@@ -81,9 +82,12 @@ __global__ __launch_bounds__(256) void zinv_kernel(const float* __restrict__ g, 
 
 struct AdjLayout {
   int hl, ltw, lth, wtw, wth, ztw, zth, tsw;
-  size_t off_red, off_ts, off_lt, off_wt, off_zt, off_dt, off_gl, off_gw, off_col, bytes;
+  size_t off_ts, off_lt, off_wt, off_zt, off_dt, off_gl, off_gw, off_col, bytes;
 };
 
+// off_col holds, in turn, the row pass of the window disparity range (2 x zth x TX
+// ints), the gathered G(q, .) (kAdjSlots x threads floats) and the block reduction
+// (4 x threads doubles).
 __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
   AdjLayout L;
   L.hl = R > A ? R : A;
@@ -95,9 +99,7 @@ __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
   L.zth = kAdjTY + 2 * A;
   L.tsw = kAdjTX + D - 1;  // target block centres per tile row
   size_t o = 0;
-  L.off_red = o;  // 8-byte items first
-  o += sizeof(double) * 4 * kAdjThreads;
-  L.off_ts = o;
+  L.off_ts = o;  // 8-byte items first
   o += sizeof(float2) * L.tsw * kAdjTY;
   L.off_lt = o;
   o += sizeof(float) * L.ltw * L.lth;
@@ -111,8 +113,13 @@ __host__ __device__ inline AdjLayout adj_layout(int R, int A, int D) {
   o += sizeof(float) * L.ltw * L.lth;
   L.off_gw = o;
   o += sizeof(float) * L.wtw * L.wth;
+  o = (o + 7) & ~size_t(7);
   L.off_col = o;
-  o += sizeof(float) * kAdjDChunk * kAdjThreads;
+  size_t col = sizeof(float) * kAdjSlots * kAdjThreads;
+  const size_t red = sizeof(double) * 4 * kAdjThreads, rng = sizeof(int) * 2 * L.zth * kAdjTX;
+  col = col > red ? col : red;
+  col = col > rng ? col : rng;
+  o += col;
   L.bytes = o;
   return L;
 }
@@ -129,7 +136,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   constexpr int KA = 2 * A + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   const AdjLayout Ly = adj_layout(R, A, D);
-  double* red = reinterpret_cast<double*>(smem + Ly.off_red);
   float2* ts = reinterpret_cast<float2*>(smem + Ly.off_ts);
   float* lt = reinterpret_cast<float*>(smem + Ly.off_lt);
   float* wt = reinterpret_cast<float*>(smem + Ly.off_wt);
@@ -138,6 +144,9 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
   float* gl = reinterpret_cast<float*>(smem + Ly.off_gl);
   float* gw = reinterpret_cast<float*>(smem + Ly.off_gw);
   float* col = reinterpret_cast<float*>(smem + Ly.off_col);
+  int* rmn = reinterpret_cast<int*>(smem + Ly.off_col);
+  int* rmx = rmn + Ly.zth * kAdjTX;
+  double* red = reinterpret_cast<double*>(smem + Ly.off_col);
 
   const int tid = threadIdx.x;
   const int tx = tid % kAdjTX, ty = tid / kAdjTX;
@@ -190,69 +199,60 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
     const bool ok = sqrt(srr / N) >= static_cast<double>(sigma_min);
     ts[i] = make_float2(static_cast<float>(S / N), ok ? static_cast<float>(1.0 / sqrt(srr)) : 0.f);
   }
+  // Range of the Omega disparities in each pixel's window, row pass (columns tx .. tx + 2A
+  // of every Omega tile row): the gathers below take kAdjSlots disparities at a time.
+  for (int i = tid; i < Ly.zth * kAdjTX; i += kAdjThreads) {
+    const int r = i / kAdjTX, c = i - r * kAdjTX;
+    int mn = INT_MAX, mx = -1;
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+      const int dp = dt[r * Ly.ztw + c + k];
+      if (dp >= 0) {
+        mn = min(mn, dp);
+        mx = max(mx, dp);
+      }
+    }
+    rmn[i] = mn;
+    rmx[i] = mx;
+  }
 
-  // Left block of q (clamp-to-edge reads), centred, and its statistics.
-  float lc[K][K];
+  // Left block of q (clamp-to-edge reads) and its statistics; its centred values are
+  // read back from the tile (minus the mean) where needed.
   double S = 0.0, Q = 0.0;
+  const float* lb0 = lt + (ty + hl - R) * Ly.ltw + tx + hl - R;
 #pragma unroll
   for (int j = 0; j < K; ++j)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float x = lt[(ty + hl - R + j) * Ly.ltw + tx + hl - R + k];
-      lc[j][k] = x;
+      const float x = lb0[j * Ly.ltw + k];
       S += x;
       Q = fma(static_cast<double>(x), static_cast<double>(x), Q);
     }
   const double sll = fmax(Q - S * S / N, 0.0);
   const bool okl = sqrt(sll / N) >= static_cast<double>(sigma_min);
   const float mul = static_cast<float>(S / N);
-#pragma unroll
-  for (int j = 0; j < K; ++j)
-#pragma unroll
-    for (int k = 0; k < K; ++k) lc[j][k] -= mul;
   const float inv_l = okl ? static_cast<float>(1.0 / sqrt(sll)) : 0.f;
   const float gq = lt[(ty + hl) * Ly.ltw + tx + hl];
+  __syncthreads();  // target statistics and the row ranges complete
 
-  // q in the role of p: A(q) at its selected disparity, the loss, and the dL/dw terms.
-  double loss_part = 0.0;
-  const int my_d = dt[(ty + A) * Ly.ztw + tx + A];
-  if (in && my_d >= 0) {
-    const float zi = zt[(ty + A) * Ly.ztw + tx + A];
-    const float* cd = cost + my_d * cps;
-    float num = 0.f;
+  int dmin = INT_MAX, dmax = -1;
 #pragma unroll
-    for (int j = 0; j < KA; ++j)
-#pragma unroll
-      for (int k = 0; k < KA; ++k) {
-        const int Y = qy + j - A, X = qx + k - A;
-        if (X >= 0 && X < W && Y >= 0 && Y < H) {
-          const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
-          num = fmaf(bilateral_weight(gx, gq, j - A, k - A, bk), cd[Y * crs + X], num);
-        }
-      }
-    const float Aq = num * zi;
-    loss_part = Aq;
-    float s = 0.f;
-#pragma unroll
-    for (int j = 0; j < KA; ++j)
-#pragma unroll
-      for (int k = 0; k < KA; ++k) {
-        const int Y = qy + j - A, X = qx + k - A;
-        if (X >= 0 && X < W && Y >= 0 && Y < H) {
-          const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
-          const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
-          const float t = (cd[Y * crs + X] - Aq) * zi * bilateral_weight_dgq(w, gx, gq, bk);
-          atomicAdd(&gl[(Y - ly0) * Ly.ltw + X - lx0], t);
-          s += t;
-        }
-      }
-    atomicAdd(&gl[(qy - ly0) * Ly.ltw + qx - lx0], -s);
+  for (int j = 0; j < KA; ++j) {
+    dmin = min(dmin, rmn[(ty + j) * kAdjTX + tx]);
+    dmax = max(dmax, rmx[(ty + j) * kAdjTX + tx]);
   }
-  __syncthreads();  // target statistics complete
+  if (!in) dmax = -1;  // no gathers outside the image
+  if (dmax < 0) dmin = 0;  // no Omega pixel in the window: one pass (for A(q) alone)
+  __syncthreads();  // the ranges' memory becomes the gather columns
 
-  // ZNCC adjoint, 64 disparities at a time.  The left-block gradient of q is the same
-  // 49 (81) positions for every d, so it stays in registers: sum_d a_d (r - mu_r) and
-  // the scalar sum_d b_d, which multiplies the centred left block once at the end.
+  const int my_d = dt[(ty + A) * Ly.ztw + tx + A];
+  const float zq = zt[(ty + A) * Ly.ztw + tx + A];
+  const float* cd = cost + (my_d >= 0 ? my_d : 0) * cps;
+  const bool has_p = in && my_d >= 0;
+  float* mycol = col + tid;
+  // ZNCC adjoint of (q, d) with weight G = dL/dc(q, d): the left-block gradient is
+  // kept in registers across disparities (sum_d a_d (r - mu_r) and the scalar
+  // sum_d b_d), the warped-block gradient goes to the LDS accumulator.
   float gacc[K][K];
 #pragma unroll
   for (int j = 0; j < K; ++j)
@@ -260,54 +260,142 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(
     for (int k = 0; k < K; ++k) gacc[j][k] = 0.f;
   float bsum = 0.f;
   const float* cq = cost + static_cast<int64_t>(qy) * crs + qx;
-  for (int d0 = 0; d0 < D; d0 += kAdjDChunk) {
-    for (int i = 0; i < kAdjDChunk; ++i) col[i * kAdjThreads + tid] = 0.f;
-    if (in) {
-#pragma unroll
-      for (int j = 0; j < KA; ++j)
-#pragma unroll
-        for (int k = 0; k < KA; ++k) {
-          const int zi = (ty + j) * Ly.ztw + tx + k;
-          const int dp = dt[zi];
-          if (dp >= d0 && dp < d0 + kAdjDChunk) {
-            const float gx = lt[(qy + j - A - ly0) * Ly.ltw + qx + k - A - lx0];
-            const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
-            col[(dp - d0) * kAdjThreads + tid] += w * zt[zi];
-          }
-        }
-    }
-    if (in && okl) {
-      const int dn = D - d0 < kAdjDChunk ? D - d0 : kAdjDChunk;
-      for (int i = 0; i < dn; ++i) {
-        const float G = col[i * kAdjThreads + tid];
-        if (G == 0.f) continue;
-        const int d = d0 + i;
-        const int tc = tx - d + (D - 1);                  // target block column in the tile
-        const float2 st = ts[ty * Ly.tsw + tc];
-        if (st.y == 0.f) continue;                        // flat target block: c == 0
-        const float c = cq[static_cast<int64_t>(d) * cps];
-        const float a = G * inv_l * st.y;
-        const float g = G * c * st.y * st.y;
-        bsum = fmaf(G * c, inv_l * inv_l, bsum);
-        const float* tb = wt + ty * Ly.wtw + tc;
-        float* gb = gw + ty * Ly.wtw + tc;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float r = tb[j * Ly.wtw + k] - st.x;
-            gacc[j][k] = fmaf(a, r, gacc[j][k]);
-            atomicAdd(&gb[j * Ly.wtw + k], fmaf(a, lc[j][k], -g * r));
-          }
-      }
-    }
-  }
-  if (in && okl) {
+  auto apply = [&](int d, float G) {
+    const int tc = tx - d + (D - 1);  // target block column in the tile
+    const float2 st = ts[ty * Ly.tsw + tc];
+    if (st.y == 0.f) return;  // flat target block: c == 0
+    const float c = cq[static_cast<int64_t>(d) * cps];
+    const float a = G * inv_l * st.y;
+    const float g = G * c * st.y * st.y;
+    bsum = fmaf(G * c, inv_l * inv_l, bsum);
+    const float* tb = wt + ty * Ly.wtw + tc;
+    float* gb = gw + ty * Ly.wtw + tc;
 #pragma unroll
     for (int j = 0; j < K; ++j)
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        atomicAdd(&gl[(ty + hl - R + j) * Ly.ltw + tx + hl - R + k], fmaf(-bsum, lc[j][k], gacc[j][k]));
+      for (int k = 0; k < K; ++k) {
+        const float r = tb[j * Ly.wtw + k] - st.x;
+        gacc[j][k] = fmaf(a, r, gacc[j][k]);
+        atomicAdd(&gb[j * Ly.wtw + k], fmaf(a, lb0[j * Ly.ltw + k] - mul, -g * r));
+      }
+  };
+
+  // One pass per kAdjSlots disparities of the window's range.  The first pass also
+  // forms A(q) at q's own disparity (q in the role of p; w(p, q) = w(q, p)) and its
+  // loss term.  G(q, d) = sum over p of w(p, q) / Z(p), p in win(q), d*(p) = d.
+  double loss_part = 0.0;
+  float Aq = 0.f;
+  for (int base = dmin, first = 1; first || base <= dmax; base += kAdjSlots, first = 0) {
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s) mycol[s * kAdjThreads] = 0.f;
+    float num = 0.f;
+    if (in) {
+#pragma unroll 1
+      for (int j = 0; j < KA; ++j)
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+          const int Y = qy + j - A, X = qx + k - A;
+          if (X >= 0 && X < W && Y >= 0 && Y < H) {
+            const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
+            const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
+            if (first && has_p) num = fmaf(w, cd[Y * crs + X], num);
+            const int zi = (ty + j) * Ly.ztw + tx + k;
+            const int ds = dt[zi] - base;
+            if (static_cast<unsigned>(ds) < static_cast<unsigned>(kAdjSlots)) mycol[ds * kAdjThreads] += w * zt[zi];
+          }
+        }
+    }
+    if (first && has_p) {
+      Aq = num * zq;
+      loss_part = Aq;
+    }
+    if (in && okl) {
+#pragma unroll 1
+      for (int s = 0; s < kAdjSlots; ++s) {
+        const float G = mycol[s * kAdjThreads];
+        if (G != 0.f && base + s < D) apply(base + s, G);
+      }
+    }
+  }
+  // dL/dw(q, p') = (c(p', d*(q)) - A(q)) / Z(q) for p' in win(q), through the guide:
+  // t(q, p') = dL/dw * dw/dg(p') goes to g(p') and -t to g(q).  The sum over p' for q
+  // is formed here; the sums over q for each p' are gathered below by the owner of p'
+  // (no LDS atomics: one float atomic per LDS address costs about one lane at a time).
+  if (has_p) {
+    float s = 0.f;
+#pragma unroll 1
+    for (int j = 0; j < KA; ++j)
+#pragma unroll
+      for (int k = 0; k < KA; ++k) {
+        const int Y = qy + j - A, X = qx + k - A;
+        if (X >= 0 && X < W && Y >= 0 && Y < H) {
+          const float gx = lt[(Y - ly0) * Ly.ltw + X - lx0];
+          const float w = bilateral_weight(gx, gq, j - A, k - A, bk);
+          s += (cd[Y * crs + X] - Aq) * zq * bilateral_weight_dgq(w, gx, gq, bk);
+        }
+      }
+    atomicAdd(&gl[(qy - ly0) * Ly.ltw + qx - lx0], -s);
+  }
+  __syncthreads();  // every pixel's gathers are done: the columns take its left-block gradient
+  // The left-block gradient of q, -bsum (l - mu_l) + gacc, goes to the left tile one
+  // block row at a time: each q writes its row j, then the owner of each position of
+  // the row band sums the (up to K) values aimed at it.
+  float* rowv = col;  // [K][threads]
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      rowv[k * kAdjThreads + tid] = (in && okl) ? fmaf(-bsum, lb0[j * Ly.ltw + k] - mul, gacc[j][k]) : 0.f;
+    __syncthreads();
+    // positions: tile rows hl - R + j + ty' (ty' = 0 .. 15), columns hl - R + c (c = 0 .. 15 + 2R)
+    constexpr int BW = kAdjTX + 2 * R;
+    for (int i = tid; i < kAdjTY * BW; i += kAdjThreads) {
+      const int qyl = i / BW, c = i - qyl * BW;  // q row in the block, tile column offset
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int qxl = c - k;  // q column in the block
+        if (qxl >= 0 && qxl < kAdjTX) acc += rowv[k * kAdjThreads + qyl * kAdjTX + qxl];
+      }
+      gl[(qyl + hl - R + j) * Ly.ltw + c + hl - R] += acc;
+    }
+    __syncthreads();
+  }
+  // per q: A(q), 1 / Z(q) (0 where q is not in Omega), d*(q), guide at q
+  float4* qinfo = reinterpret_cast<float4*>(col);
+  qinfo[tid] = make_float4(Aq, has_p ? zq : 0.f, __int_as_float(has_p ? my_d : 0), gq);
+  __syncthreads();
+  // Owner gather: position p' of the left tile adds sum over the block's q with p' in
+  // win(q) of t(q, p') (the weight and its derivative as in the scatter form).
+  for (int i = tid; i < Ly.ltw * Ly.lth; i += kAdjThreads) {
+    const int r = i / Ly.ltw, c = i - r * Ly.ltw;
+    const int Y = ly0 + r, X = lx0 + c;  // p'
+    if (X < 0 || X >= W || Y < 0 || Y >= H) continue;
+    const int j0 = max(Y - (y0 + kAdjTY - 1), -A), j1 = min(Y - y0, A);  // dy = Y - q.y
+    const int k0 = X - (x0 + kAdjTX - 1), k1 = X - x0;                    // dx = X - q.x
+    if (j0 > j1 || k0 > A || k1 < -A) continue;
+    const float gx = lt[i];
+    const float* cp = cost + static_cast<int64_t>(Y) * crs + X;
+    float acc = 0.f;
+    int dlast = -1;
+    float clast = 0.f;
+    for (int dy = j0; dy <= j1; ++dy) {
+      const float4* qrow = qinfo + (Y - dy - y0) * kAdjTX + X - x0;  // q = p' - (dy, dx): qrow[-dx]
+#pragma unroll
+      for (int dx = -A; dx <= A; ++dx) {
+        if (dx < k0 || dx > k1) continue;
+        const float4 qv = qrow[-dx];
+        if (qv.y == 0.f) continue;
+        const int dq = __float_as_int(qv.z);
+        if (dq != dlast) {
+          clast = cp[static_cast<int64_t>(dq) * cps];
+          dlast = dq;
+        }
+        const float w = bilateral_weight(gx, qv.w, dy, dx, bk);
+        acc += (clast - qv.x) * qv.y * bilateral_weight_dgq(w, gx, qv.w, bk);
+      }
+    }
+    gl[i] += acc;
   }
   __syncthreads();
 
