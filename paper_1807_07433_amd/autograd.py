@@ -2,13 +2,15 @@
 disparities, as a torch.autograd.Function whose backward is the hand-written
 adjoint kernel (rsv_cost_adjoint), plus a plane-refinement loop built on it.
 
-    loss = AggregatedZNCC.apply(left, right, theta, delta, params, disp, mask[, joint])
+    loss = AggregatedZNCC.apply(left, right, theta, delta, params, disp, mask[, joint[, plane]])
 
 theta = (a0, a1, a2) of the warp shift s = a0 + a1 v + a2 u - delta (Sec. II-A).
 The forward runs the plain path's kernels (warp, joint ZNCC volume) and sums the
 aggregation of Eq. 8 at disp(p) over mask(p) != 0 (rsv_selected_aggregate_sum); no
 aggregated volume is formed.  `joint`, if given, is the joint cost volume of this
-very (left, right, plane), e.g. the one `select` returns, and is not recomputed.
+very (left, right, plane), e.g. the one `select` returns, and is not recomputed;
+`plane`, if given, is theta's value as the host tuple (a0, a1, a2, delta), which saves
+reading theta back from the device.
 disp and mask are held fixed inside one evaluation (WTA stays exact and is re-run
 between steps by `select`).  Gradients flow to left, right (float32 images) and
 theta.
@@ -27,8 +29,9 @@ def _plane(theta: torch.Tensor, delta: float):
 
 class AggregatedZNCC(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, left, right, theta, delta, params, disp, mask, joint=None):
-        plane = _plane(theta, delta)
+    def forward(ctx, left, right, theta, delta, params, disp, mask, joint=None, plane=None):
+        if plane is None:
+            plane = _plane(theta, delta)
         if joint is None:
             joint = ops.cost_volume_joint(left, ops.warp(right, plane), params)
         cref, _ = ops.joint_views(joint, left.shape[1])
@@ -48,7 +51,7 @@ class AggregatedZNCC(torch.autograd.Function):
         s = gout.to(torch.float64)
         g_theta = (gp * s).to(device=device, dtype=dtype)
         sf = s.to(torch.float32)
-        return gl * sf, gr * sf, g_theta, None, None, None, None, None
+        return gl * sf, gr * sf, g_theta, None, None, None, None, None, None
 
 
 def select(left, right, plane, params, return_joint: bool = False):
@@ -78,10 +81,13 @@ def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, resele
     theta0: (a0, a1, a2) starting plane.  Parameters are scaled so one unit of each moves
     the shift by about one pixel across the image (a1 by 1/H, a2 by 1/W), then updated
     with Adam on -loss.  d* and Omega are re-selected every `reselect_every` steps.
+    The parameters and the optimiser live on the images' device; the plane is read
+    back once per step (the kernels take it by value).
     Returns (theta, history of losses)."""
     H, W = lefts[0].shape
-    scale = torch.tensor([1.0, 1.0 / H, 1.0 / W], dtype=torch.float64)
-    z = (torch.as_tensor(theta0, dtype=torch.float64) / scale).clone().requires_grad_(True)
+    dev = lefts[0].device
+    scale = torch.tensor([1.0, 1.0 / H, 1.0 / W], dtype=torch.float64, device=dev)
+    z = (torch.as_tensor(theta0, dtype=torch.float64, device=dev) / scale).clone().requires_grad_(True)
     opt = torch.optim.Adam([z], lr=lr)
     sel = None
     hist = []
@@ -97,12 +103,12 @@ def refine_plane(lefts, rights, theta0, delta, params, steps=50, lr=0.02, resele
         opt.zero_grad()
         objective = 0.0
         for (l, r), (d, m, joint, cnt) in zip(zip(lefts, rights), sel):
-            loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m, joint if fresh else None)
+            loss = AggregatedZNCC.apply(l, r, theta, delta, params, d, m, joint if fresh else None, plane)
             objective = objective + loss / cnt
         objective = objective / len(lefts)
         (-objective).backward()
         opt.step()
-        hist.append(float(objective.detach()))
+        hist.append(objective.detach())
         if callback:
-            callback(it, (z * scale).detach(), hist[-1])
-    return (z * scale).detach(), hist
+            callback(it, (z * scale).detach().cpu(), float(hist[-1]))
+    return (z * scale).detach().cpu(), [float(h) for h in hist]
