@@ -23,16 +23,13 @@ namespace rsv {
 // two barriers per disparity tile with a single output buffer).
 constexpr int kAggTileRows = 16;
 
-// Tile index of block b when consecutive blocks are dealt round-robin to 8 XCDs:
-// XCD x receives the contiguous (row-major) tile range [x * per + min(x, rem), ...),
-// so each XCD works through one band of the image and horizontally adjacent tiles,
-// which share halo columns, run together on the same L2.  (Enumerating the tiles in
-// strips of 4 tile rows, column by column, measured about 4% slower.)
-__device__ __forceinline__ int xcd_band_tile(int b, int ntiles) {
-  const int xcd = b & 7, k = b >> 3;
-  const int per = ntiles >> 3, rem = ntiles & 7;
-  return xcd * per + (xcd < rem ? xcd : rem) + k;
-}
+// Tiles are taken in runs of kAggXcdRun per XCD (xcd_run_item, rsv_internal.hpp): each
+// XCD works through runs of horizontally adjacent tiles, which share halo columns in its
+// L2, while the whole GPU stays on one stretch of the image (the shared cache holds its
+// rows).  At 1280x720, runs of 40 measured 1.5% faster than one band of the image per
+// XCD and equal to runs of 20; enumerating the tiles in strips of 4 tile rows, column by
+// column, measured about 4% slower than bands.
+constexpr int kAggXcdRun = 40;
 
 // agg_tile sink that writes each 16-disparity tile into the output volume: thread i
 // moves 4 consecutive pixels of one row of one plane (a wave covers 16 rows or a
@@ -75,7 +72,7 @@ __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
     int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg, int32_t* __restrict__ disp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + TY - 1) / TY;
-  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int tile = xcd_run_item<kAggXcdRun>(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * TY, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
   if constexpr (ARG) {
@@ -98,7 +95,7 @@ __global__ __launch_bounds__(1024) void aggregate_dma_kernel(
     int H, int W, int D, BilateralK bk, bool vec4, float* __restrict__ agg, int32_t* __restrict__ disp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
-  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int tile = xcd_run_item<kAggXcdRun>(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
   if constexpr (ARG) {
@@ -141,7 +138,7 @@ __global__ __launch_bounds__(1024) void aggregate_select_kernel(
     int32_t* __restrict__ dref, float* __restrict__ dsub, uint8_t* __restrict__ valid) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
-  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int tile = xcd_run_item<kAggXcdRun>(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   auto guide_at = [&](int Y, int X) { return pixel(guide, gpitch, Y, X); };
   RefQuadSink sink{D};
@@ -241,7 +238,7 @@ __global__ __launch_bounds__(1024) void aggregate_restricted_argmax_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_range[2];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
-  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int tile = xcd_run_item<kAggXcdRun>(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   int lo, hi, t_first, t_count;
   restricted_tiles(coarse, H, W, D, radius, width, by, bx, s_range, lo, hi, t_first, t_count);
@@ -263,7 +260,7 @@ __global__ __launch_bounds__(1024) void aggregate_restricted_select_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_range[2];
   const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
-  const int tile = xcd_band_tile(blockIdx.x, tiles_x * tiles_y);
+  const int tile = xcd_run_item<kAggXcdRun>(blockIdx.x, tiles_x * tiles_y);
   const int by = (tile / tiles_x) * 16, bx = (tile % tiles_x) * 16;
   int lo, hi, t_first, t_count;
   restricted_tiles(coarse, H, W, D, radius, width, by, bx, s_range, lo, hi, t_first, t_count);

@@ -341,7 +341,9 @@ __device__ __forceinline__ void batch_ref_tile(const BatchArgs& args, int4 w, un
 template <int A>
 __global__ __launch_bounds__(1024) void batch_tile_kernel(BatchArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int4 w = args.items[blockIdx.x];
+  // each XCD takes runs of 8 neighbouring tiles (they share halos in its L2), all XCDs
+  // near the same stretch of the list (one pair's volume in the shared cache)
+  const int4 w = args.items[xcd_run_item<8>(blockIdx.x, gridDim.x)];
   if (uniform(w.y) == kItemAggRef)
     batch_ref_tile<A>(args, w, smem);
   else

@@ -109,4 +109,18 @@ __device__ __forceinline__ float pixel(const T* img, int64_t pitch, int v, int u
   return static_cast<float>(as_global(img)[static_cast<int64_t>(v) * pitch + u]);
 }
 
+// Work item of block b in runs of M: blocks are dealt round-robin to the 8 XCDs, and
+// within each group of 8 M consecutive items XCD x takes the M items x M .. x M + M - 1
+// (the last partial group in order).  Neighbouring items share an L2 while the whole
+// GPU stays on one stretch of the list (one pair's volume in the shared cache).  A
+// bijection of [0, n).
+template <int M>
+__device__ __forceinline__ int xcd_run_item(int b, int n) {
+  constexpr int G = 8 * M;
+  const int g = b / G;
+  if ((g + 1) * G > n) return b;
+  const int r = b - g * G;
+  return g * G + (r & 7) * M + (r >> 3);
+}
+
 }  // namespace rsv
