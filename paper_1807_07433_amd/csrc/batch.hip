@@ -61,9 +61,6 @@ struct PairDev {
   float* joint;  // joint cost volume [D][H][jrow]: C_L and C_R are its views
   int64_t jrow;
   int32_t* ref_arg;
-  float* ref_best;
-  float* ref_am;
-  float* ref_ap;
   int32_t* tar_arg;
   int32_t* disp_ref;
   int32_t* disp_tar;
@@ -270,11 +267,9 @@ __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsig
     const int Y = by + (q >> 4), X = bx + (q & 15);
     if (Y < H && X < W) {
       const int64_t i = static_cast<int64_t>(Y) * W + X;
-      if (full) {
+      if (full) {  // the winner and Eq. 12 on it (the left-right check waits for the tail)
         uniform(pd->ref_arg)[i] = st->arg[q];
-        uniform(pd->ref_best)[i] = st->best[q];
-        uniform(pd->ref_am)[i] = st->am[q];
-        uniform(pd->ref_ap)[i] = st->ap[q];
+        uniform(pd->disp_sub)[i] = parabola(st->arg[q], st->best[q], st->am[q], st->ap[q], D);
       } else {
         uniform(pd->tar_arg)[i] = st->arg[q];
       }
@@ -325,10 +320,8 @@ __device__ __forceinline__ void batch_ref_tile(const BatchArgs& args, int4 w, un
     const int Y = by + (q >> 4), X = bx + (q & 15);
     if (Y < H && X < W) {
       const int64_t i = static_cast<int64_t>(Y) * W + X;
-      uniform(pd->ref_arg)[i] = sink.arg;
-      uniform(pd->ref_best)[i] = sink.best;
-      uniform(pd->ref_am)[i] = sink.am;
-      uniform(pd->ref_ap)[i] = sink.ap;
+      uniform(pd->ref_arg)[i] = sink.arg;  // the winner and Eq. 12 on it
+      uniform(pd->disp_sub)[i] = parabola(sink.arg, sink.best, sink.am, sink.ap, D);
     }
   }
 }
@@ -350,7 +343,8 @@ __global__ __launch_bounds__(1024) void batch_tile_kernel(BatchArgs args) {
     batch_tar_tile<A>(args, w, smem);
 }
 
-// Left-right check, Eq. 12, post-processing and 3-D points for every pixel of every pair.
+// Left-right check, post-processing and 3-D points for every pixel of every pair (the
+// reference tiles wrote the winner and its Eq. 12 refinement).
 __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, int tau) {
   const PairDev P = pairs[blockIdx.y];
   const int64_t n = static_cast<int64_t>(P.H) * P.W;
@@ -360,10 +354,9 @@ __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, i
     const int arg = P.ref_arg[i];
     const int x = u - arg;
     const bool ok = (x >= 0) && (abs(arg - P.tar_arg[static_cast<int64_t>(v) * P.W + (x < 0 ? 0 : x)]) <= tau);
-    const float ds = parabola(arg, P.ref_best[i], P.ref_am[i], P.ref_ap[i], P.D);
+    const float ds = P.disp_sub[i];
     if (P.disp_ref) P.disp_ref[i] = arg;
     if (P.disp_tar) P.disp_tar[i] = P.tar_arg[i];
-    P.disp_sub[i] = ds;
     P.valid[i] = ok ? 1 : 0;
     postprocess_point(ds, ok, u, v, P.plane, P.cam, P.disp_final ? P.disp_final + i : nullptr,
                       P.xyz ? P.xyz + 3 * i : nullptr);
@@ -528,7 +521,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     off_joint[i] = ws_bytes;
     ws_bytes = align(ws_bytes + sizeof(float) * static_cast<size_t>(D) * H * jrows[i]);
     off_maps[i] = ws_bytes;
-    ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float) * 4));  // + warped image
+    ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float)));  // winners, warped image
     max_pixels = std::max<int>(max_pixels, static_cast<int>(N));
     PairDev& P = pd[i];
     P.left = static_cast<const uint8_t*>(q.left.data);
@@ -550,9 +543,10 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.disp_final = q.disp_final;
     P.xyz = q.xyz;
   }
-  // agg items: per pair, the reference tiles then the target tiles, row-major, so
-  // each queue's stretch of the list is a band of neighbouring tiles of one volume
-  // (one tile per cost item when the cost kernel runs one workgroup per item)
+  // agg items: per pair, row by row of tiles, the reference tiles then the target
+  // tiles of the row, so both views' reads of the same rows of a pair's joint volume
+  // come close together (49.9 instead of 50.9 ms per 64-pair batch with one view after
+  // the other); one tile per cost item when the cost kernel runs one workgroup per item
   const bool grid_cost = tn.cost_blocks_per_cu < 0 || tn.per_pair_launches != 0;
   const int cost_tiles = grid_cost ? 1 : tn.cost_tiles_per_item;
   // per pair (in list order): its ranges of the cost and tile lists
@@ -564,8 +558,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     for (int b = 0; b < P.nbands; ++b)
       for (int ct = 0; ct < P.ncol_tiles; ct += cost_tiles)
         cost_items.push_back(make_int4(i, kItemCost | (cost_tiles << 8), b, ct));
-    for (int kind : {kItemAggRef, kItemAggTar})
-      for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
+    for (int ty = 0; ty < (P.H + 15) / 16; ++ty)
+      for (int kind : {kItemAggRef, kItemAggTar})
         for (int tx = 0; tx < P.tiles_x; ++tx) {
           // tiles go to the tile kernels when the LDS-loaded tile applies, else to the
           // persistent kernel
@@ -626,10 +620,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     unsigned char* m = base + o_ws + off_maps[i];
     P.ref_arg = reinterpret_cast<int32_t*>(m);
     P.tar_arg = P.ref_arg + N;
-    P.ref_best = reinterpret_cast<float*>(P.tar_arg + N);
-    P.ref_am = P.ref_best + N;
-    P.ref_ap = P.ref_am + N;
-    P.warped = P.ref_ap + N;
+    P.warped = reinterpret_cast<float*>(P.tar_arg + N);
   }
   auto fail = [&](hipError_t err) {
     set_hip_error(err);
