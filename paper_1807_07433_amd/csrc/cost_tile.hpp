@@ -13,7 +13,7 @@
 // The warped tile is stored minus 128 (kWarpShift): the centred left values sum to
 // zero, so the dot product is unchanged while its FP32 terms stay small.  Entries
 // whose target block is nearly flat (std-dev below 1 grey level, see zncc_math.hpp)
-// are recomputed exactly in FP64 from the images, since there the FP32 sum's
+// are recomputed exactly in FP64 from the tiles, since there the FP32 sum's
 // rounding, divided by a small e_r, could reach 1e-4.  Its row
 // stride is a compile-time constant so the column reads use immediate offsets.
 #pragma once
@@ -155,6 +155,22 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
     }
     return static_cast<float>(num * (static_cast<double>(lb.inv) * static_cast<double>(inv_r)));
   };
+  // Blocks of 3x3 and 5x5 meet nearly flat target blocks far more often (a few per
+  // thousand tiles of the road frame, each costing the whole tile a pass over d), so
+  // there the same sum is unrolled, reads the warped tile (minus 128: the shift drops
+  // out, the left factors summing to zero) and takes S_l once per thread.
+  auto exact_small = [&](int d, float inv_r, double S) -> float {
+    const float* lb0 = lt + ty * ltw + tx;
+    double num = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double l = fma(static_cast<double>(K * K), static_cast<double>(lb0[j * ltw + k]), -S);
+        num = fma(l, static_cast<double>(wrow[j * wtw + k - d]), num);
+      }
+    return static_cast<float>(num * (static_cast<double>(lb.inv) * static_cast<double>(inv_r)));
+  };
 
   float win[K][K];  // ring: window column k at step d0 + t lives in slot (k - t) mod K
 #pragma unroll
@@ -190,12 +206,24 @@ __device__ __forceinline__ void cost_tile(const TL* __restrict__ left, int64_t l
       }
     }
   }
-  if (*flat) {  // uniform; never taken on textured images
+  if (*flat) {  // uniform; never taken on textured images at 7x7 and larger blocks
+    double S = 0.0;
+    if constexpr (R <= 2) {
+      const float* lb0 = lt + ty * ltw + tx;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) S += static_cast<double>(lb0[j * ltw + k]);
+    }
 #pragma unroll 1
     for (int d = 0; d < D; ++d) {
       const float inv_r = irow[-d];
       if (!(inv_r < 0.f)) continue;
-      const float c = exact(d, -inv_r);
+      float c;
+      if constexpr (R <= 2)
+        c = exact_small(d, -inv_r, S);
+      else
+        c = exact(d, -inv_r);
       if (ref_ok) to_global(cost_ref + d * ref_plane)[roff] = c;
       if constexpr (TAR) {
         const int64_t pd = d * plane;
