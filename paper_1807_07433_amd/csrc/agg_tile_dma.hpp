@@ -1,44 +1,48 @@
 // The aggregation tile of agg_tile.hpp with the cost tiles brought into LDS by
-// direct global-to-LDS loads (global_load_lds_dwordx4), two disparity tiles ahead.
-// Same weights, same fp16 split of the same floats, same MFMA sequence per patch,
-// so it produces the same aggregated floats as agg_tile.
+// direct global-to-LDS loads (global_load_lds_dwordx4).  Same weights, same fp16
+// split of the same floats, same MFMA sequence per patch, so it produces the same
+// aggregated floats as agg_tile.
 //
 // Register staging holds only one tile in flight, and at the aggregation's rate a
-// disparity tile's loads take longer than its MFMAs; these loads need no registers,
-// so three buffers rotate in LDS:
-//     raw[2]   fp32 cost tiles as loaded (16 B per 4-column chunk, item order)
-//     hi / lo  fp16 planes of the tile the MFMAs read
+// disparity tile's loads take longer than its MFMAs; these loads need no registers.
+// LDS holds
+//     raw      the fp32 cost tile as loaded (16 B per 4-column chunk, item order)
+//     hl[2]    two pairs of fp16 hi / lo planes: the MFMAs read one while the next
+//              tile is converted into the other
 //     out      the transposed output tile
-// Iteration t:
-//     MFMAs(t) -> barrier -> output(t), wait for tile t+1's loads, convert
-//     raw(t+1) -> hi / lo -> barrier -> sink(t), issue tile t+3's loads into the
-//     raw buffer just converted
-// so the loads of tiles t+2 and t+3 are in flight during tile t+1's MFMAs.
+// Every thread converts exactly the chunks its own loads brought in, so a thread
+// needs no barrier between its loads landing and its conversion, nor between its
+// conversion and reloading its raw chunks.  Iteration t:
+//     MFMAs(t) from hl[t % 2], with this thread's part of tile t+1 converted from
+//     raw into hl[(t+1) % 2] between the last K-steps (its loads waited for just
+//     before) -> tile t+2's loads into raw -> barrier -> output(t) -> barrier ->
+//     sink(t)
+// so the conversion runs beside the matrix pipe instead of in a phase of its own,
+// and tile t+2's loads are in flight during the output, the sink and the first
+// K-steps of tile t+1.
 //
-// The loads are issued with inline assembly and waited for by hand: the waits are
-// "at most n vector-memory operations outstanding", where n is the number of loads
-// this wave issues per tile, so everything older (the previous tile's loads and the
-// sink's stores) has completed.  Loads complete in order, and every wave issues the
-// same number of loads for every tile: lanes whose chunk has no data (rows outside
-// the image, disparities >= D) load a valid address anyway and are masked when
-// converting; lanes past the item list are masked identically for every tile.
-// Border chunks load the in-row chunk [Xc, Xc + 3], Xc = clamp(X, 0, W - 4), and
-// the conversion picks their columns from it.  Needs W >= 4.  The cost volume is
-// read as cost[d * cps + Y * crs + X], as in agg_tile.
+// The loads are issued with inline assembly and waited for by hand ("no vector-memory
+// operations outstanding": the wave's only loads in flight at that point are the
+// ones being waited for, plus any stores of the previous sink).  Lanes whose chunk has
+// no data (rows outside the image, disparities >= D) load a valid address anyway and
+// are masked when converting; lanes past the item list issue nothing.  Border chunks
+// load the in-row chunk [Xc, Xc + 3], Xc = clamp(X, 0, W - 4), and the conversion
+// picks their columns from it.  Needs W >= 4.  The cost volume is read as
+// cost[d * cps + Y * crs + X], as in agg_tile.
 #pragma once
 
 #include "agg_tile.hpp"
 
 namespace rsv {
 
-// LDS layout: out | raw0 | raw1 | hi | lo | guide tile | spatial table.  The last two
-// are read only by the weight computation, before the first sink call; from then on
-// a sink may use the LDS from agg_tile_dma_spare_offset on.
+// LDS layout: out | raw | hi0 | lo0 | hi1 | lo1 | guide tile | spatial table.  The
+// last two are read only by the weight computation, before the first sink call; from
+// then on a sink may use the LDS from agg_tile_dma_spare_offset on.
 template <int A>
 __host__ __device__ constexpr size_t agg_tile_dma_spare_offset() {
   using G = AggGeo<A, 16>;
-  return sizeof(float) * 16 * G::OST + 2 /*raw*/ * 16 * G::NCH * 16 /*B per chunk*/ +
-         2 /*hi,lo*/ * 16 * G::PLANE * sizeof(_Float16);
+  return sizeof(float) * 16 * G::OST + 16 * G::NCH * 16 /*raw: B per chunk*/ +
+         2 /*buffers*/ * 2 /*hi,lo*/ * 16 * G::PLANE * sizeof(_Float16);
 }
 
 template <int A>
@@ -104,10 +108,9 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   constexpr int SPT = (NITEM + NT - 1) / NT;     // items per thread
   static_assert(SPT <= 3, "wait counts below assume at most 3 loads per wave and tile");
   float* out = reinterpret_cast<float*>(smem);
-  float* raw0 = out + 16 * G::OST;               // 16 B aligned: 16 * OST is a multiple of 4
-  float* raw1 = raw0 + 4 * NITEM;
-  _Float16* hi = reinterpret_cast<_Float16*>(raw1 + 4 * NITEM);
-  _Float16* lo = hi + 16 * G::PLANE;
+  float* raw = out + 16 * G::OST;                // 16 B aligned: 16 * OST is a multiple of 4
+  _Float16* hl0 = reinterpret_cast<_Float16*>(raw + 4 * NITEM);  // hi | lo of buffer 0
+  _Float16* hl1 = hl0 + 2 * 16 * G::PLANE;
   float* gt = reinterpret_cast<float*>(smem + agg_tile_dma_spare_offset<A>());
   float* skt = gt + G::RAW;
   const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
@@ -137,12 +140,10 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
     eoff[q] = yok ? dd * static_cast<int>(cps) + Y * crs + Xc : 0;
     ldso[q] = it < NITEM ? dd * G::PLANE + 4 * k : -1;
   }
-  // loads this wave issues per tile (items with at least one lane in the list)
-  const int nq = __builtin_amdgcn_readfirstlane((NITEM - 64 * wave + NT - 1) / NT);
 
   // Byte offsets from the tile's first plane fit 32 bits: eoff <= 15 cps + (H-1) crs +
   // W - 1 < 2^30 under the 2^26 limits on cps and (H-1) crs + W.
-  auto issue = [&](int t, float* raw) {
+  auto issue = [&](int t) {
     const float* base = uniform(cost + static_cast<int64_t>(16 * t) * cps);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
@@ -157,19 +158,9 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
       }
     }
   };
-  // every wave: at most nq loads outstanding, i.e. all but the newest tile's loads done
-  auto wait_older = [&]() {
-    if (nq >= 3)
-      wait_vm<3>();
-    else if (nq == 2)
-      wait_vm<2>();
-    else
-      wait_vm<1>();
-  };
-  auto convert = [&](int t, const float* raw) {
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-      if (ldso[q] < 0) continue;
+  // item q of this thread, tile t: raw -> hi / lo
+  auto convert = [&](int q, int t, _Float16* hi, _Float16* lo) {
+    if (ldso[q] >= 0) {
       const int it = tid + q * NT;
       float4_t v = *reinterpret_cast<const float4_t*>(raw + 4 * it);
       // An opaque copy of the item's metadata: the decisions below are recomputed from
@@ -200,10 +191,10 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   };
 
   const int ndt = t_count < 0 ? (D + 15) >> 4 : t_count;  // tiles t_first .. t_first + ndt - 1
-  issue(t_first, raw0);
-  if (ndt > 1) issue(t_first + 1, raw1);
-  // The guide and spatial tables are staged while the first tiles load (the wait
-  // for the guide loads may also wait for those tiles).
+  static_assert(G::KS > SPT, "the conversion of the next tile rides on the last SPT K-steps");
+  issue(t_first);
+  // The guide and spatial tables are staged while the first tile loads (the wait
+  // for the guide loads also waits for that tile).
   for (int i = tid; i < G::RAW; i += NT) {
     const int r = i / G::TC, c = i - r * G::TC;
     const int Y = by - A + r, X = x0 + c;
@@ -214,13 +205,11 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
     const int dy = a - 3 - A, dx = b - 3 - A - G::PAD;
     skt[i] = (dy >= -A && dy <= A && dx >= -A && dx <= A) ? spatial_exponent(dy, dx, bk.kd) : INFINITY;
   }
-  if (ndt > 1)
-    wait_older();
-  else
-    wait_vm<0>();
-  convert(t_first, raw0);
-  __syncthreads();  // hi / lo of the first tile ready; raw0 is free
-  if (ndt > 2) issue(t_first + 2, raw0);
+  wait_vm<0>();
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) convert(q, t_first, hl0, hl0 + 16 * G::PLANE);
+  if (ndt > 1) issue(t_first + 1);  // into the chunks this thread has just converted
+  __syncthreads();  // hi / lo of the first tile, guide and spatial tables ready
 
   PatchPos pp;
   half8_t whi[G::KS], wlo[G::KS];
@@ -230,24 +219,28 @@ __device__ __forceinline__ void agg_tile_dma(const float* __restrict__ cost, int
   const float4_t iz = patch_weights<A, 16>(whi, wlo, pp, lane, pin, gt, skt);
 
   for (int t = 0; t < ndt; ++t) {
-    const float4_t acc = patch_mfma<A, 16>(whi, wlo, hi, lo, pp, lane);
+    _Float16* cur = (t & 1) ? hl1 : hl0;
+    _Float16* nxt = (t & 1) ? hl0 : hl1;
+    const bool more = t + 1 < ndt;
+    // K-step s: after its MFMAs are issued, the next tile's loads are waited for
+    // (s = KS - SPT - 1) and its item q converted (s = KS - SPT + q), beside the
+    // matrix pipe
+    const float4_t acc = patch_mfma_then<A, 16>(whi, wlo, cur, cur + 16 * G::PLANE, pp, lane, [&](int s) {
+      if (!more) return;
+      if (s == G::KS - SPT - 1) wait_vm<0>();
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (s == G::KS - SPT + q) convert(q, t_first + t + 1, nxt, nxt + 16 * G::PLANE);
+    });
+    if (t + 2 < ndt) issue(t_first + t + 2);
     float4_t vals;
 #pragma unroll
     for (int e = 0; e < 4; ++e) vals[e] = acc[e] * iz[e];
-    __syncthreads();  // hi / lo of tile t and the output tile (sink t - 1) are free
+    __syncthreads();  // hi / lo of tile t+1 ready; tile t's planes and the output tile (sink t-1) free
     *reinterpret_cast<float4_t*>(out + (lane & 15) * G::OST + (4 * pp.pr + (lane >> 4)) * 16 + 4 * pp.pc) =
         vals;
-    if (t + 1 < ndt) {
-      // tile t+1's loads were issued two iterations ago, tile t+2's one ago
-      if (t + 2 < ndt)
-        wait_older();
-      else
-        wait_vm<0>();
-      convert(t_first + t + 1, (t + 1) & 1 ? raw1 : raw0);
-    }
-    __syncthreads();  // output t and hi / lo of tile t+1 ready
+    __syncthreads();  // output t ready
     sink(t_first + t, static_cast<const float*>(out));
-    if (t + 3 < ndt) issue(t_first + t + 3, (t + 1) & 1 ? raw1 : raw0);
   }
   wait_vm<0>();  // nothing may be in flight into LDS when the block's LDS is reused
 }

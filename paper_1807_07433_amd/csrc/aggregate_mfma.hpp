@@ -136,5 +136,27 @@ __device__ __forceinline__ float4_t patch_mfma(const half8_t* whi, const half8_t
   return acc;
 }
 
+// patch_mfma with `then(s)` called after K-step s's MFMAs are issued: independent
+// work placed there (the next tile's conversion) issues while the matrix pipe runs.
+template <int A, int TY, typename Then>
+__device__ __forceinline__ float4_t patch_mfma_then(const half8_t* whi, const half8_t* wlo,
+                                                    const _Float16* hi, const _Float16* lo,
+                                                    const PatchPos& pp, int lane, Then then) {
+  using G = AggGeo<A, TY>;
+  const int j = lane & 15, g = lane >> 4;
+  const int base = j * G::PLANE + (4 * pp.pr + (g >> 1)) * G::TC + 4 * pp.pc + 8 * (g & 1);
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < G::KS; ++s) {
+    const int off = base + 2 * s * G::TC;
+    const half8_t bh = lds_load8(hi + off);
+    const half8_t bl = lds_load8(lo + off);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi[s], bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi[s], bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo[s], bh, acc, 0, 0, 0);
+    then(s);
+  }
+  return acc;
+}
 
 }  // namespace rsv
