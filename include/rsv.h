@@ -318,6 +318,13 @@ typedef struct {
                                    tile launch, pair after pair, so its cost volume is
                                    still in the caches when aggregated (implies one cost
                                    workgroup per item); 0: one launch per phase (default) */
+  int32_t volume_budget_mib;    /* 0: every pair's joint cost volume resident at once;
+                                   > 0 (default 2048): device memory for cost volumes, MiB:
+                                   the pairs run in groups of consecutive pairs whose
+                                   volumes fit half of it (a larger pair forms a group of
+                                   its own), alternating between two slots on two graph
+                                   branches, so that one group's volumes are computed
+                                   while the previous group is aggregated               */
 } rsv_tuning;
 
 typedef struct rsv_batch_plan rsv_batch_plan;
@@ -328,7 +335,8 @@ void rsv_tuning_default(rsv_tuning* t);
  * joint cost volume (rsv_cost_volume_joint's layout, row stride W + D - 1 rounded up
  * to 64) and selection state, two work lists, and a hipGraph of
  *   [reset queue counters] -> [warp every pair] -> [cost kernel] -> [tile kernel]
- *   -> [per-pixel tail].
+ *   -> [per-pixel tail]
+ * (with a volume budget: cost and tile kernels per group of pairs, see rsv_tuning).
  * The cost kernel runs ZNCC (the arithmetic of rsv_cost_volume_joint), persistent
  * over a work queue or one workgroup per tile (see rsv_tuning); with per-pair
  * launches the graph runs each pair's cost launch and then its tile launch.  Where
@@ -346,7 +354,9 @@ void rsv_tuning_default(rsv_tuning* t);
  *              sigma_min); p->D is ignored
  *   tuning     launch shape, or NULL for the defaults (see rsv_autotune)
  *   out        host pointer receiving the plan
- * The plan owns its device memory (about 4 * sum(H*(W+D)*D) bytes) and graph.
+ * The plan owns its device memory and graph: the cost volumes (about
+ * 4 * sum(H*(W+D)*D) bytes, or two slots of at most half the tuning's volume budget
+ * each, or of the largest pair's volume if that is larger) plus 12 bytes per pixel.
  * Errors: RSV_E_NULL, RSV_E_SHAPE (also H * row stride + 1 > 2^26 for a pair),
  * RSV_E_PARAM, RSV_E_DTYPE (pairs must be uint8), RSV_E_NOMEM, RSV_E_HIP. */
 int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
@@ -365,9 +375,10 @@ int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items, int32_t* g
 int rsv_batch_plan_destroy(rsv_batch_plan* plan);
 
 /* Times candidate launch shapes (pair order x cost tiles per item x cost workgroups
- * per CU) on this batch, each with its own temporary plan, and returns the fastest
- * in *out and its time in *best_ms (may be NULL).  Writes the pairs' outputs.
- * Synchronises `stream`. */
+ * per CU x per-pair launches, at the default volume budget; then volume budgets of
+ * 0, 512 and 4096 MiB on the fastest shape) on this batch, each with its own
+ * temporary plan, and returns the fastest in *out and its time in *best_ms (may be
+ * NULL).  Writes the pairs' outputs.  Synchronises `stream`. */
 int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p, rsv_tuning* out,
                  float* best_ms, void* stream);
 

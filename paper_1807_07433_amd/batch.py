@@ -22,7 +22,7 @@ class PairDesc(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("largest_first", C.c_int32), ("cost_tiles_per_item", C.c_int32),
                 ("cost_blocks_per_cu", C.c_int32), ("agg_blocks_per_cu", C.c_int32),
-                ("per_pair_launches", C.c_int32)]
+                ("per_pair_launches", C.c_int32), ("volume_budget_mib", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -364,23 +364,31 @@ __global__ __launch_bounds__(256) void batch_tail_kernel(const PairDev* pairs, i
 }
 
 __global__ void batch_reset_kernel(int* heads, int n) {
-  if (static_cast<int>(threadIdx.x) < n) heads[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) heads[i] = 0;
 }
 
 }  // namespace rsv
 
 // ------------------------------------------------------------------ host side
+// Default device memory for cost volumes.  On the 64-pair mixed batch (pairs up to
+// 1920x1080 with D = 128, 1.1 GB of volume) groups of at most 1 GiB, i.e. mostly one
+// pair, ran 46.5 ms against 47.9 ms with every volume resident (21.9 GiB): the next
+// group's cost volumes are computed while the current one is aggregated, and each
+// group's volumes are read back soon after they are written.
+constexpr int32_t kDefaultVolumeBudgetMiB = 2048;
+
 struct rsv_batch_plan {
   int n_pairs = 0;
   rsv_tuning tuning{};
   void* dev_mem = nullptr;  // one allocation: pair table, item lists, counters, workspace
   rsv::PairDev* d_pairs = nullptr;
-  int* d_heads = nullptr;   // [cost, aggregation queues]
-  rsv::BatchArgs cost_args{}, agg_args{}, tile_args{};
+  int* d_heads = nullptr;   // per group: [cost, aggregation queues]
   // agg: items of the persistent aggregation kernel; tar / ref: of the tile kernels
   int n_cost_items = 0, n_agg_items = 0, n_tile_items = 0;
-  int cost_grid = 0, agg_grid = 0;
-  hipStream_t capture_stream = nullptr;
+  int n_groups = 1;
+  int cost_grid = 0, agg_grid = 0;  // largest launch of a group
+  hipStream_t capture_stream = nullptr, capture_stream2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -468,6 +476,7 @@ extern "C" void rsv_tuning_default(rsv_tuning* t) {
   t->cost_blocks_per_cu = 0;
   t->agg_blocks_per_cu = 0;
   t->per_pair_launches = 0;
+  t->volume_budget_mib = kDefaultVolumeBudgetMiB;
 }
 
 extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, const rsv_params* p,
@@ -486,7 +495,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   rsv_tuning_default(&tn);
   if (tuning) tn = *tuning;
   if (tn.cost_tiles_per_item < 1 || tn.cost_tiles_per_item > 16 || tn.cost_blocks_per_cu < -1 ||
-      tn.agg_blocks_per_cu < 0)
+      tn.agg_blocks_per_cu < 0 || tn.volume_budget_mib < 0)
     return RSV_E_PARAM;
   int maxD = 0;
   for (int i = 0; i < n; ++i) {
@@ -508,18 +517,44 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   std::vector<int4> cost_items, agg_items, tile_items;
   size_t tile_lds = 0;
   const void* tk = pick_tile_kernel(A, &tile_lds);
-  size_t ws_bytes = 0;
   int max_pixels = 0;
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-  std::vector<size_t> off_joint(n), off_maps(n);
+  std::vector<size_t> off_joint(n), off_maps(n), vol(n);
   std::vector<int64_t> jrows(n);
+  for (int i = 0; i < n; ++i) {
+    const rsv_pair_desc& q = pairs[i];
+    jrows[i] = joint_row_stride(q.left.width, q.D);
+    vol[i] = align(sizeof(float) * static_cast<size_t>(q.D) * q.left.height * jrows[i]);
+  }
+  // Groups of consecutive pairs (in list order) whose joint volumes are resident
+  // together: one group without a budget; with one, groups of at most half the
+  // budget (at least one pair each) alternating between two slots, so that group
+  // g + 1's cost volumes are computed while group g is aggregated.
+  const size_t budget = static_cast<size_t>(tn.volume_budget_mib) << 20;
+  std::vector<int> group_first{0};  // list positions where groups start
+  std::vector<size_t> in_group(n);  // volume offset of list position k inside its group
+  size_t slot_bytes = 0, cur = 0;
+  for (int k = 0; k < n; ++k) {
+    const size_t v = vol[order[k]];
+    if (budget && k > group_first.back() && cur + v > budget / 2) {
+      group_first.push_back(k);
+      cur = 0;
+    }
+    in_group[k] = cur;
+    cur += v;
+    slot_bytes = std::max(slot_bytes, cur);
+  }
+  const int n_groups = static_cast<int>(group_first.size());
+  group_first.push_back(n);
+  const int n_slots = n_groups > 1 ? 2 : 1;
+  size_t ws_bytes = slot_bytes * n_slots;
+  for (int g = 0; g < n_groups; ++g)
+    for (int k = group_first[g]; k < group_first[g + 1]; ++k)
+      off_joint[order[k]] = slot_bytes * (g % n_slots) + in_group[k];
   for (int i = 0; i < n; ++i) {
     const rsv_pair_desc& q = pairs[i];
     const int H = q.left.height, W = q.left.width, D = q.D;
     const size_t N = static_cast<size_t>(H) * W;
-    jrows[i] = joint_row_stride(W, D);
-    off_joint[i] = ws_bytes;
-    ws_bytes = align(ws_bytes + sizeof(float) * static_cast<size_t>(D) * H * jrows[i]);
     off_maps[i] = ws_bytes;
     ws_bytes = align(ws_bytes + N * (sizeof(int32_t) * 2 + sizeof(float)));  // winners, warped image
     max_pixels = std::max<int>(max_pixels, static_cast<int>(N));
@@ -550,7 +585,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   const bool grid_cost = tn.cost_blocks_per_cu < 0 || tn.per_pair_launches != 0;
   const int cost_tiles = grid_cost ? 1 : tn.cost_tiles_per_item;
   // per pair (in list order): its ranges of the cost and tile lists
-  std::vector<int> cost_beg, cost_end, tile_beg, tile_end;
+  std::vector<int> cost_beg, cost_end, tile_beg, tile_end, agg_end;
   for (int i : order) {
     const PairDev& P = pd[i];
     cost_beg.push_back(static_cast<int>(cost_items.size()));
@@ -571,14 +606,27 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
         }
     cost_end.push_back(static_cast<int>(cost_items.size()));
     tile_end.push_back(static_cast<int>(tile_items.size()));
+    agg_end.push_back(static_cast<int>(agg_items.size()));
   }
-  // queue boundaries: [0, n_cost) for the cost kernel; 8 equal stretches of the agg list
-  std::vector<int> qbeg(2 + kAggQueues + 1);
-  qbeg[0] = 0;
-  qbeg[1] = static_cast<int>(cost_items.size());
-  const int na = static_cast<int>(agg_items.size());
-  for (int q = 0; q <= kAggQueues; ++q)
-    qbeg[2 + q] = static_cast<int>((static_cast<int64_t>(na) * q) / kAggQueues);
+  // per group: its ranges of the three lists, queue boundaries ([cost begin, cost end);
+  // 8 equal stretches of its agg items) and queue counters
+  constexpr int kQB = 2 + kAggQueues + 1, kHB = 1 + kAggQueues;
+  std::vector<int> qbeg(static_cast<size_t>(kQB) * n_groups);
+  std::vector<int> g_cost(n_groups + 1), g_tile(n_groups + 1), g_agg(n_groups + 1);
+  for (int g = 0; g <= n_groups; ++g) {
+    const int k = group_first[g];
+    g_cost[g] = k < n ? cost_beg[k] : static_cast<int>(cost_items.size());
+    g_tile[g] = k < n ? tile_beg[k] : static_cast<int>(tile_items.size());
+    g_agg[g] = k == 0 ? 0 : agg_end[k - 1];
+  }
+  for (int g = 0; g < n_groups; ++g) {
+    int* qb = qbeg.data() + static_cast<size_t>(kQB) * g;
+    qb[0] = g_cost[g];
+    qb[1] = g_cost[g + 1];
+    const int na = g_agg[g + 1] - g_agg[g];
+    for (int q = 0; q <= kAggQueues; ++q)
+      qb[2 + q] = g_agg[g] + static_cast<int>((static_cast<int64_t>(na) * q) / kAggQueues);
+  }
 
   rsv_batch_plan* plan = new (std::nothrow) rsv_batch_plan();
   if (!plan) return RSV_E_NOMEM;
@@ -598,7 +646,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   const size_t o_ti = off;
   off = align(off + sizeof(int4) * tile_items.size());
   const size_t o_heads = off;
-  off = align(off + sizeof(int) * (1 + kAggQueues));
+  off = align(off + sizeof(int) * kHB * n_groups);
   const size_t o_qbeg = off;
   off = align(off + sizeof(int) * qbeg.size());
   const size_t o_ws = off;
@@ -673,68 +721,98 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   }
   const int cpc = tn.cost_blocks_per_cu > 0 ? std::min(tn.cost_blocks_per_cu, cost_fit) : cost_fit;
   const int apc = tn.agg_blocks_per_cu > 0 ? std::min(tn.agg_blocks_per_cu, agg_fit) : agg_fit;
-  plan->cost_grid = cost_grid_mode ? std::max(1, plan->n_cost_items)
-                                   : std::min(cus * cpc, std::max(1, plan->n_cost_items));
-  plan->agg_grid = plan->n_agg_items > 0 ? std::min(cus * apc, plan->n_agg_items) : 0;
+  // launch sizes of one group's cost and persistent aggregation kernels
+  auto cost_blocks = [&](int g) {
+    const int items = g_cost[g + 1] - g_cost[g];
+    return cost_grid_mode ? items : std::min(cus * cpc, items);
+  };
+  auto agg_blocks = [&](int g) { return std::min(cus * apc, g_agg[g + 1] - g_agg[g]); };
+  plan->n_groups = n_groups;
+  plan->cost_grid = 0;
+  plan->agg_grid = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    plan->cost_grid = std::max(plan->cost_grid, cost_blocks(g));
+    plan->agg_grid = std::max(plan->agg_grid, agg_blocks(g));
+  }
 
   const int* d_qbeg = reinterpret_cast<const int*>(base + o_qbeg);
-  BatchArgs& ca = plan->cost_args;
+  BatchArgs ca{};
   ca.pairs = plan->d_pairs;
   ca.items = reinterpret_cast<const int4*>(base + o_ci);
-  ca.qbeg = d_qbeg;
   ca.nq = 1;
-  ca.head = plan->d_heads;
   ca.sigma_min = p->sigma_min;
   ca.bk = bilateral_constants(p->gamma_d, p->gamma_r);
-  BatchArgs& aa = plan->agg_args;
-  aa = ca;
+  BatchArgs aa = ca;
   aa.items = reinterpret_cast<const int4*>(base + o_ai);
-  aa.qbeg = d_qbeg + 2;
   aa.nq = kAggQueues;
-  aa.head = plan->d_heads + 1;
-  BatchArgs& ta = plan->tile_args;
-  ta = ca;
+  BatchArgs ta = ca;
   ta.items = reinterpret_cast<const int4*>(base + o_ti);
 
-  // graph: reset counters -> warp -> cost kernel -> [persistent aggregation kernel] ->
-  // tile kernel -> tail
+  // graph: reset counters -> warp -> per group: cost kernel -> [persistent aggregation
+  // kernel] -> tile kernel -> tail.  Groups alternate between two streams (two volume
+  // slots): group g + 1's launches may run beside group g's, group g + 2's follow
+  // group g's on the same stream, which frees the slot they share.
   if ((e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+  if (n_groups > 1) {
+    if ((e = hipStreamCreateWithFlags(&plan->capture_stream2, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming)) != hipSuccess) return fail(e);
+    if ((e = hipEventCreateWithFlags(&plan->join, hipEventDisableTiming)) != hipSuccess) return fail(e);
+  }
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
-  batch_reset_kernel<<<1, 64, 0, plan->capture_stream>>>(plan->d_heads, 1 + kAggQueues);
+  batch_reset_kernel<<<1, 256, 0, plan->capture_stream>>>(plan->d_heads, kHB * n_groups);
   const int tail_x = std::min(1024, (max_pixels + 255) / 256);
   batch_warp_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs);
-  if (tn.per_pair_launches) {
-    // pair after pair: its cost items, then its tiles, each launch over its own range
-    // of the lists (one workgroup per item); the persistent kernel's tiles after all
-    for (size_t k = 0; k < cost_beg.size(); ++k) {
-      BatchArgs c = plan->cost_args;
-      c.items += cost_beg[k];
+  if (n_groups > 1) {
+    hipEventRecord(plan->fork, plan->capture_stream);
+    hipStreamWaitEvent(plan->capture_stream2, plan->fork, 0);
+  }
+  for (int g = 0; g < n_groups; ++g) {
+    hipStream_t gs = (g & 1) ? plan->capture_stream2 : plan->capture_stream;
+    BatchArgs c = ca, a = aa;
+    c.qbeg = d_qbeg + static_cast<size_t>(kQB) * g;
+    c.head = plan->d_heads + static_cast<size_t>(kHB) * g;
+    a.qbeg = c.qbeg + 2;
+    a.head = c.head + 1;
+    if (tn.per_pair_launches) {
+      // pair after pair: its cost items, then its tiles, each launch over its own range
+      // of the lists (one workgroup per item); the persistent kernel's tiles after them
+      for (int k = group_first[g]; k < group_first[g + 1]; ++k) {
+        BatchArgs ck1 = ca;
+        ck1.items += cost_beg[k];
+        void* cargs[] = {&ck1};
+        hipLaunchKernel(ck, dim3(cost_end[k] - cost_beg[k]), dim3(kCostThreads), cargs, cost_lds, gs);
+        if (tile_end[k] > tile_beg[k]) {
+          BatchArgs t = ta;
+          t.items += tile_beg[k];
+          void* targs[] = {&t};
+          hipLaunchKernel(tk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), targs, tile_lds, gs);
+        }
+      }
+      if (agg_blocks(g) > 0) {
+        void* aargs[] = {&a};
+        hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs);
+      }
+    } else {
+      if (cost_grid_mode) c.items += g_cost[g];  // one workgroup per item of the group
       void* cargs[] = {&c};
-      hipLaunchKernel(ck, dim3(cost_end[k] - cost_beg[k]), dim3(kCostThreads), cargs, cost_lds,
-                      plan->capture_stream);
-      if (tile_end[k] > tile_beg[k]) {
-        BatchArgs t = plan->tile_args;
-        t.items += tile_beg[k];
+      if (cost_blocks(g) > 0)
+        hipLaunchKernel(ck, dim3(cost_blocks(g)), dim3(kCostThreads), cargs, cost_lds, gs);
+      if (agg_blocks(g) > 0) {
+        void* aargs[] = {&a};
+        hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs);
+      }
+      if (g_tile[g + 1] > g_tile[g]) {
+        BatchArgs t = ta;
+        t.items += g_tile[g];
         void* targs[] = {&t};
-        hipLaunchKernel(tk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), targs, tile_lds, plan->capture_stream);
+        hipLaunchKernel(tk, dim3(g_tile[g + 1] - g_tile[g]), dim3(1024), targs, tile_lds, gs);
       }
     }
-    if (plan->agg_grid > 0) {
-      void* aargs[] = {&plan->agg_args};
-      hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
-    }
-  } else {
-    void* cargs[] = {&plan->cost_args};
-    hipLaunchKernel(ck, dim3(plan->cost_grid), dim3(kCostThreads), cargs, cost_lds, plan->capture_stream);
-    if (plan->agg_grid > 0) {
-      void* aargs[] = {&plan->agg_args};
-      hipLaunchKernel(ak, dim3(plan->agg_grid), dim3(kAggItemThreads), aargs, agg_lds, plan->capture_stream);
-    }
-    if (plan->n_tile_items > 0) {
-      void* targs[] = {&plan->tile_args};
-      hipLaunchKernel(tk, dim3(plan->n_tile_items), dim3(1024), targs, tile_lds, plan->capture_stream);
-    }
+  }
+  if (n_groups > 1) {
+    hipEventRecord(plan->join, plan->capture_stream2);
+    hipStreamWaitEvent(plan->capture_stream, plan->join, 0);
   }
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
   hipError_t le = hipGetLastError();
@@ -781,6 +859,9 @@ extern "C" int rsv_batch_plan_destroy(rsv_batch_plan* plan) {
   if (plan->exec) hipGraphExecDestroy(plan->exec);
   if (plan->graph) hipGraphDestroy(plan->graph);
   if (plan->capture_stream) hipStreamDestroy(plan->capture_stream);
+  if (plan->capture_stream2) hipStreamDestroy(plan->capture_stream2);
+  if (plan->fork) hipEventDestroy(plan->fork);
+  if (plan->join) hipEventDestroy(plan->join);
   if (plan->dev_mem) hipFree(plan->dev_mem);
   delete plan;
   return RSV_OK;
@@ -797,6 +878,25 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RSV_E_HIP;
   int status = RSV_OK;
+  // mean time of 3 runs after a warm-up, or 1e30 if the plan cannot be built
+  auto time_plan = [&](const rsv_tuning& t) {
+    rsv_batch_plan* plan = nullptr;
+    const int s = rsv_batch_plan_create(pairs, n, p, &t, &plan);
+    if (s != RSV_OK) {
+      status = s;
+      return 1e30f;
+    }
+    rsv_batch_run(plan, st);  // warm-up
+    hipEventRecord(e0, st);
+    const int reps = 3;
+    for (int r = 0; r < reps; ++r) rsv_batch_run(plan, st);
+    hipEventRecord(e1, st);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    rsv_batch_plan_destroy(plan);
+    return ms / reps;
+  };
   for (int lf = 0; lf <= 1; ++lf)
     for (int tiles : {1, 2, 4})
       for (int cpc : {-1, 0, 2})
@@ -809,27 +909,25 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
         t.cost_tiles_per_item = tiles;
         t.cost_blocks_per_cu = cpc;
         t.per_pair_launches = pp;
-        rsv_batch_plan* plan = nullptr;
-        const int s = rsv_batch_plan_create(pairs, n, p, &t, &plan);
-        if (s != RSV_OK) {
-          status = s;
-          continue;
-        }
-        rsv_batch_run(plan, st);  // warm-up
-        hipEventRecord(e0, st);
-        const int reps = 3;
-        for (int r = 0; r < reps; ++r) rsv_batch_run(plan, st);
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        rsv_batch_plan_destroy(plan);
+        const float ms = time_plan(t);
         if (ms < best_t) {
           best_t = ms;
           best = t;
         }
       }
+  // then the volume budget, on the fastest launch shape
+  if (best_t < 1e30f) {
+    const rsv_tuning shape = best;
+    for (int mib : {0, 512, 4096}) {
+      rsv_tuning t = shape;
+      t.volume_budget_mib = mib;
+      const float ms = time_plan(t);
+      if (ms < best_t) {
+        best_t = ms;
+        best = t;
+      }
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (best_t >= 1e30f) return status != RSV_OK ? status : RSV_E_HIP;

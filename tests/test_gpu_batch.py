@@ -127,6 +127,14 @@ def test_batch_realistic_sizes_equal_plain(rsv_gpu):
     pairs = _pairs(cases)
     _say(f"[batch] realistic sizes {[c.pair.left.shape + (c.params.D,) for c in cases]}")
     plan = BatchPlan(pairs, PRM)
+    # default volume budget (2048 MiB): two slots of at most max(1 GiB, largest volume)
+    # instead of every volume, plus 12 B per pixel and the lists
+    vols = [4 * c.params.D * c.pair.left.shape[0] * (-(-(c.pair.left.shape[1] + c.params.D - 1) // 64) * 64)
+            for c in cases]
+    pix = sum(c.pair.left.size for c in cases)
+    info = plan.info()
+    _say(f"  plan {info}; volumes {sum(vols) / 2**30:.2f} GiB, largest {max(vols) / 2**30:.2f} GiB")
+    assert info["workspace_bytes"] <= 2 * max(2**30, max(vols)) + 13 * pix + (64 << 20)
     plan.run()
     torch.cuda.synchronize()
     for i, (pair, c) in enumerate(zip(pairs, cases)):
@@ -134,19 +142,23 @@ def test_batch_realistic_sizes_equal_plain(rsv_gpu):
     plan.close()
 
 
+@pytest.mark.parametrize("budget", [None, 1])  # default budget: one group; 1 MiB: a group per pair
 @pytest.mark.parametrize("r,rho,shapes", [
     (3, 6, [(37, 150, 31), (24, 70, 8)]),             # radius 6: every tile in the persistent kernel
     (1, 2, [(20, 3, 5), (30, 90, 17), (9, 5, 4)])])  # widths below 4 there, the rest in the tile kernels
-def test_batch_persistent_path_equals_plain(rsv_gpu, r, rho, shapes):
+def test_batch_persistent_path_equals_plain(rsv_gpu, r, rho, shapes, budget):
     rsv = rsv_gpu
-    from paper_1807_07433_amd.batch import BatchPlan
+    from paper_1807_07433_amd.batch import BatchPlan, default_tuning
     prm = synth.MethodParams(D=0, block_radius=r, agg_radius=rho, gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
     cases = [synth.small_case(H, W, D, r, rho, 960 + k, plane_a=0.07, plane_b=4.0 + k,
                               gamma_d=PRM.gamma_d, gamma_r=PRM.gamma_r)
              for k, (H, W, D) in enumerate(shapes)]
     pairs = _pairs(cases)
-    _say(f"[batch] r={r} rho={rho} shapes {shapes}")
-    plan = BatchPlan(pairs, prm)
+    t = default_tuning()
+    if budget is not None:
+        t.volume_budget_mib = budget
+    _say(f"[batch] r={r} rho={rho} shapes {shapes} tuning {t.as_dict()}")
+    plan = BatchPlan(pairs, prm, t)
     _say(f"  plan {plan.info()}")
     plan.run()
     torch.cuda.synchronize()
@@ -157,9 +169,13 @@ def test_batch_persistent_path_equals_plain(rsv_gpu, r, rho, shapes):
     plan.close()
 
 
-@pytest.mark.parametrize("largest_first,tiles,cpc,per_pair",
-                         [(0, 1, 0, 0), (1, 4, 2, 0), (1, 3, 1, 0), (1, 4, -1, 0), (0, 1, -1, 1), (1, 2, 0, 1)])
-def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc, per_pair):
+# budget (MiB): 0 every volume resident; 1 a group per pair (two slots, two graph
+# branches); 8 groups of one or two pairs
+@pytest.mark.parametrize("largest_first,tiles,cpc,per_pair,budget",
+                         [(0, 1, 0, 0, 0), (1, 4, 2, 0, 0), (1, 3, 1, 0, 2048), (1, 4, -1, 0, 0),
+                          (0, 1, -1, 1, 0), (1, 2, 0, 1, 2048), (0, 1, -1, 0, 1), (1, 2, 0, 0, 1),
+                          (0, 1, -1, 1, 1), (1, 1, -1, 0, 8)])
+def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc, per_pair, budget):
     rsv = rsv_gpu
     from paper_1807_07433_amd.batch import BatchPlan, default_tuning
     cases = _cases(SHAPES[:3], 950)
@@ -167,6 +183,7 @@ def test_tuning_variants_equal_plain(rsv_gpu, largest_first, tiles, cpc, per_pai
     t = default_tuning()
     t.largest_first, t.cost_tiles_per_item, t.cost_blocks_per_cu = largest_first, tiles, cpc
     t.per_pair_launches = per_pair
+    t.volume_budget_mib = budget
     _say(f"[batch] tuning {t.as_dict()}")
     plan = BatchPlan(pairs, PRM, t)
     plan.run()
