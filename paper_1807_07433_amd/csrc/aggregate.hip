@@ -86,9 +86,8 @@ __global__ __launch_bounds__(64 * TY, 4) void aggregate_kernel(
   }
 }
 
-// The same tile with its cost tiles loaded straight into LDS two disparity tiles
-// ahead (agg_tile_dma.hpp): used when its buffers fit one CU's LDS (rho <= 5) and
-// W >= 4.
+// The same tile with its cost tiles loaded straight into LDS ahead of use
+// (agg_tile_dma.hpp): used when its buffers fit one CU's LDS (rho <= 5) and W >= 4.
 template <int A, typename TG, bool ARG>
 __global__ __launch_bounds__(1024) void aggregate_dma_kernel(
     const float* __restrict__ cost, int64_t cps, int crs, const TG* __restrict__ guide, int64_t gpitch,
