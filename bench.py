@@ -83,6 +83,7 @@ _AGG_SOURCES = ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_
                 "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"]
 KERNEL_SOURCES = {
     "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
+    "aggregate_views": _AGG_SOURCES,
     "aggregate_ref": _AGG_SOURCES,
     "aggregate_tar": _AGG_SOURCES,
     "select_subpixel": ["select.hip", "select_math.hpp", "rsv_internal.hpp"],
@@ -145,18 +146,20 @@ def cost_lds_bytes(W, H, D, r):
 
 def agg_entry(stage_ms, key, W, H, D, prm, fused):
     """One aggregation launch against the FP32 arithmetic roofline: 2m + 2 FLOP per
-    entry (m = (2 rho + 1)^2 weighted terms, the weight sum and the normalisation).
-    Also its HBM rate (4 B per entry read; 4 B written as well where an unfused
-    reference launch writes its volume), the matrix-core work it issues (3 split-fp16
-    MFMAs per K-step over the padded window union) against the fp16 matrix peak, and
-    its LDS traffic from the tile's design."""
-    n = W * H * D
+    entry (m = (2 rho + 1)^2 weighted terms, the weight sum and the normalisation),
+    for both views' entries in the two-view launch (key "aggregate_views").  Also its
+    HBM rate (4 B per entry read; 4 B written as well where an unfused reference launch
+    writes its volume), the matrix-core work it issues (3 split-fp16 MFMAs per K-step
+    over the padded window union) against the fp16 matrix peak, and its LDS traffic
+    from the tile's design."""
+    views = 2 if key == "aggregate_views" else 1
+    n = W * H * D * views
     m = (2 * prm.agg_radius + 1) ** 2
     ms = stage_ms[key]
     flops = (2 * m + 2) * n
     tf = flops / (ms * 1e-3) / 1e12
     tiles = ((W + 15) // 16) * ((H + 15) // 16)
-    issued = tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
+    issued = views * tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
     itf = issued / (ms * 1e-3) / 1e12
     writes = key == "aggregate_ref" and not fused
     gbs = (8 if writes else 4) * n / (ms * 1e-3) / 1e9
@@ -166,7 +169,7 @@ def agg_entry(stage_ms, key, W, H, D, prm, fused):
             "hbm_view": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)},
             "mfma_view": {"issued_flops_per_launch": issued, "achieved_tflops": round(itf, 1),
                           "peak": PEAK_FP16_MFMA_TFLOPS, "frac": round(itf / PEAK_FP16_MFMA_TFLOPS, 4)},
-            "lds_view": lds_view(agg_lds_bytes(W, H, D, prm.agg_radius), ms)}
+            "lds_view": lds_view(views * agg_lds_bytes(W, H, D, prm.agg_radius), ms)}
 
 
 def lds_view(nbytes, ms):
@@ -182,16 +185,21 @@ def kernel_rooflines(stage_ms, W, H, D, prm, fused=False):
       cost_volume:    HBM, writes the joint volume that holds C_ref and C_tar (the
                       identity after Eq. 5): every distinct cost value once, 4 B each,
                       H (D W + D (D - 1) / 2) values (image reads are O(1/D));
-      aggregate_ref,  FP32 arithmetic (agg_entry), each launch on its own: the reference
-      aggregate_tar:  aggregation (with the selection folded in where fused) and the
-                      target aggregation reduced to its argmax;
-      select:         HBM, reads the reference aggregated volume, 4 B per entry (the
-                      target volume is reduced to its argmax inside its aggregation).
+      aggregate_views: FP32 arithmetic (agg_entry), where fused: both views in one
+                      launch, the target reduced to its argmax and the reference to its
+                      winner and Eq. 12;
+      lr_check:       HBM, where fused: Eq. 11 reads both maps and writes the mask,
+                      9 B per pixel;
+      aggregate_ref,  FP32 arithmetic, where not fused, each launch on its own: the
+      aggregate_tar:  reference aggregation and the target one reduced to its argmax;
+      select:         HBM, where not fused: reads the reference aggregated volume, 4 B
+                      per entry.
     The cost kernel also carries its LDS traffic (cost_lds_bytes) against the LDS peak."""
     n = W * H * D
     out = {}
     joint_bytes = 4 * H * (D * W + D * (D - 1) // 2)
-    hbm_kernels = [("cost_volume", joint_bytes)] + ([] if fused else [("select_subpixel", 4 * n)])
+    hbm_kernels = [("cost_volume", joint_bytes)] + ([("lr_check", 9 * W * H)] if fused else
+                                                      [("select_subpixel", 4 * n)])
     for k, nbytes in hbm_kernels:
         ms = stage_ms[k]
         gbs = nbytes / (ms * 1e-3) / 1e9
@@ -199,9 +207,17 @@ def kernel_rooflines(stage_ms, W, H, D, prm, fused=False):
                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes, "ms": round(ms, 5)}
     out["cost_volume"]["lds_view"] = lds_view(cost_lds_bytes(W, H, D, prm.block_radius),
                                               stage_ms["cost_volume"])
-    for key in ("aggregate_ref", "aggregate_tar"):
+    for key in (("aggregate_views",) if fused else ("aggregate_ref", "aggregate_tar")):
         out[key] = agg_entry(stage_ms, key, W, H, D, prm, fused)
     return out
+
+
+def agg_stage_ms(stage_ms):
+    """Both views' aggregation with the selection: the two-view launch and the
+    left-right check, or the target and reference launches."""
+    if "aggregate_views" in stage_ms:
+        return stage_ms["aggregate_views"] + stage_ms["lr_check"]
+    return stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
 
 
 def bench_batch(a, rsv, torch):
@@ -259,10 +275,12 @@ def bench_batch(a, rsv, torch):
             rsv.warp(right, plane, out=o["wp"])
             rsv.cost_volume_joint(left, o["wp"], c.params, out=o["j"])
             cr, ct = rsv.joint_views(o["j"], left.shape[1])
-            rsv.aggregate_argmax(ct, o["wp"], c.params, out=o["sel"]["disp_tar"])
             if rsv.aggregate_select_supported(left.shape[1], c.params):
-                rsv.aggregate_select(cr, left, c.params, o["sel"]["disp_tar"], out=o["sel"])
+                rsv.aggregate_views(cr, ct, left, o["wp"], c.params, out=o["sel"])
+                rsv.lr_check(o["sel"]["disp_ref"], o["sel"]["disp_tar"], c.params.lr_threshold,
+                             out=o["sel"]["valid"])
             else:
+                rsv.aggregate_argmax(ct, o["wp"], c.params, out=o["sel"]["disp_tar"])
                 rsv.aggregate(cr, left, c.params, out=ar)
                 rsv.select_subpixel(ar, None, c.params, out=o["sel"])
             rsv.triangulate(o["sel"]["disp_sub"], o["sel"]["valid"], plane, cam, out_disp=o["dfin"],
@@ -564,8 +582,7 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
 
     full_acc = accuracy(full_dfin.cpu().numpy().astype(np.float64), full_sel["valid"].cpu().numpy().astype(bool))
     out = {"full": {"mean_abs_err_px": full_acc[0], "valid_frac": full_acc[1],
-                    "cost_plus_agg_ms": round(stage_full["cost_volume"] + stage_full["aggregate_ref"] +
-                                              stage_full["aggregate_tar"], 5)},
+                    "cost_plus_agg_ms": round(stage_full["cost_volume"] + agg_stage_ms(stage_full), 5)},
            "radii": {}}
     for radius in (2, 4, 8):
         def step(ev=None):
@@ -647,12 +664,15 @@ def bench_sweep(a, rsv, torch, case, L, R):
                 rsv.cost_volume_joint(L, wp, prm, out=joint)
                 if record:
                     ev[1].record()
-                rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
-                if record:
-                    ev[2].record()
                 if fused:
-                    rsv.aggregate_select(cref, L, prm, sel["disp_tar"], out=sel)
+                    rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
+                    if record:
+                        ev[2].record()
+                    rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
                 else:
+                    rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
+                    if record:
+                        ev[2].record()
                     rsv.aggregate(cref, L, prm, out=aref)
                     rsv.select_subpixel(aref, None, prm, out=sel)
                 if record:
@@ -759,13 +779,13 @@ def main():
            "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
     dfin = torch.empty((H, W), **f32)
     xyz = torch.empty((H, W, 3), **f32)
-    # Where rsv_aggregate_select runs (radius <= 5), the selection is folded into the
-    # reference aggregation and no aggregated volume is written; the stage
-    # "aggregate_ref" then includes WTA, Eq. 11 and Eq. 12, and "select_subpixel" is
-    # empty.  Otherwise the reference volume is written and selected from.
+    # Where the LDS-loaded tile runs (radius <= 5, W >= 4), both views are aggregated in
+    # one launch with WTA and Eq. 12 folded in ("aggregate_views"), then Eq. 11
+    # ("lr_check"); no aggregated volume is written.  Otherwise the target volume is
+    # reduced to its argmax and the reference volume is written and selected from.
     fused = rsv.aggregate_select_supported(W, prm)
-    stages = ["warp", "cost_volume", "aggregate_tar", "aggregate_ref"] + \
-        ([] if fused else ["select_subpixel"]) + ["triangulate"]
+    stages = ["warp", "cost_volume"] + (["aggregate_views", "lr_check"] if fused else
+                                        ["aggregate_tar", "aggregate_ref", "select_subpixel"]) + ["triangulate"]
 
     def step(ev=None):
         marks = iter(ev) if ev is not None else None
@@ -778,11 +798,13 @@ def main():
         mark()
         rsv.cost_volume_joint(L, wp, prm, out=joint)
         mark()
-        rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])  # the target volume only feeds its argmax
-        mark()
         if fused:
-            rsv.aggregate_select(cref, L, prm, sel["disp_tar"], out=sel)
+            rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
+            mark()
+            rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
         else:
+            rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])  # the target volume only feeds its argmax
+            mark()
             rsv.aggregate(cref, L, prm, out=aref)
             mark()
             rsv.select_subpixel(aref, None, prm, out=sel)
@@ -809,7 +831,7 @@ def main():
     stage_ms = {s: sum(e[k].elapsed_time(e[k + 1]) for e in evs) / a.steps
                 for k, s in enumerate(stages)}
 
-    t_ca = stage_ms["cost_volume"] + stage_ms["aggregate_ref"] + stage_ms["aggregate_tar"]
+    t_ca = stage_ms["cost_volume"] + agg_stage_ms(stage_ms)
     mde = mde_per_s(W, H, D, t_ca * 1e-3)          # the metric: cost + both aggregations
     mde_frame = mde_per_s(W, H, D, ms_step * 1e-3)  # whole frame, warp to 3-D points
     graph = None if a.no_graph else plain_graph(torch, step, a.steps, (sel["disp_sub"], sel["valid"], xyz))
@@ -817,7 +839,7 @@ def main():
     kernels = kernel_rooflines(stage_ms, W, H, D, prm, fused)
     if probe:
         measured = max(probe["b64_tbs"], probe["b128_tbs"])
-        for k in ("cost_volume", "aggregate_ref", "aggregate_tar"):
+        for k in [k for k in kernels if "lds_view" in kernels[k]]:
             v = kernels[k]["lds_view"]
             v["measured_peak_tbs"] = measured
             v["frac_of_measured"] = round(v["achieved_tbs"] / measured, 4)
@@ -843,8 +865,9 @@ def main():
                                f"NCC {2 * prm.block_radius + 1}x{2 * prm.block_radius + 1}, "
                                f"bilateral {2 * prm.agg_radius + 1}x{2 * prm.agg_radius + 1}",
                    "width": W, "height": H, "D": D, "parallelism": "single-gpu",
-                   "value_definition": "W*H*D / (cost volume + both aggregations) time, Eq. 13",
-                   "selection": "folded into the reference aggregation" if fused else "separate kernel"},
+                   "value_definition": "W*H*D / (cost volume + both aggregations with selection) time, Eq. 13",
+                   "selection": ("both views in one launch with WTA and Eq. 12 folded in, then the Eq. 11 check "
+                                 "(its time counted)") if fused else "separate kernel"},
         "fps": round(1000.0 / ms_step, 2),
         "mde_full_frame": round(mde_frame, 2),
         "ms_per_step_median": round(float(sorted(sum(e[k].elapsed_time(e[k + 1]) for k in range(len(stages)))

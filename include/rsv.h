@@ -214,6 +214,35 @@ int rsv_aggregate_select(const float* cost, int64_t plane_stride, int64_t row_st
                          rsv_image guide, const rsv_params* p, const int32_t* disp_tar,
                          int32_t* disp_ref, float* disp_sub, uint8_t* valid, void* stream);
 
+/* Both views' aggregation in one launch (Sec. II-B.2 and II-B.3, Eq. 8-10 and 12):
+ * the target view reduced to its winner-take-all map as rsv_aggregate_argmax does, and
+ * the reference view to its winner and Eq. 12 as rsv_aggregate_select does; the
+ * left-right check (Eq. 11) is left to rsv_lr_check, which needs the complete target
+ * map.  disp_tar, disp_ref and disp_sub equal those of rsv_aggregate_argmax followed
+ * by rsv_aggregate_select bit for bit; no aggregated volume is written.  Runs where
+ * the cost tiles are loaded straight into LDS: agg_radius <= 5 and W >= 4.
+ *   cost_ref(d, v, u) = cost_ref[d*ref_plane_stride + v*ref_row_stride + u] (the
+ *             reference view), cost_tar likewise (the target view; e.g. both views of
+ *             one joint volume)
+ *   guide_ref the left image (u8 or f32);  guide_tar the warped right image (f32),
+ *             of the same H, W
+ *   disp_tar, disp_ref out, int32 [H][W];  disp_sub out, float32 [H][W]
+ * Errors: as rsv_aggregate_select; RSV_E_DTYPE for a guide_tar that is not float32,
+ * RSV_E_SHAPE for guides of different sizes. */
+int rsv_aggregate_views(const float* cost_ref, int64_t ref_plane_stride, int64_t ref_row_stride,
+                        const float* cost_tar, int64_t tar_plane_stride, int64_t tar_row_stride,
+                        rsv_image guide_ref, rsv_image guide_tar, const rsv_params* p,
+                        int32_t* disp_tar, int32_t* disp_ref, float* disp_sub, void* stream);
+
+/* Left-right consistency check (Sec. II-B.4, Eq. 11) of two winner-take-all maps:
+ *   valid(u, v) = (u - disp_ref >= 0) && |disp_ref - disp_tar(u - disp_ref, v)| <= tau
+ * with disp_ref = disp_ref(u, v), as the select kernels compute it.
+ *   disp_ref, disp_tar  int32 [H][W], read;  valid out, uint8 [H][W]
+ * Errors: RSV_E_NULL, RSV_E_ALIGN (int32 maps not 4-byte aligned), RSV_E_SHAPE
+ * (H or W < 1), RSV_E_PARAM (tau < 0), RSV_E_HIP. */
+int rsv_lr_check(const int32_t* disp_ref, const int32_t* disp_tar, int32_t height, int32_t width,
+                 int32_t tau, uint8_t* valid, void* stream);
+
 /* ------------------------------------------- restricted search (Sec. IV)
  * The paper's proposed speed-up: bilateral filtering only on the disparities around
  * an already calculated disparity instead of on the whole cost volume.  Here the

@@ -215,6 +215,52 @@ def aggregate_select(cost: torch.Tensor, guide: torch.Tensor, params, disp_tar: 
     return o
 
 
+def aggregate_views(cost_ref: torch.Tensor, cost_tar: torch.Tensor, guide_ref: torch.Tensor,
+                    guide_tar: torch.Tensor, params, out: dict | None = None) -> dict:
+    """Both views aggregated in one launch (rsv_aggregate_views): disp_tar as
+    aggregate_argmax gives it, disp_ref and disp_sub as aggregate_select gives them,
+    bit for bit; the left-right check is lr_check's.  guide_tar is the float32
+    warped right image.  Runs where aggregate_select_supported holds."""
+    lib = load()
+    D, H, W = cost_ref.shape
+    for t, n in ((cost_ref, "cost_ref"), (cost_tar, "cost_tar")):
+        _dev(t, n, torch.float32, (int(params.D), H, W))
+        if t.stride(2) != 1:
+            raise ValueError(f"{n}: cost views need unit column stride")
+    for g, n in ((guide_ref, "guide_ref"), (guide_tar, "guide_tar")):
+        if tuple(g.shape) != (H, W):
+            raise ValueError(f"{n} must match the volume's H, W")
+    dev = cost_ref.device
+    o = dict(out) if out else {}
+    shapes = {"disp_tar": ((H, W), torch.int32), "disp_ref": ((H, W), torch.int32),
+              "disp_sub": ((H, W), torch.float32)}
+    for k, (shp, dt) in shapes.items():
+        if k not in o:
+            o[k] = torch.empty(shp, dtype=dt, device=dev)
+        _contig(o[k], k, dt, shp)
+    p = _params(params)
+    check(lib.rsv_aggregate_views(cost_ref.data_ptr(), cost_ref.stride(0), cost_ref.stride(1), cost_tar.data_ptr(),
+                                  cost_tar.stride(0), cost_tar.stride(1), image(guide_ref, "guide_ref"),
+                                  image(guide_tar, "guide_tar"), C.byref(p), o["disp_tar"].data_ptr(),
+                                  o["disp_ref"].data_ptr(), o["disp_sub"].data_ptr(), _stream(dev)),
+          "rsv_aggregate_views")
+    return o
+
+
+def lr_check(disp_ref: torch.Tensor, disp_tar: torch.Tensor, tau: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. 11 on two winner-take-all maps (rsv_lr_check): uint8 valid [H][W]."""
+    lib = load()
+    H, W = disp_ref.shape
+    _contig(disp_ref, "disp_ref", torch.int32, (H, W))
+    _contig(disp_tar, "disp_tar", torch.int32, (H, W))
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=disp_ref.device)
+    _contig(out, "valid", torch.uint8, (H, W))
+    check(lib.rsv_lr_check(disp_ref.data_ptr(), disp_tar.data_ptr(), H, W, int(tau), out.data_ptr(),
+                           _stream(disp_ref.device)), "rsv_lr_check")
+    return out
+
+
 def cost_argmax(cost: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
     """First argmax over d of an unaggregated [D][H][W] cost volume or view
     (rsv_cost_argmax): the calculated disparities of the restricted search (Sec. IV)."""
@@ -466,15 +512,17 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
     one joint volume (rsv_cost_volume_joint); otherwise two dense volumes.  With
     tar_volume=False the target volume is reduced to its argmax as it is aggregated
     (rsv_aggregate_argmax) and "agg_tar" is None.  With ref_volume=False as well (and
-    where rsv_aggregate_select runs, without top2) the selection is folded into the
-    reference aggregation and "agg_ref" is None.  Every other output is the same."""
+    where rsv_aggregate_select runs, without top2) both views are aggregated in one
+    launch with the selection folded in (rsv_aggregate_views, then rsv_lr_check) and
+    "agg_ref" is None.  Every other output is the same."""
     wp = warp(right, plane)
     if joint:
         cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
     else:
         cref, ctar = cost_volume(left, wp, params)
     if not tar_volume and not ref_volume and not want_top2 and aggregate_select_supported(left.shape[1], params):
-        sel = aggregate_select(cref, left, params, aggregate_argmax(ctar, wp, params))
+        sel = aggregate_views(cref, ctar, left, wp, params)
+        sel["valid"] = lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold)
         dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
         out = dict(warped=wp, cost_ref=cref, cost_tar=ctar, agg_ref=None, agg_tar=None,
                    disp_final=dfin, xyz=xyz)
@@ -496,7 +544,7 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
-           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select",
+           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select", "aggregate_views", "lr_check",
            "aggregate_select_supported", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "selected_aggregate_sum", "cost_adjoint",
            "cost_argmax", "aggregate_restricted_argmax", "aggregate_restricted_select", "reconstruct_restricted",

@@ -223,6 +223,39 @@ def test_aggregate_select_validation(lib):
     assert f(A, 32 * 48, 48, _img(), C.byref(_params(gamma_r=0.0)), B, Cc, Dd, A, None) == -3
 
 
+def test_aggregate_views_and_lr_check_validation(lib):
+    """rsv_aggregate_views rejects bad arguments before launching: nulls, alignment,
+    strides, guides of different sizes, a target guide that is not float32, radii the
+    LDS-loaded tile cannot take, widths below 4; rsv_lr_check: nulls, alignment, sizes
+    and a negative tolerance."""
+    p = _params()
+    A, B, Cc, Dd, E = (FAKE + i * 4096 for i in range(5))
+    f = lib.rsv_aggregate_views
+    g8, gf = _img(), _img(dtype=1)
+    ok = (A, 32 * 48, 48, B, 32 * 48 + 1, 48, g8, gf, C.byref(p), Cc, Dd, E, None)
+
+    def call(**kw):
+        args = list(ok)
+        for i, v in kw.items():
+            args[int(i[1:])] = v
+        return f(*args)
+    assert call(a0=None) == -1 and call(a3=None) == -1 and call(a9=None) == -1 and call(a11=None) == -1
+    assert call(a3=B + 2) == -5 and call(a10=Dd + 2) == -5
+    assert call(a2=47) == -2 and call(a5=47) == -2                 # row stride < W
+    assert call(a4=0) == -2                                        # plane stride < 1
+    assert call(a7=_img(h=31, dtype=1)) == -2                      # guides of different sizes
+    assert call(a7=_img()) == -4                                   # target guide must be float32
+    assert call(a8=C.byref(_params(agg_radius=6))) == -3
+    assert call(a6=_img(w=3), a7=_img(w=3, dtype=1), a2=3, a5=3, a1=96, a4=97) == -2  # W < 4
+    assert call(a8=C.byref(_params(lr_threshold=-1))) == -3
+    lr = lib.rsv_lr_check
+    assert lr(None, B, 32, 48, 1, Cc, None) == -1
+    assert lr(A, B, 32, 48, 1, None, None) == -1
+    assert lr(A + 2, B, 32, 48, 1, Cc, None) == -5
+    assert lr(A, B, 0, 48, 1, Cc, None) == -2
+    assert lr(A, B, 32, 48, -1, Cc, None) == -3
+
+
 def test_lds_probe_library_loads_and_rejects_bad_arguments():
     """libprobe.so (the LDS bandwidth probe bench.py uses) is built beside librsv.so,
     exports its entry point and rejects bad arguments before launching anything."""

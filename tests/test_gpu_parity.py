@@ -135,6 +135,12 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
         fused = rsv.aggregate_select(jref, L, prm, dt)
         for k in ("disp_ref", "disp_sub", "valid"):
             assert torch.equal(fused[k], sel[k]), k
+        _say("  rsv_aggregate_views + rsv_lr_check (both views in one launch)")
+        vw = rsv.aggregate_views(jref, jtar, L, wp, prm)
+        assert torch.equal(vw["disp_tar"], dt), "disp_tar of the two-view launch"
+        for k in ("disp_ref", "disp_sub"):
+            assert torch.equal(vw[k], sel[k]), k
+        assert torch.equal(rsv.lr_check(vw["disp_ref"], vw["disp_tar"], prm.lr_threshold), sel["valid"])
     top2 = P.to_np(sel["top2"])
     P.check_close("best", top2[0], ref["best"], P.AGG_TOL)
     if D > 1:

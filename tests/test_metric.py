@@ -69,20 +69,25 @@ def test_lds_traffic_of_the_tiles():
 
 
 def test_kernel_rooflines_with_the_selection_folded_in():
-    """With the selection folded into the reference aggregation there is no select
-    kernel to report, each aggregation launch is reported on its own, and each reads
-    4 B per entry and writes maps."""
+    """With both views aggregated in one launch and the selection folded in, there is
+    no select kernel to report: the two-view launch carries both views' FLOPs and reads
+    4 B per entry of each view, and the left-right check reads both maps and writes the
+    mask, 9 B per pixel."""
     class P:
         agg_radius = 5
         block_radius = 3
-    st = {"cost_volume": 0.1, "aggregate_ref": 0.25, "aggregate_tar": 0.24}
+    st = {"cost_volume": 0.1, "aggregate_views": 0.45, "lr_check": 0.005}
     k = bench.kernel_rooflines(st, 1280, 720, 64, P, fused=True)
-    assert set(k) == {"cost_volume", "aggregate_ref", "aggregate_tar"}
+    assert set(k) == {"cost_volume", "aggregate_views", "lr_check"}
     n = 1280 * 720 * 64
-    for key, ms in (("aggregate_ref", 0.25), ("aggregate_tar", 0.24)):
-        assert abs(k[key]["hbm_view"]["achieved_gbs"] - 4 * n / (ms * 1e-3) / 1e9) < 0.1
-        assert k[key]["flops_per_launch"] == (2 * 121 + 2) * n
-        assert abs(k[key]["achieved"] - (2 * 121 + 2) * n / (ms * 1e-3) / 1e12) < 0.01
+    v = k["aggregate_views"]
+    assert abs(v["hbm_view"]["achieved_gbs"] - 2 * 4 * n / (0.45e-3) / 1e9) < 0.1
+    assert v["flops_per_launch"] == 2 * (2 * 121 + 2) * n
+    assert abs(v["achieved"] - 2 * (2 * 121 + 2) * n / (0.45e-3) / 1e12) < 0.01
+    assert v["lds_view"]["bytes_per_launch"] == 2 * bench.agg_lds_bytes(1280, 720, 64, 5)
+    assert k["lr_check"]["bytes_per_launch"] == 9 * 1280 * 720
+    assert abs(bench.agg_stage_ms(st) - 0.455) < 1e-12
+    assert abs(bench.agg_stage_ms({"aggregate_ref": 0.25, "aggregate_tar": 0.24}) - 0.49) < 1e-12
 
 
 def test_adjoint_flop_count_by_hand():
