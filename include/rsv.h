@@ -343,10 +343,11 @@ typedef struct {
   int32_t cost_blocks_per_cu;   /* persistent cost workgroups per CU; 0 = as many as fit
                                    (default); -1 = one workgroup per cost item, no queue */
   int32_t agg_blocks_per_cu;    /* persistent aggregation workgroups per CU; 0 = as fit  */
-  int32_t per_pair_launches;    /* 1: the graph runs each pair's cost launch and then its
-                                   tile launch, pair after pair, so its cost volume is
-                                   still in the caches when aggregated (implies one cost
-                                   workgroup per item); 0: one launch per phase (default) */
+  int32_t per_pair_launches;    /* 1 (default): each pair's cost launch and then its tile
+                                   launch, pair after pair within a group, each kernel
+                                   taking the pair's descriptor as an argument (implies
+                                   one cost workgroup per tile); 0: one launch per phase
+                                   and group over the item lists                        */
   int32_t volume_budget_mib;    /* 0: every pair's joint cost volume resident at once;
                                    > 0 (default 2048): device memory for cost volumes, MiB:
                                    the pairs run in groups of consecutive pairs whose

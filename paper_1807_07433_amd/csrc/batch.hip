@@ -239,6 +239,20 @@ __global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_
                           cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D), cwork);
 }
 
+// One pair's cost tiles, the pair's descriptor a kernel argument (block b: band
+// b / ncol_tiles, column tile b % ncol_tiles); used by the per-pair launch schedule.
+template <int R>
+__global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_pair_cost_kernel(PairDev P, float sigma_min) {
+  extern __shared__ __align__(16) float cwork[];
+  const float* warped = P.warped;
+  const int W = P.W;
+  auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
+  const int band = static_cast<int>(blockIdx.x) / P.ncol_tiles;
+  const int ct = static_cast<int>(blockIdx.x) - band * P.ncol_tiles;
+  cost_tile<R, kBandRows, false>(P.left, P.lpitch, warped_at, P.H, W, P.D, sigma_min, ct * kCostTW,
+                                 band * kBandRows, cost_out_joint(P.joint, P.jrow, P.H, W, P.D), cwork);
+}
+
 template <int A>
 __device__ __noinline__ void batch_agg_item(const BatchArgs& args, int4 w, unsigned char* smem) {
   // the item and the pair's fields are the same for the whole workgroup
@@ -285,45 +299,61 @@ __global__ __launch_bounds__(kAggItemThreads) void batch_agg_kernel(BatchArgs ar
   for_each_item(args, home, s_item, [&](int it) { batch_agg_item<A>(args, args.items[it], smem); });
 }
 
-// Target-volume items on the LDS-loaded tile (rho <= 5, W >= 4): only the argmax over
-// d is kept, in registers (ArgmaxSink), as in rsv_aggregate_argmax.
+// Target-volume tiles on the LDS-loaded tile (rho <= 5, W >= 4): only the argmax over
+// d is kept, in registers (ArgmaxSink), as in rsv_aggregate_argmax.  P holds the
+// pair's descriptor (wave-uniform values).
 template <int A>
-__device__ __forceinline__ void batch_tar_tile(const BatchArgs& args, int4 w, unsigned char* smem) {
-  const PairDev* pd = uniform(args.pairs + uniform(w.x));
-  const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
-  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
-  const float* warped = uniform(pd->warped);
-  const int jrow = static_cast<int>(uniform(pd->jrow));
+__device__ __forceinline__ void batch_tar_tile(const PairDev& P, const BilateralK& bk, int by, int bx,
+                                               unsigned char* smem) {
+  const int H = P.H, W = P.W, D = P.D;
+  const float* warped = P.warped;
+  const int jrow = static_cast<int>(P.jrow);
   auto guide = [&](int Y, int X) { return as_global(warped)[static_cast<int64_t>(Y) * W + X]; };
   ArgmaxSink sink{D};
-  agg_tile_dma<A>(uniform(pd->joint), static_cast<int64_t>(H) * jrow + 1, jrow, H, W, D, args.bk, by, bx, guide,
-                  sink, smem, lds_address(smem));
-  sink.finish(uniform(pd->tar_arg), H, W, by, bx);
+  agg_tile_dma<A>(P.joint, static_cast<int64_t>(H) * jrow + 1, jrow, H, W, D, bk, by, bx, guide, sink, smem,
+                  lds_address(smem));
+  sink.finish(P.tar_arg, H, W, by, bx);
 }
 
-// Reference-volume items on the LDS-loaded tile (rho <= 5, W >= 4): the select
+// Reference-volume tiles on the LDS-loaded tile (rho <= 5, W >= 4): the select
 // kernel's scan result from all 1024 threads (RefQuadSink).
 template <int A>
-__device__ __forceinline__ void batch_ref_tile(const BatchArgs& args, int4 w, unsigned char* smem) {
-  const PairDev* pd = uniform(args.pairs + uniform(w.x));
-  const int H = uniform(pd->H), W = uniform(pd->W), D = uniform(pd->D);
-  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
-  const uint8_t* left = uniform(pd->left);
-  const int64_t lpitch = uniform(pd->lpitch);
-  const int jrow = static_cast<int>(uniform(pd->jrow));
+__device__ __forceinline__ void batch_ref_tile(const PairDev& P, const BilateralK& bk, int by, int bx,
+                                               unsigned char* smem) {
+  const int H = P.H, W = P.W, D = P.D;
+  const uint8_t* left = P.left;
+  const int64_t lpitch = P.lpitch;
+  const int jrow = static_cast<int>(P.jrow);
   auto guide = [&](int Y, int X) { return pixel(left, lpitch, Y, X); };
   RefQuadSink sink{D};
-  agg_tile_dma<A>(uniform(pd->joint), static_cast<int64_t>(H) * jrow, jrow, H, W, D, args.bk, by, bx, guide, sink,
-                  smem, lds_address(smem));
+  agg_tile_dma<A>(P.joint, static_cast<int64_t>(H) * jrow, jrow, H, W, D, bk, by, bx, guide, sink, smem,
+                  lds_address(smem));
   if ((threadIdx.x & 3) == 0) {  // the four lanes of a pixel hold the same result
     const int q = threadIdx.x >> 2;
     const int Y = by + (q >> 4), X = bx + (q & 15);
     if (Y < H && X < W) {
       const int64_t i = static_cast<int64_t>(Y) * W + X;
-      uniform(pd->ref_arg)[i] = sink.arg;  // the winner and Eq. 12 on it
-      uniform(pd->disp_sub)[i] = parabola(sink.arg, sink.best, sink.am, sink.ap, D);
+      P.ref_arg[i] = sink.arg;  // the winner and Eq. 12 on it
+      P.disp_sub[i] = parabola(sink.arg, sink.best, sink.am, sink.ap, D);
     }
   }
+}
+
+// The pair descriptor of an item, read into wave-uniform registers.
+__device__ __forceinline__ PairDev load_pair(const PairDev* pd) {
+  PairDev P;
+  P.left = uniform(pd->left);
+  P.lpitch = uniform(pd->lpitch);
+  P.H = uniform(pd->H);
+  P.W = uniform(pd->W);
+  P.D = uniform(pd->D);
+  P.warped = uniform(pd->warped);
+  P.joint = uniform(pd->joint);
+  P.jrow = uniform(pd->jrow);
+  P.ref_arg = uniform(pd->ref_arg);
+  P.tar_arg = uniform(pd->tar_arg);
+  P.disp_sub = uniform(pd->disp_sub);
+  return P;
 }
 
 // The tile items {pair, kind, tile row, tile column} of the LDS-loaded tile, one
@@ -337,10 +367,28 @@ __global__ __launch_bounds__(1024) void batch_tile_kernel(BatchArgs args) {
   // each XCD takes runs of 8 neighbouring tiles (they share halos in its L2), all XCDs
   // near the same stretch of the list (one pair's volume in the shared cache)
   const int4 w = args.items[xcd_run_item<8>(blockIdx.x, gridDim.x)];
+  const PairDev P = load_pair(args.pairs + uniform(w.x));
+  const int by = 16 * uniform(w.z), bx = 16 * uniform(w.w);
   if (uniform(w.y) == kItemAggRef)
-    batch_ref_tile<A>(args, w, smem);
+    batch_ref_tile<A>(P, args.bk, by, bx, smem);
   else
-    batch_tar_tile<A>(args, w, smem);
+    batch_tar_tile<A>(P, args.bk, by, bx, smem);
+}
+
+// One pair's tiles of both views, the pair's descriptor a kernel argument: no item
+// list and no descriptor load before the tile's first loads.  Tiles in the order of
+// rsv_aggregate_views (a tile row of reference tiles, then of target tiles), XCDs in
+// runs of 80.  Used by the per-pair launch schedule.
+template <int A>
+__global__ __launch_bounds__(1024) void batch_pair_tile_kernel(PairDev P, BilateralK bk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tiles_x = (P.W + 15) >> 4, tiles_y = (P.H + 15) >> 4;
+  const int k = xcd_run_item<80>(blockIdx.x, 2 * tiles_x * tiles_y);
+  const int ty = k / (2 * tiles_x), r = k - ty * 2 * tiles_x;
+  if (r < tiles_x)
+    batch_ref_tile<A>(P, bk, 16 * ty, 16 * r, smem);
+  else
+    batch_tar_tile<A>(P, bk, 16 * ty, 16 * (r - tiles_x), smem);
 }
 
 // Left-right check, post-processing and 3-D points for every pixel of every pair (the
@@ -397,6 +445,11 @@ namespace rsv {
 namespace {
 
 template <int R>
+const void* pair_cost_kernel_ptr() {
+  return reinterpret_cast<const void*>(batch_pair_cost_kernel<R>);
+}
+
+template <int R>
 const void* cost_kernel_ptr(bool grid) {
   return grid ? reinterpret_cast<const void*>(batch_cost_grid_kernel<R>)
               : reinterpret_cast<const void*>(batch_cost_kernel<R>);
@@ -412,6 +465,16 @@ const void* pick_cost_kernel(int R, bool grid) {
     case 2: return cost_kernel_ptr<2>(grid);
     case 3: return cost_kernel_ptr<3>(grid);
     case 4: return cost_kernel_ptr<4>(grid);
+    default: return nullptr;
+  }
+}
+
+const void* pick_pair_cost_kernel(int R) {
+  switch (R) {
+    case 1: return pair_cost_kernel_ptr<1>();
+    case 2: return pair_cost_kernel_ptr<2>();
+    case 3: return pair_cost_kernel_ptr<3>();
+    case 4: return pair_cost_kernel_ptr<4>();
     default: return nullptr;
   }
 }
@@ -437,6 +500,25 @@ const void* tile_kernel_ptr(size_t* lds) {
     return reinterpret_cast<const void*>(batch_tile_kernel<A>);
   } else {
     return nullptr;
+  }
+}
+
+template <int A>
+const void* pair_tile_kernel_ptr() {
+  if constexpr (agg_dma_fits<A>())
+    return reinterpret_cast<const void*>(batch_pair_tile_kernel<A>);
+  else
+    return nullptr;
+}
+
+const void* pick_pair_tile_kernel(int A) {
+  switch (A) {
+    case 1: return pair_tile_kernel_ptr<1>();
+    case 2: return pair_tile_kernel_ptr<2>();
+    case 3: return pair_tile_kernel_ptr<3>();
+    case 4: return pair_tile_kernel_ptr<4>();
+    case 5: return pair_tile_kernel_ptr<5>();
+    default: return nullptr;
   }
 }
 
@@ -475,7 +557,7 @@ extern "C" void rsv_tuning_default(rsv_tuning* t) {
   t->cost_tiles_per_item = 2;
   t->cost_blocks_per_cu = 0;
   t->agg_blocks_per_cu = 0;
-  t->per_pair_launches = 0;
+  t->per_pair_launches = 1;
   t->volume_budget_mib = kDefaultVolumeBudgetMiB;
 }
 
@@ -702,8 +784,16 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   if ((e = hipFuncSetAttribute(ck, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(cost_lds))) !=
       hipSuccess)
     return fail(e);
+  const void* pck = pick_pair_cost_kernel(R);  // non-null: R was validated above
+  if ((e = hipFuncSetAttribute(pck, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(cost_lds))) !=
+      hipSuccess)
+    return fail(e);
   if (tk && (e = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(tile_lds))) != hipSuccess)
+    return fail(e);
+  const void* ptk = pick_pair_tile_kernel(A);
+  if (ptk && (e = hipFuncSetAttribute(ptk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(tile_lds))) != hipSuccess)
     return fail(e);
   if ((e = hipFuncSetAttribute(ak, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(agg_lds))) !=
       hipSuccess)
@@ -778,15 +868,15 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       // pair after pair: its cost items, then its tiles, each launch over its own range
       // of the lists (one workgroup per item); the persistent kernel's tiles after them
       for (int k = group_first[g]; k < group_first[g + 1]; ++k) {
-        BatchArgs ck1 = ca;
-        ck1.items += cost_beg[k];
-        void* cargs[] = {&ck1};
-        hipLaunchKernel(ck, dim3(cost_end[k] - cost_beg[k]), dim3(kCostThreads), cargs, cost_lds, gs);
-        if (tile_end[k] > tile_beg[k]) {
-          BatchArgs t = ta;
-          t.items += tile_beg[k];
-          void* targs[] = {&t};
-          hipLaunchKernel(tk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), targs, tile_lds, gs);
+        PairDev Pc = pd[order[k]];
+        float sm = p->sigma_min;
+        void* cargs[] = {&Pc, &sm};
+        hipLaunchKernel(pck, dim3(Pc.nbands * Pc.ncol_tiles), dim3(kCostThreads), cargs, cost_lds, gs);
+        if (tile_end[k] > tile_beg[k]) {  // all of the pair's tiles, both views
+          PairDev P = pd[order[k]];
+          BilateralK bk = ca.bk;
+          void* pargs[] = {&P, &bk};
+          hipLaunchKernel(ptk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), pargs, tile_lds, gs);
         }
       }
       if (agg_blocks(g) > 0) {
