@@ -266,20 +266,6 @@ int dispatch_agg_views(const float* cref, int64_t rps, int rrs, const float* cta
   }
 }
 
-// Eq. 11 for every pixel: valid where u - d_ref(u) is in the image and the target
-// winner there is within tau of d_ref (the select kernels' test).
-__global__ __launch_bounds__(256) void lr_check_kernel(const int32_t* __restrict__ dref,
-                                                       const int32_t* __restrict__ dtar, int H, int W, int tau,
-                                                       uint8_t* __restrict__ valid) {
-  const int64_t n = static_cast<int64_t>(H) * W;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * 256) {
-    const int Y = static_cast<int>(i / W), X = static_cast<int>(i - static_cast<int64_t>(Y) * W);
-    const int a = dref[i], x = X - a;
-    valid[i] = (x >= 0 && abs(a - dtar[static_cast<int64_t>(Y) * W + (x < 0 ? 0 : x)]) <= tau) ? 1 : 0;
-  }
-}
-
 // ------------------------------------------------- restricted search (Sec. IV)
 // Each pixel aggregates only the window of `width` disparities around its calculated
 // (unaggregated winner-take-all) disparity, lo = clamp(coarse - radius, 0, D - width).
@@ -575,19 +561,6 @@ extern "C" int rsv_aggregate_views(const float* cost_ref, int64_t ref_plane_stri
                                        guide_tar, p, disp_tar, disp_ref, disp_sub, st);
   return dispatch_agg_views<float>(cost_ref, ref_plane_stride, rrs, cost_tar, tar_plane_stride, trs, guide_ref,
                                    guide_tar, p, disp_tar, disp_ref, disp_sub, st);
-}
-
-extern "C" int rsv_lr_check(const int32_t* disp_ref, const int32_t* disp_tar, int32_t height, int32_t width,
-                            int32_t tau, uint8_t* valid, void* stream) {
-  using namespace rsv;
-  if (!disp_ref || !disp_tar || !valid) return RSV_E_NULL;
-  if (!aligned(disp_ref, 4) || !aligned(disp_tar, 4)) return RSV_E_ALIGN;
-  if (height < 1 || width < 1) return RSV_E_SHAPE;
-  if (tau < 0) return RSV_E_PARAM;
-  const int64_t n = static_cast<int64_t>(height) * width;
-  const int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 8192));
-  lr_check_kernel<<<dim3(blocks), dim3(256), 0, as_stream(stream)>>>(disp_ref, disp_tar, height, width, tau, valid);
-  return check_launch();
 }
 
 extern "C" int rsv_aggregate_restricted_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,

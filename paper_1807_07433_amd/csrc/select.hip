@@ -165,6 +165,18 @@ int run_select(const float* agg_ref, const float* agg_tar, int32_t height, int32
 
 }  // namespace rsv
 
+extern "C" int rsv_lr_check(const int32_t* disp_ref, const int32_t* disp_tar, int32_t height, int32_t width,
+                            int32_t tau, uint8_t* valid, void* stream) {
+  using namespace rsv;
+  if (!disp_ref || !disp_tar || !valid) return RSV_E_NULL;
+  if (!aligned(disp_ref, 4) || !aligned(disp_tar, 4)) return RSV_E_ALIGN;
+  if (height < 1 || width < 1) return RSV_E_SHAPE;
+  if (tau < 0) return RSV_E_PARAM;
+  const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
+  lr_check_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(disp_ref, disp_tar, width, tau, valid);
+  return check_launch();
+}
+
 extern "C" int rsv_select_subpixel(const float* agg_ref, const float* agg_tar, int32_t height,
                                    int32_t width, const rsv_params* p, int32_t* disp_ref,
                                    int32_t* disp_tar, float* disp_sub, uint8_t* valid, float* top2,
