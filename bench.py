@@ -549,13 +549,14 @@ def accuracy_block(case, cam, xyz):
 
 def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_full):
     """The restricted search of Sec. IV on the same frame: calculated disparities of
-    both views (rsv_cost_argmax on the joint volume's views), then the target argmax
-    and the reference aggregation with the selection folded in, each over windows of
-    2r + 1 disparities, for r = 2, 4, 8.  Per radius: stage times, the rate over cost +
-    calculated disparities + both aggregations (the full method's W*H*D in the
-    numerator, so it compares with `value`), agreement with the full method, and the
-    accuracy of both against the generator's ground truth (mean |d_f - d_gt| over the
-    pixels each keeps valid, away from the borders)."""
+    both views (rsv_cost_argmax on the joint volume's views), then both views'
+    aggregations over windows of 2r + 1 disparities in one launch with the selection
+    folded in, and the left-right check, for r = 2, 4, 8.  Per radius: stage times,
+    the rate over cost + calculated disparities + both aggregations with the check
+    (the full method's W*H*D in the numerator, so it compares with `value`),
+    agreement with the full method, and the accuracy of both against the generator's
+    ground truth (mean |d_f - d_gt| over the pixels each keeps valid, away from the
+    borders)."""
     import numpy as np
     p, prm = case.pair, case.params
     H, W = p.left.shape
@@ -566,11 +567,12 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
     joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
     cref, ctar = rsv.joint_views(joint, W)
     i32 = dict(dtype=torch.int32, device=dev)
-    cc_ref, cc_tar, dtar = torch.empty((H, W), **i32), torch.empty((H, W), **i32), torch.empty((H, W), **i32)
-    sel = {"disp_ref": torch.empty((H, W), **i32), "disp_sub": torch.empty((H, W), **f32),
+    cc_ref, cc_tar = torch.empty((H, W), **i32), torch.empty((H, W), **i32)
+    sel = {"disp_ref": torch.empty((H, W), **i32), "disp_tar": torch.empty((H, W), **i32),
+           "disp_sub": torch.empty((H, W), **f32),
            "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
     dfin, xyz = torch.empty((H, W), **f32), torch.empty((H, W, 3), **f32)
-    stages = ["warp", "cost_volume", "cost_argmax", "aggregate_tar", "aggregate_ref", "triangulate"]
+    stages = ["warp", "cost_volume", "cost_argmax", "aggregate_views", "lr_check", "triangulate"]
     gt = p.disp_gt
     edge = prm.block_radius + prm.agg_radius
     inner = np.zeros((H, W), bool)
@@ -599,9 +601,9 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
             rsv.cost_argmax(cref, out=cc_ref)
             rsv.cost_argmax(ctar, out=cc_tar)
             mark()
-            rsv.aggregate_restricted_argmax(ctar, wp, prm, cc_tar, radius, out=dtar)
+            rsv.aggregate_restricted_views(cref, ctar, L, wp, prm, cc_ref, cc_tar, radius, out=sel)
             mark()
-            rsv.aggregate_restricted_select(cref, L, prm, cc_ref, radius, dtar, out=sel)
+            rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
             mark()
             rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
             mark()
@@ -613,7 +615,7 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
             step(evs[i])
         torch.cuda.synchronize()
         st = {k: sum(e[j].elapsed_time(e[j + 1]) for e in evs) / a.steps for j, k in enumerate(stages)}
-        t_ca = st["cost_volume"] + st["cost_argmax"] + st["aggregate_tar"] + st["aggregate_ref"]
+        t_ca = st["cost_volume"] + st["cost_argmax"] + agg_stage_ms(st)
         frame = sum(st.values())
         acc = accuracy(dfin.cpu().numpy().astype(np.float64), sel["valid"].cpu().numpy().astype(bool))
         mm = accuracy_block(case, cam, xyz) if case.pair.extra.get("bumps") else {}
@@ -625,7 +627,7 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
             "ms_per_frame": round(frame, 5),
             "speedup_cost_plus_agg_vs_full": round(out["full"]["cost_plus_agg_ms"] / t_ca, 3),
             "disp_ref_equal_to_full": round(float((sel["disp_ref"] == full_sel["disp_ref"]).float().mean()), 5),
-            "disp_tar_equal_to_full": round(float((dtar == full_sel["disp_tar"]).float().mean()), 5),
+            "disp_tar_equal_to_full": round(float((sel["disp_tar"] == full_sel["disp_tar"]).float().mean()), 5),
             "valid_equal_to_full": round(float((sel["valid"] == full_sel["valid"]).float().mean()), 5),
             "mean_abs_err_px": acc[0], "valid_frac": acc[1]}
     return out

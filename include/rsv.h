@@ -281,6 +281,22 @@ int rsv_aggregate_restricted_select(const float* cost, int64_t plane_stride, int
                                     int32_t radius, const int32_t* disp_tar, int32_t* disp_ref,
                                     float* disp_sub, uint8_t* valid, void* stream);
 
+/* Both views' restricted aggregations in one launch, as rsv_aggregate_views does for
+ * the full range: the target view's winner inside each pixel's window around
+ * coarse_tar (rsv_aggregate_restricted_argmax's disp), the reference view's winner
+ * inside its window around coarse_ref and Eq. 12 on it (rsv_aggregate_restricted_
+ * select's disp_ref and disp_sub), bit for bit; the left-right check is rsv_lr_check's.
+ *   cost_ref / cost_tar, guide_ref / guide_tar  as rsv_aggregate_views
+ *   coarse_ref, coarse_tar  int32 [H][W], read;  radius >= 0
+ *   disp_tar, disp_ref out, int32 [H][W];  disp_sub out, float32 [H][W]
+ * Errors: as rsv_aggregate_views; RSV_E_NULL and RSV_E_ALIGN also for the coarse maps,
+ * RSV_E_PARAM also for radius < 0. */
+int rsv_aggregate_restricted_views(const float* cost_ref, int64_t ref_plane_stride, int64_t ref_row_stride,
+                                   const float* cost_tar, int64_t tar_plane_stride, int64_t tar_row_stride,
+                                   rsv_image guide_ref, rsv_image guide_tar, const rsv_params* p,
+                                   const int32_t* coarse_ref, const int32_t* coarse_tar, int32_t radius,
+                                   int32_t* disp_tar, int32_t* disp_ref, float* disp_sub, void* stream);
+
 /* Road-plane estimation (Sec. II-A): the plane of disparities d = a0 + a1 v + a2 u
  * that the warp of Eq. 2 uses (a0, a1 as in Eq. 2; a2 the term of the roll-fitted
  * plane), fitted by least squares inside RANSAC to the valid pixels of a disparity

@@ -358,6 +358,118 @@ __global__ __launch_bounds__(1024) void aggregate_restricted_select_kernel(
   valid[i] = (x >= 0 && abs(a - dtar[row + (x < 0 ? 0 : x)]) <= tau) ? 1 : 0;
 }
 
+// Both views' restricted aggregations in one launch, in aggregate_views_kernel's
+// item order: reference tiles as aggregate_restricted_select_kernel without Eq. 11
+// (winner in the window and Eq. 12), target tiles as the restricted argmax.
+template <int A, typename TGR>
+__global__ __launch_bounds__(1024) void aggregate_restricted_views_kernel(
+    const float* __restrict__ cref, int64_t rps, int rrs, const float* __restrict__ ctar, int64_t tps, int trs,
+    const TGR* __restrict__ gref, int64_t grp, const float* __restrict__ gtar, int64_t gtp, int H, int W, int D,
+    BilateralK bk, const int32_t* __restrict__ coarse_ref, const int32_t* __restrict__ coarse_tar, int radius,
+    int width, int32_t* __restrict__ dtar, int32_t* __restrict__ dref, float* __restrict__ dsub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_range[2];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int k = xcd_run_item<kViewsXcdRun>(blockIdx.x, 2 * tiles_x * tiles_y);
+  const int ty = k / (2 * tiles_x), r = k - ty * 2 * tiles_x;
+  const bool ref = r < tiles_x;  // uniform per block
+  const int by = ty * 16, bx = (ref ? r : r - tiles_x) * 16;
+  int lo, hi, t_first, t_count;
+  restricted_tiles(ref ? coarse_ref : coarse_tar, H, W, D, radius, width, by, bx, s_range, lo, hi, t_first,
+                   t_count);
+  if (t_count <= 0) return;  // no pixel of the block in the image
+  if (ref) {
+    auto guide_at = [&](int Y, int X) { return pixel(gref, grp, Y, X); };
+    RefQuadSink sink{D};
+    sink.lo = lo;
+    sink.hi = hi;
+    agg_tile_dma<A>(cref, rps, rrs, H, W, D, bk, by, bx, guide_at, sink, smem, lds_address(smem), t_first,
+                    t_count);
+    const int q = threadIdx.x >> 2;
+    const int Y = by + (q >> 4), X = bx + (q & 15);
+    if ((threadIdx.x & 3) == 0 && Y < H && X < W) {
+      const int64_t i = static_cast<int64_t>(Y) * W + X;
+      dref[i] = sink.arg;
+      dsub[i] = parabola(sink.arg, sink.best, sink.am, sink.ap, D);
+    }
+  } else {
+    auto guide_at = [&](int Y, int X) { return pixel(gtar, gtp, Y, X); };
+    ArgmaxSink sink{D};
+    sink.lo = lo;
+    sink.hi = hi;
+    agg_tile_dma<A>(ctar, tps, trs, H, W, D, bk, by, bx, guide_at, sink, smem, lds_address(smem), t_first,
+                    t_count);
+    sink.finish(dtar, H, W, by, bx);
+  }
+}
+
+template <int A, typename TGR>
+int launch_restricted_views(const float* cref, int64_t rps, int rrs, const float* ctar, int64_t tps, int trs,
+                            const rsv_image& gr, const rsv_image& gt, const rsv_params* p, const int32_t* cc_ref,
+                            const int32_t* cc_tar, int radius, int32_t* dtar, int32_t* dref, float* dsub,
+                            hipStream_t st) {
+  if constexpr (agg_dma_fits<A>()) {
+    const int tiles = ((gr.width + 15) / 16) * ((gr.height + 15) / 16);
+    const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+    const size_t lds = agg_tile_dma_lds_bytes<A>();
+    const int width = 2 * radius + 1 < p->D ? 2 * radius + 1 : p->D;
+    auto kern = aggregate_restricted_views_kernel<A, TGR>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return RSV_E_HIP;
+    }
+    kern<<<dim3(2 * tiles), dim3(1024), lds, st>>>(cref, rps, rrs, ctar, tps, trs, static_cast<const TGR*>(gr.data),
+                                                   gr.pitch, static_cast<const float*>(gt.data), gt.pitch, gr.height,
+                                                   gr.width, p->D, bk, cc_ref, cc_tar, radius, width, dtar, dref,
+                                                   dsub);
+    return check_launch();
+  } else {
+    return RSV_E_PARAM;
+  }
+}
+
+template <typename TGR>
+int dispatch_restricted_views(const float* cref, int64_t rps, int rrs, const float* ctar, int64_t tps, int trs,
+                              const rsv_image& gr, const rsv_image& gt, const rsv_params* p, const int32_t* cc_ref,
+                              const int32_t* cc_tar, int radius, int32_t* dtar, int32_t* dref, float* dsub,
+                              hipStream_t st) {
+#define RSV_RV(A) \
+  launch_restricted_views<A, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, cc_ref, cc_tar, radius, dtar, dref, dsub, st)
+  switch (p->agg_radius) {
+    case 1: return RSV_RV(1);
+    case 2: return RSV_RV(2);
+    case 3: return RSV_RV(3);
+    case 4: return RSV_RV(4);
+    case 5: return RSV_RV(5);
+    default: return RSV_E_PARAM;
+  }
+#undef RSV_RV
+}
+
+// Argument checks shared by the two-view entry points.
+int validate_views(const float* cost_ref, int64_t rps, int64_t rrs, const float* cost_tar, int64_t tps, int64_t trs,
+                   const rsv_image& gr, const rsv_image& gt, const rsv_params* p, const int32_t* dtar,
+                   const int32_t* dref, const float* dsub) {
+  if (int s = validate_image(gr)) return s;
+  if (int s = validate_image(gt)) return s;
+  if (int s = validate_agg_params(p)) return s;
+  if (int s = validate_select_params(p)) return s;
+  if (!cost_ref || !cost_tar || !dtar || !dref || !dsub) return RSV_E_NULL;
+  if (!aligned(cost_ref, 4) || !aligned(cost_tar, 4) || !aligned(dtar, 4) || !aligned(dref, 4) || !aligned(dsub, 4))
+    return RSV_E_ALIGN;
+  if (gt.dtype != RSV_F32) return RSV_E_DTYPE;
+  if (p->agg_radius > 5) return RSV_E_PARAM;
+  if (gt.width != gr.width || gt.height != gr.height) return RSV_E_SHAPE;
+  const int64_t H = gr.height, W = gr.width;
+  for (int64_t rs : {rrs, trs})
+    if (W < 4 || rs < W || (H - 1) * rs + W > kAggMaxPixels) return RSV_E_SHAPE;
+  for (int64_t ps : {rps, tps})
+    if (ps < 1 || ps > kAggMaxPixels) return RSV_E_SHAPE;
+  return RSV_OK;
+}
+
 template <int A, typename TG, bool SEL>
 int launch_restricted(const float* cost, int64_t cps, int crs, const rsv_image& g, const rsv_params* p,
                       const int32_t* coarse, int radius, const int32_t* dtar, int32_t* dref, float* dsub,
@@ -538,22 +650,9 @@ extern "C" int rsv_aggregate_views(const float* cost_ref, int64_t ref_plane_stri
                                    rsv_image guide_ref, rsv_image guide_tar, const rsv_params* p,
                                    int32_t* disp_tar, int32_t* disp_ref, float* disp_sub, void* stream) {
   using namespace rsv;
-  if (int s = validate_image(guide_ref)) return s;
-  if (int s = validate_image(guide_tar)) return s;
-  if (int s = validate_agg_params(p)) return s;
-  if (int s = validate_select_params(p)) return s;
-  if (!cost_ref || !cost_tar || !disp_tar || !disp_ref || !disp_sub) return RSV_E_NULL;
-  if (!aligned(cost_ref, 4) || !aligned(cost_tar, 4) || !aligned(disp_tar, 4) || !aligned(disp_ref, 4) ||
-      !aligned(disp_sub, 4))
-    return RSV_E_ALIGN;
-  if (guide_tar.dtype != RSV_F32) return RSV_E_DTYPE;
-  if (p->agg_radius > 5) return RSV_E_PARAM;
-  if (guide_tar.width != guide_ref.width || guide_tar.height != guide_ref.height) return RSV_E_SHAPE;
-  const int64_t H = guide_ref.height, W = guide_ref.width;
-  for (int64_t rs : {ref_row_stride, tar_row_stride})
-    if (W < 4 || rs < W || (H - 1) * rs + W > kAggMaxPixels) return RSV_E_SHAPE;
-  for (int64_t ps : {ref_plane_stride, tar_plane_stride})
-    if (ps < 1 || ps > kAggMaxPixels) return RSV_E_SHAPE;
+  if (int s = validate_views(cost_ref, ref_plane_stride, ref_row_stride, cost_tar, tar_plane_stride, tar_row_stride,
+                             guide_ref, guide_tar, p, disp_tar, disp_ref, disp_sub))
+    return s;
   hipStream_t st = as_stream(stream);
   const int rrs = static_cast<int>(ref_row_stride), trs = static_cast<int>(tar_row_stride);
   if (guide_ref.dtype == RSV_U8)
@@ -561,6 +660,30 @@ extern "C" int rsv_aggregate_views(const float* cost_ref, int64_t ref_plane_stri
                                        guide_tar, p, disp_tar, disp_ref, disp_sub, st);
   return dispatch_agg_views<float>(cost_ref, ref_plane_stride, rrs, cost_tar, tar_plane_stride, trs, guide_ref,
                                    guide_tar, p, disp_tar, disp_ref, disp_sub, st);
+}
+
+extern "C" int rsv_aggregate_restricted_views(const float* cost_ref, int64_t ref_plane_stride,
+                                              int64_t ref_row_stride, const float* cost_tar,
+                                              int64_t tar_plane_stride, int64_t tar_row_stride, rsv_image guide_ref,
+                                              rsv_image guide_tar, const rsv_params* p, const int32_t* coarse_ref,
+                                              const int32_t* coarse_tar, int32_t radius, int32_t* disp_tar,
+                                              int32_t* disp_ref, float* disp_sub, void* stream) {
+  using namespace rsv;
+  if (int s = validate_views(cost_ref, ref_plane_stride, ref_row_stride, cost_tar, tar_plane_stride, tar_row_stride,
+                             guide_ref, guide_tar, p, disp_tar, disp_ref, disp_sub))
+    return s;
+  if (!coarse_ref || !coarse_tar) return RSV_E_NULL;
+  if (!aligned(coarse_ref, 4) || !aligned(coarse_tar, 4)) return RSV_E_ALIGN;
+  if (radius < 0) return RSV_E_PARAM;
+  hipStream_t st = as_stream(stream);
+  const int rrs = static_cast<int>(ref_row_stride), trs = static_cast<int>(tar_row_stride);
+  if (guide_ref.dtype == RSV_U8)
+    return dispatch_restricted_views<uint8_t>(cost_ref, ref_plane_stride, rrs, cost_tar, tar_plane_stride, trs,
+                                              guide_ref, guide_tar, p, coarse_ref, coarse_tar, radius, disp_tar,
+                                              disp_ref, disp_sub, st);
+  return dispatch_restricted_views<float>(cost_ref, ref_plane_stride, rrs, cost_tar, tar_plane_stride, trs, guide_ref,
+                                          guide_tar, p, coarse_ref, coarse_tar, radius, disp_tar, disp_ref, disp_sub,
+                                          st);
 }
 
 extern "C" int rsv_aggregate_restricted_argmax(const float* cost, int64_t plane_stride, int64_t row_stride,

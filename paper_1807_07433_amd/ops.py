@@ -247,6 +247,43 @@ def aggregate_views(cost_ref: torch.Tensor, cost_tar: torch.Tensor, guide_ref: t
     return o
 
 
+def aggregate_restricted_views(cost_ref: torch.Tensor, cost_tar: torch.Tensor, guide_ref: torch.Tensor,
+                               guide_tar: torch.Tensor, params, coarse_ref: torch.Tensor, coarse_tar: torch.Tensor,
+                               radius: int, out: dict | None = None) -> dict:
+    """Both views' restricted aggregations in one launch (rsv_aggregate_restricted_views):
+    disp_tar, disp_ref and disp_sub as aggregate_restricted_argmax and
+    aggregate_restricted_select give them, bit for bit; the left-right check is
+    lr_check's."""
+    lib = load()
+    D, H, W = cost_ref.shape
+    for t, n in ((cost_ref, "cost_ref"), (cost_tar, "cost_tar")):
+        _dev(t, n, torch.float32, (int(params.D), H, W))
+        if t.stride(2) != 1:
+            raise ValueError(f"{n}: cost views need unit column stride")
+    for g, n in ((guide_ref, "guide_ref"), (guide_tar, "guide_tar")):
+        if tuple(g.shape) != (H, W):
+            raise ValueError(f"{n} must match the volume's H, W")
+    _contig(coarse_ref, "coarse_ref", torch.int32, (H, W))
+    _contig(coarse_tar, "coarse_tar", torch.int32, (H, W))
+    dev = cost_ref.device
+    o = dict(out) if out else {}
+    shapes = {"disp_tar": ((H, W), torch.int32), "disp_ref": ((H, W), torch.int32),
+              "disp_sub": ((H, W), torch.float32)}
+    for k, (shp, dt) in shapes.items():
+        if k not in o:
+            o[k] = torch.empty(shp, dtype=dt, device=dev)
+        _contig(o[k], k, dt, shp)
+    p = _params(params)
+    check(lib.rsv_aggregate_restricted_views(cost_ref.data_ptr(), cost_ref.stride(0), cost_ref.stride(1),
+                                             cost_tar.data_ptr(), cost_tar.stride(0), cost_tar.stride(1),
+                                             image(guide_ref, "guide_ref"), image(guide_tar, "guide_tar"), C.byref(p),
+                                             coarse_ref.data_ptr(), coarse_tar.data_ptr(), int(radius),
+                                             o["disp_tar"].data_ptr(), o["disp_ref"].data_ptr(),
+                                             o["disp_sub"].data_ptr(), _stream(dev)),
+          "rsv_aggregate_restricted_views")
+    return o
+
+
 def lr_check(disp_ref: torch.Tensor, disp_tar: torch.Tensor, tau: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """Eq. 11 on two winner-take-all maps (rsv_lr_check): uint8 valid [H][W]."""
     lib = load()
@@ -327,15 +364,17 @@ def aggregate_restricted_select(cost: torch.Tensor, guide: torch.Tensor, params,
 def reconstruct_restricted(left: torch.Tensor, right: torch.Tensor, plane, camera, params, radius: int,
                            out: dict | None = None) -> dict:
     """The plain path with the restricted search of Sec. IV: warp -> joint cost volume ->
-    calculated disparities of both views (rsv_cost_argmax) -> target argmax and the
-    reference aggregation with the selection folded in, each over the windows of
-    min(2 radius + 1, D) disparities -> post-processing + 3-D points."""
+    calculated disparities of both views (rsv_cost_argmax) -> both views' aggregations
+    over the windows of min(2 radius + 1, D) disparities in one launch, with the
+    selection folded in (rsv_aggregate_restricted_views) -> left-right check ->
+    post-processing + 3-D points."""
     wp = warp(right, plane)
     cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
     cc_ref = cost_argmax(cref)
     cc_tar = cost_argmax(ctar)
-    dtar = aggregate_restricted_argmax(ctar, wp, params, cc_tar, radius)
-    sel = aggregate_restricted_select(cref, left, params, cc_ref, radius, dtar, out=out)
+    sel = aggregate_restricted_views(cref, ctar, left, wp, params, cc_ref, cc_tar, radius, out=out)
+    sel["valid"] = lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold,
+                            out=(out or {}).get("valid"))
     dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)
     res = dict(warped=wp, cost_ref=cref, cost_tar=ctar, coarse_ref=cc_ref, coarse_tar=cc_tar,
                disp_final=dfin, xyz=xyz)
@@ -544,7 +583,7 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
-           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select", "aggregate_views", "lr_check",
+           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select", "aggregate_views", "aggregate_restricted_views", "lr_check",
            "aggregate_select_supported", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "selected_aggregate_sum", "cost_adjoint",
            "cost_argmax", "aggregate_restricted_argmax", "aggregate_restricted_select", "reconstruct_restricted",

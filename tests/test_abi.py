@@ -248,6 +248,20 @@ def test_aggregate_views_and_lr_check_validation(lib):
     assert call(a8=C.byref(_params(agg_radius=6))) == -3
     assert call(a6=_img(w=3), a7=_img(w=3, dtype=1), a2=3, a5=3, a1=96, a4=97) == -2  # W < 4
     assert call(a8=C.byref(_params(lr_threshold=-1))) == -3
+    rv = lib.rsv_aggregate_restricted_views
+    args = list(ok[:9]) + [B, Cc, 2] + list(ok[9:])  # valid: never called, each case breaks one argument
+    bad = list(args)
+    bad[9] = None
+    assert rv(*bad) == -1                                          # coarse_ref
+    bad = list(args)
+    bad[10] = Cc + 2
+    assert rv(*bad) == -5                                          # coarse_tar misaligned
+    bad = list(args)
+    bad[11] = -1
+    assert rv(*bad) == -3                                          # radius < 0
+    bad = list(args)
+    bad[7] = _img()
+    assert rv(*bad) == -4                                          # target guide must be float32
     lr = lib.rsv_lr_check
     assert lr(None, B, 32, 48, 1, Cc, None) == -1
     assert lr(A, B, 32, 48, 1, None, None) == -1

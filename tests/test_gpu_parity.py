@@ -231,6 +231,21 @@ def test_flat_images_give_zero_costs_and_lowest_d(rsv_gpu):
     assert torch.all(out["disp_sub"] == 0)
 
 
+@pytest.mark.parametrize("H,W,D,tau,seed", [(1, 1, 1, 0, 1), (7, 300, 40, 0, 2), (33, 65, 64, 1, 3),
+                                             (720, 1280, 64, 1, 4)])
+def test_lr_check_against_oracle(rsv_gpu, H, W, D, tau, seed):
+    """rsv_lr_check on random winner maps (values up to D, so matches fall left of the
+    image too) against the oracle's Eq. 11, every pixel, bit for bit."""
+    rng = np.random.default_rng(seed)
+    dref = rng.integers(0, D, (H, W), dtype=np.int32)
+    dtar = np.where(rng.random((H, W)) < 0.5, dref, rng.integers(0, D, (H, W))).astype(np.int32)
+    _say(f"[lr_check] {W}x{H} D={D} tau={tau}")
+    valid = rsv_gpu.lr_check(_gpu(dref), _gpu(dtar), tau)
+    torch.cuda.synchronize()
+    ref = S.lr_check(dref, dtar, tau)
+    assert np.array_equal(P.to_np(valid).astype(bool), ref)
+
+
 def test_rerun_is_bitwise_deterministic(rsv_gpu):
     rsv = rsv_gpu
     case = synth.small_case(50, 170, 24, 3, 5, 31)

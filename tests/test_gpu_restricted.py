@@ -106,6 +106,29 @@ def test_full_range_window_equals_full_method_bitwise(rsv_gpu, H, W, D, r, rho, 
         assert torch.equal(res[k].nan_to_num(), full[k].nan_to_num()), k
 
 
+@pytest.mark.parametrize("H,W,D,r,rho,seed,radius", CASES)
+def test_two_view_launch_equals_two_launches(rsv_gpu, H, W, D, r, rho, seed, radius):
+    """rsv_aggregate_restricted_views + rsv_lr_check give the outputs of
+    rsv_aggregate_restricted_argmax followed by rsv_aggregate_restricted_select, bit
+    for bit (u8 left image; and float32 images)."""
+    rsv = rsv_gpu
+    case = synth.small_case(H, W, D, r, rho, seed)
+    prm = case.params
+    for L, R in ((_gpu(case.pair.left), _gpu(case.pair.right)),
+                 (_gpu(case.pair.left.astype(np.float32)), _gpu(case.pair.right.astype(np.float32)))):
+        _say(f"[restricted] two-view launch H={H} W={W} D={D} radius={radius} {L.dtype}")
+        wp = rsv.warp(R, case.plane)
+        cref, ctar = rsv.joint_views(rsv.cost_volume_joint(L, wp, prm), W)
+        cc_ref, cc_tar = rsv.cost_argmax(cref), rsv.cost_argmax(ctar)
+        dtar = rsv.aggregate_restricted_argmax(ctar, wp, prm, cc_tar, radius)
+        sel = rsv.aggregate_restricted_select(cref, L, prm, cc_ref, radius, dtar)
+        vw = rsv.aggregate_restricted_views(cref, ctar, L, wp, prm, cc_ref, cc_tar, radius)
+        assert torch.equal(vw["disp_tar"], dtar)
+        for k in ("disp_ref", "disp_sub"):
+            assert torch.equal(vw[k], sel[k]), k
+        assert torch.equal(rsv.lr_check(vw["disp_ref"], vw["disp_tar"], prm.lr_threshold), sel["valid"])
+
+
 def test_road1280_d64_agrees_with_full_inside_windows(rsv_gpu):
     """1280x720, D = 64: wherever the full method's winner lies inside the pixel's
     window, the restricted winner is the same (the window's values are the same
