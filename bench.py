@@ -150,8 +150,8 @@ def agg_entry(stage_ms, key, W, H, D, prm, fused):
     for both views' entries in the two-view launch (key "aggregate_views").  Also its
     HBM rate (4 B per entry read; 4 B written as well where an unfused reference launch
     writes its volume), the matrix-core work it issues (3 split-fp16 MFMAs per K-step
-    over the padded window union) against the fp16 matrix peak, and its LDS traffic
-    from the tile's design."""
+    and disparity tile over the padded window union, 2 per K-step for the weight sums)
+    against the fp16 matrix peak, and its LDS traffic from the tile's design."""
     views = 2 if key == "aggregate_views" else 1
     n = W * H * D * views
     m = (2 * prm.agg_radius + 1) ** 2
@@ -159,7 +159,8 @@ def agg_entry(stage_ms, key, W, H, D, prm, fused):
     flops = (2 * m + 2) * n
     tf = flops / (ms * 1e-3) / 1e12
     tiles = ((W + 15) // 16) * ((H + 15) // 16)
-    issued = views * tiles * ((D + 15) // 16) * 16 * (2 + prm.agg_radius) * 3 * (16 * 16 * 32 * 2)
+    # per block and view: 16 waves x KS K-steps x (3 split MFMAs per disparity tile + 2 for the weight sums)
+    issued = views * tiles * 16 * (2 + prm.agg_radius) * (3 * ((D + 15) // 16) + 2) * (16 * 16 * 32 * 2)
     itf = issued / (ms * 1e-3) / 1e12
     writes = key == "aggregate_ref" and not fused
     gbs = (8 if writes else 4) * n / (ms * 1e-3) / 1e9

@@ -73,15 +73,11 @@ __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, co
   const float gp = pin ? gt[(4 * pp.pr + py + A) * G::TC + 4 * pp.pc + px + A + G::PAD] : 0.f;
   const float* gq = gt + (4 * pp.pr + (g >> 1)) * G::TC + 4 * pp.pc + 8 * (g & 1);
   const float* sk = skt + ((g >> 1) - py + 3) * G::SKC + 8 * (g & 1) - px + 3;
-  float z = 0.f;
 #pragma unroll
   for (int s = 0; s < G::KS; ++s) {
     float wt[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      wt[e] = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e]);
-      z += wt[e];
-    }
+    for (int e = 0; e < 8; ++e) wt[e] = bilateral_weight_s(gq[2 * s * G::TC + e], gp, sk[2 * s * G::SKC + e]);
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
       half2_t h, l;
@@ -92,15 +88,22 @@ __device__ __forceinline__ float4_t patch_weights(half8_t* whi, half8_t* wlo, co
       wlo[s][e + 1] = l[1];
     }
   }
-  // the four lanes holding pixel i cover disjoint K ranges: sum them
-  z += __shfl_xor(z, 16);
-  z += __shfl_xor(z, 32);
+  // Each pixel's weight sum (Eq. 8's normaliser) as the product of its weights with a
+  // matrix of ones, on the matrix pipe, which is idle while the weights are computed:
+  // sum of hi + lo over the window, the same split weights the products use.  Lane l
+  // ends with the sums of pixels 4 (l >> 4) + e, the layout of the tile's accumulator.
+  half8_t ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = static_cast<_Float16>(1.f);
+  float4_t za = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < G::KS; ++s) {
+    za = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi[s], ones, za, 0, 0, 0);
+    za = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo[s], ones, za, 0, 0, 0);
+  }
   float4_t iz;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const float ze = __shfl(z, 4 * g + e);
-    iz[e] = ze > 0.f ? 1.f / ze : 0.f;
-  }
+  for (int e = 0; e < 4; ++e) iz[e] = za[e] > 0.f ? 1.f / za[e] : 0.f;
   return iz;
 }
 

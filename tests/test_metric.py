@@ -38,7 +38,8 @@ def test_kernel_roofline_units():
     # the unfused reference launch also writes its volume
     assert abs(agg["hbm_view"]["achieved_gbs"] - 8 * n / 0.2e-3 / 1e9) < 0.1
     # issued matrix work: 80 x 45 tiles, 4 disparity tiles, 16 patches, 7 K-steps, 3 MFMAs
-    assert agg["mfma_view"]["issued_flops_per_launch"] == 80 * 45 * 4 * 16 * 7 * 3 * 16384
+    # per block: 16 waves x 7 K-steps x (3 MFMAs x 4 disparity tiles + 2 for the weight sums)
+    assert agg["mfma_view"]["issued_flops_per_launch"] == 80 * 45 * 16 * 7 * (3 * 4 + 2) * 16384
 
 
 def test_kernel_sha_covers_every_source():
