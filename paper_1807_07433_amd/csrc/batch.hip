@@ -799,8 +799,8 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       hipSuccess)
     return fail(e);
   int dev = 0, cus = 0, cost_fit = 0, agg_fit = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(e);
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return fail(e);
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cost_fit, ck, kCostThreads, cost_lds)) != hipSuccess)
     return fail(e);
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&agg_fit, ak, kAggItemThreads, agg_lds)) != hipSuccess)
@@ -850,12 +850,17 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   }
   if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return fail(e);
+  hipError_t cap = hipSuccess;  // first failure while capturing; the capture is ended either way
+  auto note = [&](hipError_t r) {
+    if (r != hipSuccess && cap == hipSuccess) cap = r;
+  };
   batch_reset_kernel<<<1, 256, 0, plan->capture_stream>>>(plan->d_heads, kHB * n_groups);
   const int tail_x = std::min(1024, (max_pixels + 255) / 256);
   batch_warp_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs);
+  note(hipGetLastError());
   if (n_groups > 1) {
-    hipEventRecord(plan->fork, plan->capture_stream);
-    hipStreamWaitEvent(plan->capture_stream2, plan->fork, 0);
+    note(hipEventRecord(plan->fork, plan->capture_stream));
+    note(hipStreamWaitEvent(plan->capture_stream2, plan->fork, 0));
   }
   for (int g = 0; g < n_groups; ++g) {
     hipStream_t gs = (g & 1) ? plan->capture_stream2 : plan->capture_stream;
@@ -871,43 +876,43 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
         PairDev Pc = pd[order[k]];
         float sm = p->sigma_min;
         void* cargs[] = {&Pc, &sm};
-        hipLaunchKernel(pck, dim3(Pc.nbands * Pc.ncol_tiles), dim3(kCostThreads), cargs, cost_lds, gs);
+        note(hipLaunchKernel(pck, dim3(Pc.nbands * Pc.ncol_tiles), dim3(kCostThreads), cargs, cost_lds, gs));
         if (tile_end[k] > tile_beg[k]) {  // all of the pair's tiles, both views
           PairDev P = pd[order[k]];
           BilateralK bk = ca.bk;
           void* pargs[] = {&P, &bk};
-          hipLaunchKernel(ptk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), pargs, tile_lds, gs);
+          note(hipLaunchKernel(ptk, dim3(tile_end[k] - tile_beg[k]), dim3(1024), pargs, tile_lds, gs));
         }
       }
       if (agg_blocks(g) > 0) {
         void* aargs[] = {&a};
-        hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs);
+        note(hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs));
       }
     } else {
       if (cost_grid_mode) c.items += g_cost[g];  // one workgroup per item of the group
       void* cargs[] = {&c};
       if (cost_blocks(g) > 0)
-        hipLaunchKernel(ck, dim3(cost_blocks(g)), dim3(kCostThreads), cargs, cost_lds, gs);
+        note(hipLaunchKernel(ck, dim3(cost_blocks(g)), dim3(kCostThreads), cargs, cost_lds, gs));
       if (agg_blocks(g) > 0) {
         void* aargs[] = {&a};
-        hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs);
+        note(hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs));
       }
       if (g_tile[g + 1] > g_tile[g]) {
         BatchArgs t = ta;
         t.items += g_tile[g];
         void* targs[] = {&t};
-        hipLaunchKernel(tk, dim3(g_tile[g + 1] - g_tile[g]), dim3(1024), targs, tile_lds, gs);
+        note(hipLaunchKernel(tk, dim3(g_tile[g + 1] - g_tile[g]), dim3(1024), targs, tile_lds, gs));
       }
     }
   }
   if (n_groups > 1) {
-    hipEventRecord(plan->join, plan->capture_stream2);
-    hipStreamWaitEvent(plan->capture_stream, plan->join, 0);
+    note(hipEventRecord(plan->join, plan->capture_stream2));
+    note(hipStreamWaitEvent(plan->capture_stream, plan->join, 0));
   }
   batch_tail_kernel<<<dim3(tail_x, n), 256, 0, plan->capture_stream>>>(plan->d_pairs, p->lr_threshold);
-  hipError_t le = hipGetLastError();
+  note(hipGetLastError());
   e = hipStreamEndCapture(plan->capture_stream, &plan->graph);
-  if (le != hipSuccess) return fail(le);
+  if (cap != hipSuccess) return fail(cap);
   if (e != hipSuccess) return fail(e);
   if ((e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0)) != hipSuccess) return fail(e);
   *out = plan;
@@ -938,7 +943,7 @@ extern "C" int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items,
   }
   if (workspace_bytes) {
     size_t sz = 0;
-    hipMemPtrGetInfo(plan->dev_mem, &sz);
+    if (hipMemPtrGetInfo(plan->dev_mem, &sz) != hipSuccess) sz = 0;
     *workspace_bytes = static_cast<int64_t>(sz);
   }
   return RSV_OK;
@@ -946,13 +951,14 @@ extern "C" int rsv_batch_plan_info(const rsv_batch_plan* plan, int32_t* n_items,
 
 extern "C" int rsv_batch_plan_destroy(rsv_batch_plan* plan) {
   if (!plan) return RSV_E_NULL;
-  if (plan->exec) hipGraphExecDestroy(plan->exec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
-  if (plan->capture_stream) hipStreamDestroy(plan->capture_stream);
-  if (plan->capture_stream2) hipStreamDestroy(plan->capture_stream2);
-  if (plan->fork) hipEventDestroy(plan->fork);
-  if (plan->join) hipEventDestroy(plan->join);
-  if (plan->dev_mem) hipFree(plan->dev_mem);
+  // teardown: failures here leave nothing to undo
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+  if (plan->capture_stream2) (void)hipStreamDestroy(plan->capture_stream2);
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
+  if (plan->join) (void)hipEventDestroy(plan->join);
+  if (plan->dev_mem) (void)hipFree(plan->dev_mem);
   delete plan;
   return RSV_OK;
 }
@@ -976,15 +982,18 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
       status = s;
       return 1e30f;
     }
-    rsv_batch_run(plan, st);  // warm-up
-    hipEventRecord(e0, st);
     const int reps = 3;
-    for (int r = 0; r < reps; ++r) rsv_batch_run(plan, st);
-    hipEventRecord(e1, st);
-    hipEventSynchronize(e1);
+    int run = rsv_batch_run(plan, st);  // warm-up
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    bool ok = run == RSV_OK && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r) ok = rsv_batch_run(plan, st) == RSV_OK;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     rsv_batch_plan_destroy(plan);
+    if (!ok) {
+      status = RSV_E_HIP;
+      return 1e30f;
+    }
     return ms / reps;
   };
   for (int lf = 0; lf <= 1; ++lf)
@@ -1018,8 +1027,8 @@ extern "C" int rsv_autotune(const rsv_pair_desc* pairs, int32_t n, const rsv_par
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (best_t >= 1e30f) return status != RSV_OK ? status : RSV_E_HIP;
   *out = best;
   if (best_ms) *best_ms = best_t;

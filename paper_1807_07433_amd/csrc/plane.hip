@@ -270,7 +270,9 @@ extern "C" int rsv_plane_ransac(const float* disp, const uint8_t* valid, int32_t
       disp, height, width, samples, K, ws.planes, counts, ws.sums);
   if (int s = check_launch()) return s;
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;  // only sizes the grid
   const int64_t n = static_cast<int64_t>(height) * width;
   const dim3 grid(static_cast<unsigned>((n + kPlaneBlockPix - 1) / kPlaneBlockPix),
                   (K + kPlaneChunk - 1) / kPlaneChunk);
