@@ -330,3 +330,47 @@ def test_plane_ransac_validation(lib):
     assert f(A, B, 32, 48, Cc, 16, float("nan"), Dd, E, F, G, None) == -3
     assert f(A + 2, B, 32, 48, Cc, 16, 0.5, Dd, E, F, G, None) == -5
     assert f(A, B, 32, 48, Cc, 16, 0.5, Dd + 4, E, F, G, None) == -5
+
+
+def test_batch_tuning_defaults_and_plan_validation(lib):
+    """rsv_tuning_default fills the documented defaults; rsv_batch_plan_create rejects
+    bad arguments before it allocates anything: nulls, an empty batch, tunings out of
+    range (a negative volume budget among them), float images, mismatched pair sizes,
+    D out of range."""
+    from paper_1807_07433_amd.batch import PairDesc, Tuning
+    t = Tuning()
+    lib.rsv_tuning_default(C.byref(t))
+    assert t.as_dict() == {"largest_first": 1, "cost_tiles_per_item": 2, "cost_blocks_per_cu": 0,
+                           "agg_blocks_per_cu": 0, "per_pair_launches": 1, "volume_budget_mib": 2048}
+    p = _params()
+
+    def pair(**kw):
+        d = PairDesc()
+        d.left = kw.get("left", _img(h=32, w=48))
+        d.right = kw.get("right", _img(h=32, w=48, data=FAKE + 8192))
+        d.plane = _lib.Plane(1.0, 0.1, 0.0, 2.0)
+        d.camera = _lib.Camera(1000.0, 0.3, 24.0, 16.0)
+        d.D = kw.get("D", 16)
+        d.disp_sub, d.valid = FAKE + 16384, FAKE + 20480
+        return d
+
+    def create(pairs, tuning=None, params=p):
+        arr = (PairDesc * len(pairs))(*pairs)
+        plan = C.c_void_p()
+        return lib.rsv_batch_plan_create(arr, len(pairs), C.byref(params),
+                                         C.byref(tuning) if tuning is not None else None, C.byref(plan))
+
+    plan = C.c_void_p()
+    assert lib.rsv_batch_plan_create(None, 1, C.byref(p), None, C.byref(plan)) == -1
+    arr = (PairDesc * 1)(pair())
+    assert lib.rsv_batch_plan_create(arr, 0, C.byref(p), None, C.byref(plan)) == -2
+    for field, bad in (("cost_tiles_per_item", 0), ("cost_tiles_per_item", 17), ("cost_blocks_per_cu", -2),
+                       ("agg_blocks_per_cu", -1), ("volume_budget_mib", -1)):
+        tb = Tuning()
+        lib.rsv_tuning_default(C.byref(tb))
+        setattr(tb, field, bad)
+        assert create([pair()], tb) == -3, field
+    assert create([pair(left=_img(h=32, w=48, dtype=_lib.RSV_F32))]) == -4
+    assert create([pair(right=_img(h=31, w=48, data=FAKE + 8192))]) == -2
+    assert create([pair(D=0)]) == -2 and create([pair(D=_lib.RSV_MAX_D + 1)]) == -2
+    assert create([pair()], params=_params(agg_radius=9)) == -3
