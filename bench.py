@@ -599,8 +599,7 @@ def bench_restricted(a, rsv, torch, case, L, R, cam, full_sel, full_dfin, stage_
             mark()
             rsv.cost_volume_joint(L, wp, prm, out=joint)
             mark()
-            rsv.cost_argmax(cref, out=cc_ref)
-            rsv.cost_argmax(ctar, out=cc_tar)
+            rsv.cost_argmax_views(cref, ctar, out=(cc_ref, cc_tar))
             mark()
             rsv.aggregate_restricted_views(cref, ctar, L, wp, prm, cc_ref, cc_tar, radius, out=sel)
             mark()

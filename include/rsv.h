@@ -261,6 +261,17 @@ int rsv_lr_check(const int32_t* disp_ref, const int32_t* disp_tar, int32_t heigh
 int rsv_cost_argmax(const float* cost, int64_t plane_stride, int64_t row_stride, int32_t height,
                     int32_t width, int32_t D, int32_t* disp, void* stream);
 
+/* rsv_cost_argmax of two views in one pass: disp_ref of cost_ref and disp_tar of
+ * cost_tar, each bit for bit rsv_cost_argmax's.  Where the two are views of one joint
+ * volume (rsv_cost_volume_joint), a thread reads entry (d, v, u) of both views, whose
+ * lines the other view's threads also read, so the volume is fetched about once.
+ *   disp_ref, disp_tar  out, int32 [H][W]
+ * Errors: as rsv_cost_argmax, for either view. */
+int rsv_cost_argmax_views(const float* cost_ref, int64_t ref_plane_stride, int64_t ref_row_stride,
+                          const float* cost_tar, int64_t tar_plane_stride, int64_t tar_row_stride,
+                          int32_t height, int32_t width, int32_t D, int32_t* disp_ref, int32_t* disp_tar,
+                          void* stream);
+
 /* rsv_aggregate_argmax restricted to each pixel's window around coarse[v][u]: the
  * first maximum over the window of the aggregation of Eq. 8-10.
  *   coarse  int32 [H][W], read (any values; clamped into the range as above)

@@ -59,6 +59,8 @@ _SIGNATURES = {
     "rsv_aggregate_views": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, Image, Image,
                                       C.POINTER(Params), _P, _P, _P, _P]),
     "rsv_lr_check": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "rsv_cost_argmax_views": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                        C.c_int32, _P, _P, _P]),
     "rsv_aggregate_restricted_views": (C.c_int, [_P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, Image, Image,
                                                  C.POINTER(Params), _P, _P, C.c_int32, _P, _P, _P, _P]),
     "rsv_select_subpixel": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(Params), _P, _P, _P,

@@ -137,6 +137,57 @@ __global__ __launch_bounds__(kSelThreads) void cost_argmax_kernel(const float* _
   disp[static_cast<int64_t>(v) * W + u] = a;
 }
 
+// The same for two views in one pass (e.g. both views of one joint volume): per
+// thread the scans of pixel u in both, their loads interleaved, so that where the
+// views share a volume its lines are fetched once for both.
+__global__ __launch_bounds__(kSelThreads) void cost_argmax2_kernel(const float* __restrict__ c0, int64_t cps0,
+                                                                  int64_t crs0, const float* __restrict__ c1,
+                                                                  int64_t cps1, int64_t crs1, int W, int D,
+                                                                  int32_t* __restrict__ d0,
+                                                                  int32_t* __restrict__ d1) {
+  const int u = blockIdx.x * kSelThreads + threadIdx.x;
+  if (u >= W) return;
+  const int v = blockIdx.y;
+  const float* p0 = c0 + static_cast<int64_t>(v) * crs0 + u;
+  const float* p1 = c1 + static_cast<int64_t>(v) * crs1 + u;
+  float b0 = wta_key(p0[0]), b1 = wta_key(p1[0]);
+  int a0 = 0, a1 = 0;
+  int d = 1;
+  for (; d + kSelUnroll <= D; d += kSelUnroll) {
+    float x0[kSelUnroll], x1[kSelUnroll];
+#pragma unroll
+    for (int i = 0; i < kSelUnroll; ++i) {
+      x0[i] = wta_key(p0[(d + i) * cps0]);
+      x1[i] = wta_key(p1[(d + i) * cps1]);
+    }
+#pragma unroll
+    for (int i = 0; i < kSelUnroll; ++i) {
+      if (x0[i] > b0) {
+        b0 = x0[i];
+        a0 = d + i;
+      }
+      if (x1[i] > b1) {
+        b1 = x1[i];
+        a1 = d + i;
+      }
+    }
+  }
+  for (; d < D; ++d) {
+    const float y0 = wta_key(p0[d * cps0]), y1 = wta_key(p1[d * cps1]);
+    if (y0 > b0) {
+      b0 = y0;
+      a0 = d;
+    }
+    if (y1 > b1) {
+      b1 = y1;
+      a1 = d;
+    }
+  }
+  const int64_t i = static_cast<int64_t>(v) * W + u;
+  d0[i] = a0;
+  d1[i] = a1;
+}
+
 }  // namespace rsv
 
 namespace rsv {
@@ -203,5 +254,23 @@ extern "C" int rsv_cost_argmax(const float* cost, int64_t plane_stride, int64_t 
   const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
   cost_argmax_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(cost, plane_stride, row_stride, width, D,
                                                                         disp);
+  return check_launch();
+}
+
+extern "C" int rsv_cost_argmax_views(const float* cost_ref, int64_t ref_plane_stride, int64_t ref_row_stride,
+                                     const float* cost_tar, int64_t tar_plane_stride, int64_t tar_row_stride,
+                                     int32_t height, int32_t width, int32_t D, int32_t* disp_ref, int32_t* disp_tar,
+                                     void* stream) {
+  using namespace rsv;
+  if (!cost_ref || !cost_tar || !disp_ref || !disp_tar) return RSV_E_NULL;
+  if (height < 1 || width < 1 || D < 1 || D > RSV_MAX_D || ref_row_stride < width || tar_row_stride < width ||
+      ref_plane_stride < 1 || tar_plane_stride < 1)
+    return RSV_E_SHAPE;
+  if (!aligned(cost_ref, 4) || !aligned(cost_tar, 4) || !aligned(disp_ref, 4) || !aligned(disp_tar, 4))
+    return RSV_E_ALIGN;
+  const dim3 grid((width + kSelThreads - 1) / kSelThreads, height);
+  cost_argmax2_kernel<<<grid, dim3(kSelThreads), 0, as_stream(stream)>>>(cost_ref, ref_plane_stride, ref_row_stride,
+                                                                         cost_tar, tar_plane_stride, tar_row_stride,
+                                                                         width, D, disp_ref, disp_tar);
   return check_launch();
 }

@@ -313,6 +313,26 @@ def cost_argmax(cost: torch.Tensor, out: torch.Tensor | None = None) -> torch.Te
     return out
 
 
+def cost_argmax_views(cost_ref: torch.Tensor, cost_tar: torch.Tensor, out: tuple | None = None) -> tuple:
+    """cost_argmax of two views in one pass (rsv_cost_argmax_views): (coarse_ref,
+    coarse_tar), each bit for bit cost_argmax's."""
+    lib = load()
+    D, H, W = cost_ref.shape
+    for t, n in ((cost_ref, "cost_ref"), (cost_tar, "cost_tar")):
+        _dev(t, n, torch.float32, (D, H, W))
+        if t.stride(2) != 1:
+            raise ValueError(f"{n}: cost views need unit column stride")
+    dev = cost_ref.device
+    cr, ct = out if out is not None else (torch.empty((H, W), dtype=torch.int32, device=dev),
+                                          torch.empty((H, W), dtype=torch.int32, device=dev))
+    _contig(cr, "disp_ref", torch.int32, (H, W))
+    _contig(ct, "disp_tar", torch.int32, (H, W))
+    check(lib.rsv_cost_argmax_views(cost_ref.data_ptr(), cost_ref.stride(0), cost_ref.stride(1), cost_tar.data_ptr(),
+                                    cost_tar.stride(0), cost_tar.stride(1), H, W, D, cr.data_ptr(), ct.data_ptr(),
+                                    _stream(dev)), "rsv_cost_argmax_views")
+    return cr, ct
+
+
 def aggregate_restricted_argmax(cost: torch.Tensor, guide: torch.Tensor, params, coarse: torch.Tensor,
                                 radius: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """rsv_aggregate_argmax inside each pixel's window of min(2 radius + 1, D) disparities
@@ -364,14 +384,13 @@ def aggregate_restricted_select(cost: torch.Tensor, guide: torch.Tensor, params,
 def reconstruct_restricted(left: torch.Tensor, right: torch.Tensor, plane, camera, params, radius: int,
                            out: dict | None = None) -> dict:
     """The plain path with the restricted search of Sec. IV: warp -> joint cost volume ->
-    calculated disparities of both views (rsv_cost_argmax) -> both views' aggregations
+    calculated disparities of both views in one pass (rsv_cost_argmax_views) -> both views' aggregations
     over the windows of min(2 radius + 1, D) disparities in one launch, with the
     selection folded in (rsv_aggregate_restricted_views) -> left-right check ->
     post-processing + 3-D points."""
     wp = warp(right, plane)
     cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
-    cc_ref = cost_argmax(cref)
-    cc_tar = cost_argmax(ctar)
+    cc_ref, cc_tar = cost_argmax_views(cref, ctar)
     sel = aggregate_restricted_views(cref, ctar, left, wp, params, cc_ref, cc_tar, radius, out=out)
     sel["valid"] = lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold,
                             out=(out or {}).get("valid"))
@@ -583,7 +602,7 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
 
 
 __all__ = ["StereoParams", "RsvError", "warp", "cost_volume", "cost_volume_joint", "joint_views",
-           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select", "aggregate_views", "aggregate_restricted_views", "lr_check",
+           "joint_row_stride", "aggregate", "aggregate_argmax", "aggregate_select", "aggregate_views", "aggregate_restricted_views", "cost_argmax_views", "lr_check",
            "aggregate_select_supported", "select_subpixel",
            "triangulate", "reconstruct", "selected_cost_sum", "selected_aggregate_sum", "cost_adjoint",
            "cost_argmax", "aggregate_restricted_argmax", "aggregate_restricted_select", "reconstruct_restricted",

@@ -248,6 +248,13 @@ def test_aggregate_views_and_lr_check_validation(lib):
     assert call(a8=C.byref(_params(agg_radius=6))) == -3
     assert call(a6=_img(w=3), a7=_img(w=3, dtype=1), a2=3, a5=3, a1=96, a4=97) == -2  # W < 4
     assert call(a8=C.byref(_params(lr_threshold=-1))) == -3
+    cv = lib.rsv_cost_argmax_views
+    assert cv(None, 32 * 48, 48, B, 32 * 48 + 1, 48, 32, 48, 16, Cc, Dd, None) == -1
+    assert cv(A, 32 * 48, 48, B, 32 * 48 + 1, 48, 32, 48, 16, Cc, None, None) == -1
+    assert cv(A, 32 * 48, 48, B, 32 * 48 + 1, 47, 32, 48, 16, Cc, Dd, None) == -2   # row stride < W
+    assert cv(A, 32 * 48, 48, B, 0, 48, 32, 48, 16, Cc, Dd, None) == -2             # plane stride < 1
+    assert cv(A, 32 * 48, 48, B, 32 * 48 + 1, 48, 32, 48, 0, Cc, Dd, None) == -2    # D < 1
+    assert cv(A, 32 * 48, 48, B + 2, 32 * 48 + 1, 48, 32, 48, 16, Cc, Dd, None) == -5
     rv = lib.rsv_aggregate_restricted_views
     args = list(ok[:9]) + [B, Cc, 2] + list(ok[9:])  # valid: never called, each case breaks one argument
     bad = list(args)

@@ -129,6 +129,25 @@ def test_two_view_launch_equals_two_launches(rsv_gpu, H, W, D, r, rho, seed, rad
         assert torch.equal(rsv.lr_check(vw["disp_ref"], vw["disp_tar"], prm.lr_threshold), sel["valid"])
 
 
+@pytest.mark.parametrize("H,W,D,seed", [(1, 1, 1, 1), (9, 33, 17, 2), (37, 150, 31, 3), (20, 70, 64, 4)])
+def test_calculated_disparities_of_both_views_in_one_pass(rsv_gpu, H, W, D, seed):
+    """rsv_cost_argmax_views equals two rsv_cost_argmax calls bit for bit, on the
+    joint volume's views and on two dense volumes; with ties (a flat volume) and NaN."""
+    rsv = rsv_gpu
+    case = synth.small_case(max(H, 7), max(W, 7), D, 3, 2, seed)
+    L, R = _gpu(case.pair.left), _gpu(case.pair.right)
+    wp = rsv.warp(R, case.plane)
+    jref, jtar = rsv.joint_views(rsv.cost_volume_joint(L, wp, case.params), L.shape[1])
+    rng = np.random.default_rng(seed)
+    dense = torch.from_numpy(rng.standard_normal((2, D, H, W)).astype(np.float32)).cuda()
+    dense[0, :, 0, :] = 0.25                      # a row of ties
+    dense[1, D // 2, :, 0] = float("nan")         # NaN ranks below every number
+    _say(f"[restricted] calculated disparities of both views H={H} W={W} D={D}")
+    for a, b in ((jref, jtar), (dense[0], dense[1])):
+        cr, ct = rsv.cost_argmax_views(a, b)
+        assert torch.equal(cr, rsv.cost_argmax(a)) and torch.equal(ct, rsv.cost_argmax(b))
+
+
 def test_road1280_d64_agrees_with_full_inside_windows(rsv_gpu):
     """1280x720, D = 64: wherever the full method's winner lies inside the pixel's
     window, the restricted winner is the same (the window's values are the same
