@@ -388,24 +388,24 @@ typedef struct rsv_batch_plan rsv_batch_plan;
 
 void rsv_tuning_default(rsv_tuning* t);
 
-/* Builds a plan for the whole batch: device workspace for every pair's warped image,
- * joint cost volume (rsv_cost_volume_joint's layout, row stride W + D - 1 rounded up
- * to 64) and selection state, two work lists, and a hipGraph of
- *   [reset queue counters] -> [warp every pair] -> [cost kernel] -> [tile kernel]
- *   -> [per-pixel tail]
- * (with a volume budget: cost and tile kernels per group of pairs, see rsv_tuning).
- * The cost kernel runs ZNCC (the arithmetic of rsv_cost_volume_joint), persistent
- * over a work queue or one workgroup per tile (see rsv_tuning); with per-pair
- * launches the graph runs each pair's cost launch and then its tile launch.  Where
- * agg_radius <= 5 and W >= 4 the tile kernel takes one workgroup per (pair, 16 x 16
- * block, view), the LDS-loaded aggregation tile of rsv_aggregate_select (reference
- * view: winner, its value and neighbours) or of rsv_aggregate_argmax (target view);
- * otherwise a persistent kernel pulls (pair, block, view) items from per-XCD atomic
- * counters and runs rsv_aggregate's tile with winner-take-all fused in.  No
- * aggregated volume is written.  The tail runs the left-right check, Eq. 12,
- * post-processing
- * and triangulation (those of rsv_select_subpixel and rsv_triangulate).  Every
- * output equals the plain path's bit for bit.
+/* Builds a plan for the whole batch: device workspace for every pair's warped image
+ * and selection state, the joint cost volumes of the pairs in flight
+ * (rsv_cost_volume_joint's layout, row stride W + D - 1 rounded up to 64), the work
+ * lists, and a hipGraph of
+ *   [reset queue counters] -> [warp every pair] -> per group of pairs: [cost kernel]
+ *   -> [tile kernel] -> [per-pixel tail]
+ * (one group without a volume budget; with one, groups alternate between two volume
+ * slots on two graph branches, see rsv_tuning).  The cost kernel runs ZNCC (the
+ * arithmetic of rsv_cost_volume_joint): persistent over a work queue, one workgroup
+ * per tile, or, in the per-pair schedule (the default), one launch per pair taking the
+ * pair's descriptor as an argument.  Where agg_radius <= 5 and W >= 4 the tile kernel
+ * takes one workgroup per (pair, 16 x 16 block, view), the LDS-loaded aggregation tile
+ * of rsv_aggregate_views (reference view: winner and Eq. 12; target view: its argmax),
+ * per pair in the per-pair schedule; otherwise a persistent kernel pulls (pair, block,
+ * view) items from per-XCD atomic counters and runs rsv_aggregate's tile with
+ * winner-take-all fused in.  No aggregated volume is written.  The tail runs the
+ * left-right check, post-processing and triangulation (those of rsv_lr_check and
+ * rsv_triangulate).  Every output equals the plain path's bit for bit.
  *   pairs, n   the batch (host array, copied)
  *   p          shared parameters (block_radius, agg_radius, gammas, lr_threshold,
  *              sigma_min); p->D is ignored
