@@ -185,6 +185,15 @@ def test_pitched_inputs_match_dense(rsv_gpu):
     b = rsv.reconstruct(Lp, Rp, case.plane, _camera(case), prm)
     for k in ("warped", "cost_ref", "cost_tar", "agg_ref", "agg_tar", "disp_ref", "disp_sub", "valid"):
         assert torch.equal(a[k], b[k]), k
+    # the fused forms (both views in one launch; the restricted search) read the pitched left image too
+    _say("[pitched] two-view launch and restricted search with row pitch 200")
+    c = rsv.reconstruct(Lp, Rp, case.plane, _camera(case), prm, tar_volume=False, ref_volume=False)
+    for k in ("disp_ref", "disp_tar", "disp_sub", "valid"):
+        assert torch.equal(a[k], c[k]), k
+    r1 = rsv.reconstruct_restricted(L, R, case.plane, _camera(case), prm, 3)
+    r2 = rsv.reconstruct_restricted(Lp, Rp, case.plane, _camera(case), prm, 3)
+    for k in ("coarse_ref", "coarse_tar", "disp_ref", "disp_tar", "disp_sub", "valid"):
+        assert torch.equal(r1[k], r2[k]), k
 
 
 @pytest.mark.parametrize("H,W,D,r,rho,seed", [(33, 90, 20, 3, 5, 41), (21, 37, 9, 2, 6, 42)])
