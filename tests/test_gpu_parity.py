@@ -267,9 +267,11 @@ def test_rerun_is_bitwise_deterministic(rsv_gpu):
         assert torch.equal(a[k].nan_to_num(), b[k].nan_to_num()), k
 
 
-def test_plain_frame_graph_replays_equal_eager(rsv_gpu):
+@pytest.mark.parametrize("fused", [False, True])
+def test_plain_frame_graph_replays_equal_eager(rsv_gpu, fused):
     """The plain frame (warp, joint cost volume, reference aggregation, target argmax,
-    selection, 3-D points) captured as one graph: every replay, with eager work and
+    selection, 3-D points; fused: both views in one launch with the selection folded in,
+    then the left-right check) captured as one graph: every replay, with eager work and
     synchronisations between replays and the outputs cleared before each, reproduces
     the eager frame bit for bit."""
     rsv = rsv_gpu
@@ -295,12 +297,16 @@ def test_plain_frame_graph_replays_equal_eager(rsv_gpu):
     def frame():
         rsv.warp(R, case.plane, out=wp)
         rsv.cost_volume_joint(L, wp, prm, out=joint)
-        rsv.aggregate(cref, L, prm, out=aref)
-        rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
-        rsv.select_subpixel(aref, None, prm, out=sel)
+        if fused:
+            rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
+            rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
+        else:
+            rsv.aggregate(cref, L, prm, out=aref)
+            rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
+            rsv.select_subpixel(aref, None, prm, out=sel)
         rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
 
-    _say("[graph] eager frame, 320x180 D=32")
+    _say(f"[graph] eager frame, 320x180 D=32, fused={fused}")
     frame()
     torch.cuda.synchronize()
     eager = [t.clone() for t in outs]
