@@ -191,12 +191,14 @@ int dispatch_agg_select(const float* cost, int64_t cps, int crs, const rsv_image
 // ------------------------------------------- both views in one launch
 // Items come row by row of tiles, the reference tiles of a tile row next to its
 // target tiles, so both views' reads of the same rows of the joint volume come close
-// together in time; XCDs take the items in runs of kViewsXcdRun (two tile rows of both
+// together in time; XCDs take the items in runs of kViewsXcdRun (one tile row of both
 // views at 1280 columns).  One launch of 2T tiles also leaves one partial last round of
 // blocks instead of two.  Measured at 1280x720, D = 64 against the target argmax and
 // the reference selection as two launches: 0.469 -> 0.443 ms (runs of 80; 20: 0.456,
-// 40: 0.447).
-constexpr int kViewsXcdRun = 80;
+// 40: 0.447); later, with the conversion beside the MFMAs, runs of 80 / 160 / 240 / 320
+// gave 0.433 / 0.430 / 0.433 / 0.431 ms, and interleaving the two views tile by tile
+// instead of row by row gained nothing.
+constexpr int kViewsXcdRun = 160;
 
 template <int A, typename TGR>
 __global__ __launch_bounds__(1024) void aggregate_views_kernel(

@@ -110,17 +110,23 @@ __device__ __forceinline__ float pixel(const T* img, int64_t pitch, int v, int u
 }
 
 // Work item of block b in runs of M: blocks are dealt round-robin to the 8 XCDs, and
-// within each group of 8 M consecutive items XCD x takes the M items x M .. x M + M - 1
-// (the last partial group in order).  Neighbouring items share an L2 while the whole
-// GPU stays on one stretch of the list (one pair's volume in the shared cache).  A
-// bijection of [0, n).
+// within each group of 8 M consecutive items XCD x takes the M items x M .. x M + M - 1.
+// Neighbouring items share an L2 while the whole GPU stays on one stretch of the list
+// (one pair's volume in the shared cache).  The last partial group of m items is cut
+// into 8 contiguous chunks the same way (XCD x takes m / 8 items, one more for
+// x < m % 8), so its neighbours share an L2 too: dealing it round-robin instead cost
+// 15 % more L2 fetches in the two-view aggregation at 1280x720, whose last 800 of 7200
+// items form such a group.  A bijection of [0, n).
 template <int M>
 __device__ __forceinline__ int xcd_run_item(int b, int n) {
   constexpr int G = 8 * M;
   const int g = b / G;
-  if ((g + 1) * G > n) return b;
   const int r = b - g * G;
-  return g * G + (r & 7) * M + (r >> 3);
+  const int x = r & 7, i = r >> 3;
+  if ((g + 1) * G <= n) return g * G + x * M + i;
+  const int m = n - g * G;
+  const int q = m >> 3, e = m & 7;
+  return g * G + x * q + (x < e ? x : e) + i;
 }
 
 }  // namespace rsv
