@@ -862,6 +862,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "arithmetic": {
+            "storage": "FP32 cost volumes and maps",
+            "cost_volume": "FP32 FMA dot products (FP64 block statistics; FP64 recompute of nearly flat target blocks)",
+            "aggregate_views": "split-fp16 matrix products, v_mfma_f32_16x16x32_f16 (hi*hi + hi*lo + lo*hi, FP32 "
+                               "accumulation, relative error about 2^-22); weights by the hardware base-2 exponential",
+            "lr_check": "integer"},
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {W}x{H} uint8 road pair, D={D}, "
                                f"NCC {2 * prm.block_radius + 1}x{2 * prm.block_radius + 1}, "
