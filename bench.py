@@ -82,7 +82,7 @@ CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
 _AGG_SOURCES = ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
                 "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"]
 KERNEL_SOURCES = {
-    "cost_volume": ["cost.hip", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
+    "cost_volume": ["cost.hip", "cost_box.hpp", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
     "aggregate_views": _AGG_SOURCES,
     "aggregate_ref": _AGG_SOURCES,
     "aggregate_tar": _AGG_SOURCES,
@@ -133,15 +133,32 @@ def agg_lds_bytes(W, H, D, rho):
 
 
 def cost_lds_bytes(W, H, D, r):
-    """LDS bytes one cost launch moves, from the tile's design (64 centres x 4 rows per
-    block, centres u < W + D - 1): per entry, one new window column (2r + 1 floats) and
-    1/e_r of the target centre; per block, the tile fills, the target statistics (a pair
-    of rows reads 2r + 2 rows of 2r + 1) and the left blocks."""
+    """LDS bytes one cost launch moves, from the tile's design.  Blocks of 3x3 and 5x5
+    (direct tile, 64 centres x 4 rows per block, centres u < W + D - 1): per entry, one
+    new window column (2r + 1 floats) and 1/e_r of the target centre; per block, the
+    tile fills, the target statistics (a pair of rows reads 2r + 2 rows of 2r + 1) and
+    the left blocks.  Blocks of 7x7 and 9x9 (sliding-sum tile, 64 centres x 16 rows per
+    block of 8 waves, disparities in chunks of 64): per block the left tile, its row
+    sums and S_l, 1/e_l (read by every wave); per chunk the warped rows and the target
+    statistics; per disparity the horizontal pass reads 8 + 2r warped values and writes
+    8 FP64 sums per run of 8 centres (8 runs per row of the tile and its halo), and the
+    vertical pass reads a column of sums and S_r, 1/e_r per entry."""
     k = 2 * r + 1
-    bx, by = (W + D - 1 + 63) // 64, (H + 3) // 4
-    rows, wtc, ltw, nt = 4 + 2 * r, 64 + D - 1 + 2 * r, 64 + 2 * r, 64 + D - 1
-    per_block = 4 * (256 * D * (k + 1) + rows * (wtc + ltw) + 2 * nt * ((k + 1) * k + 2) + 256 * k * k)
-    return bx * by * per_block
+    if r <= 2:
+        bx, by = (W + D - 1 + 63) // 64, (H + 3) // 4
+        rows, wtc, ltw, nt = 4 + 2 * r, 64 + D - 1 + 2 * r, 64 + 2 * r, 64 + D - 1
+        per_block = 4 * (256 * D * (k + 1) + rows * (wtc + ltw) + 2 * nt * ((k + 1) * k + 2) + 256 * k * k)
+        return bx * by * per_block
+    th, tw = 16, 64
+    rows, lw, ws, tc = th + 2 * r, tw + 2 * r, 127 + 2 * r, 127
+    jobs, nl = rows * 8, 8 + 2 * r
+    bx, by = (W + D - 1 + tw - 1) // tw, (H + th - 1) // th
+    chunks = (D + 63) // 64
+    setup = (rows * lw * 4 + rows * tw * (k * 4 + 16) + th * tw * (k * 16 + 12) + jobs * nl * 4
+             + 8 * th * tw * 12)
+    chunk = rows * ws * 4 + tc * 4 * (4 + 2 * r) * k * 4 + tc * th * 12
+    per_d = jobs * (nl * 4 + 8 * 8) + tw * (rows * 8 + th * 12)
+    return bx * by * (setup + chunks * chunk + D * per_d)
 
 
 def agg_entry(stage_ms, key, W, H, D, prm, fused):
@@ -864,7 +881,9 @@ def main():
         "dtype": "f32",
         "arithmetic": {
             "storage": "FP32 cost volumes and maps",
-            "cost_volume": "FP32 FMA dot products (FP64 block statistics; FP64 recompute of nearly flat target blocks)",
+            "cost_volume": "7x7 and 9x9 blocks: FP64 sliding window sums (exact numerator for uint8 images); 3x3 "
+                           "and 5x5: FP32 FMA dot products, FP64 block statistics, FP64 recompute of nearly flat "
+                           "target blocks",
             "aggregate_views": "split-fp16 matrix products, v_mfma_f32_16x16x32_f16 (hi*hi + hi*lo + lo*hi, FP32 "
                                "accumulation, relative error about 2^-22); weights by the hardware base-2 exponential",
             "lr_check": "integer"},

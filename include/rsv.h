@@ -365,8 +365,9 @@ typedef struct {
 /* Launch shape of a plan (rsv_tuning_default fills the defaults). */
 typedef struct {
   int32_t largest_first;        /* 1: queue the pairs by decreasing W*H*D; 0: as given    */
-  int32_t cost_tiles_per_item;  /* cost work item = this many tiles of 4 rows x 64
-                                   centres (1 .. 16; 1 when cost_blocks_per_cu = -1)       */
+  int32_t cost_tiles_per_item;  /* cost work item = this many tiles of 64 centres x 4
+                                   rows (3x3, 5x5 blocks) or x 16 rows (7x7, 9x9)
+                                   (1 .. 16; 1 when cost_blocks_per_cu = -1)               */
   int32_t cost_blocks_per_cu;   /* persistent cost workgroups per CU; 0 = as many as fit
                                    (default); -1 = one workgroup per cost item, no queue */
   int32_t agg_blocks_per_cu;    /* persistent aggregation workgroups per CU; 0 = as fit  */

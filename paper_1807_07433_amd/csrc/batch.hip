@@ -37,14 +37,12 @@
 #include "agg_tile.hpp"
 #include "agg_tile_dma.hpp"
 #include "argmax_sink.hpp"
-#include "cost_tile.hpp"
+#include "cost_box.hpp"
 #include "select_math.hpp"
 #include "warp_math.hpp"
 
 namespace rsv {
 
-constexpr int kCostThreads = 256;
-constexpr int kBandRows = kCostThreads / kCostTW;  // 4
 constexpr int kAggItemThreads = 1024;
 constexpr int kAggQueues = 8;  // one per XCD
 
@@ -197,29 +195,29 @@ __global__ __launch_bounds__(256) void batch_warp_kernel(const PairDev* pairs) {
 }
 
 // Cost item {pair, tiles << 8, band, first column tile}: `tiles` consecutive tiles of
-// 64 centres x kBandRows rows.
+// 64 centres x cost_tile_rows<R>() rows.
 template <int R>
-__device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, float* cwork) {
+__device__ __forceinline__ void batch_cost_item(const BatchArgs& args, int4 w, unsigned char* cwork) {
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const float* warped = uniform(pd->warped);
   const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
   auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
   const int c0 = uniform(w.w);
   const int last = min(c0 + (uniform(w.y) >> 8), uniform(pd->ncol_tiles));
-  const int v0 = uniform(w.z) * kBandRows;
+  const int v0 = uniform(w.z) * cost_tile_rows<R>();
   const uint8_t* left = uniform(pd->left);
   const int64_t lpitch = uniform(pd->lpitch);
   const CostOut out = cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D);
   for (int ct = c0; ct < last; ++ct) {
     if (ct > c0) __syncthreads();  // LDS is reused by the next tile
-    cost_tile<R, kBandRows, false>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
+    cost_tile_for<R, false>(left, lpitch, warped_at, H, W, D, args.sigma_min, ct * kCostTW, v0,
                             out, cwork);
   }
 }
 
 template <int R>
-__global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args) {
-  extern __shared__ __align__(16) float cwork[];
+__global__ __launch_bounds__(cost_tile_threads<R>()) void batch_cost_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char cwork[];
   __shared__ int s_item[2];
   for_each_item(args, 0, s_item, [&](int it) { batch_cost_item<R>(args, args.items[it], cwork); });
 }
@@ -227,30 +225,30 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchArgs args
 // The same work with one workgroup per cost item (no queue): without the item loop
 // the kernel keeps the plain cost kernel's register budget and occupancy.
 template <int R>
-__global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_cost_grid_kernel(BatchArgs args) {
-  extern __shared__ __align__(16) float cwork[];
+__global__ __launch_bounds__(cost_tile_threads<R>(), cost_uses_box<R>() ? 1 : 4) void batch_cost_grid_kernel(BatchArgs args) {
+  extern __shared__ __align__(16) unsigned char cwork[];
   const int4 w = args.items[blockIdx.x];  // one tile: {pair, 1 << 8, band, column tile}
   const PairDev* pd = uniform(args.pairs + uniform(w.x));
   const float* warped = uniform(pd->warped);
   const int W = uniform(pd->W), H = uniform(pd->H), D = uniform(pd->D);
   auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
-  cost_tile<R, kBandRows, false>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
-                          uniform(w.w) * kCostTW, uniform(w.z) * kBandRows,
+  cost_tile_for<R, false>(uniform(pd->left), uniform(pd->lpitch), warped_at, H, W, D, args.sigma_min,
+                          uniform(w.w) * kCostTW, uniform(w.z) * cost_tile_rows<R>(),
                           cost_out_joint(uniform(pd->joint), uniform(pd->jrow), H, W, D), cwork);
 }
 
 // One pair's cost tiles, the pair's descriptor a kernel argument (block b: band
 // b / ncol_tiles, column tile b % ncol_tiles); used by the per-pair launch schedule.
 template <int R>
-__global__ __launch_bounds__(kCostThreads, R <= 3 ? 4 : 1) void batch_pair_cost_kernel(PairDev P, float sigma_min) {
-  extern __shared__ __align__(16) float cwork[];
+__global__ __launch_bounds__(cost_tile_threads<R>(), cost_uses_box<R>() ? 1 : 4) void batch_pair_cost_kernel(PairDev P, float sigma_min) {
+  extern __shared__ __align__(16) unsigned char cwork[];
   const float* warped = P.warped;
   const int W = P.W;
   auto warped_at = [&](int y, int x) { return as_global(warped)[static_cast<int64_t>(y) * W + x]; };
   const int band = static_cast<int>(blockIdx.x) / P.ncol_tiles;
   const int ct = static_cast<int>(blockIdx.x) - band * P.ncol_tiles;
-  cost_tile<R, kBandRows, false>(P.left, P.lpitch, warped_at, P.H, W, P.D, sigma_min, ct * kCostTW,
-                                 band * kBandRows, cost_out_joint(P.joint, P.jrow, P.H, W, P.D), cwork);
+  cost_tile_for<R, false>(P.left, P.lpitch, warped_at, P.H, W, P.D, sigma_min, ct * kCostTW,
+                                 band * cost_tile_rows<R>(), cost_out_joint(P.joint, P.jrow, P.H, W, P.D), cwork);
 }
 
 template <int A>
@@ -648,7 +646,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     P.H = H;
     P.W = W;
     P.D = D;
-    P.nbands = (H + kBandRows - 1) / kBandRows;
+    P.nbands = (H + cost_tile_rows_rt(R) - 1) / cost_tile_rows_rt(R);
     P.ncol_tiles = (W + D - 1 + kCostTW - 1) / kCostTW;
     P.tiles_x = (W + 15) / 16;
     P.plane = q.plane;
@@ -780,7 +778,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
     rsv_batch_plan_destroy(plan);
     return RSV_E_PARAM;
   }
-  const size_t cost_lds = sizeof(float) * cost_tile_lds_floats(maxD, R, kBandRows);
+  const size_t cost_lds = cost_tile_lds(R, maxD);
   if ((e = hipFuncSetAttribute(ck, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(cost_lds))) !=
       hipSuccess)
     return fail(e);
@@ -801,7 +799,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
   int dev = 0, cus = 0, cost_fit = 0, agg_fit = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(e);
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return fail(e);
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cost_fit, ck, kCostThreads, cost_lds)) != hipSuccess)
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cost_fit, ck, cost_tile_threads_rt(R), cost_lds)) != hipSuccess)
     return fail(e);
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&agg_fit, ak, kAggItemThreads, agg_lds)) != hipSuccess)
     return fail(e);
@@ -876,7 +874,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
         PairDev Pc = pd[order[k]];
         float sm = p->sigma_min;
         void* cargs[] = {&Pc, &sm};
-        note(hipLaunchKernel(pck, dim3(Pc.nbands * Pc.ncol_tiles), dim3(kCostThreads), cargs, cost_lds, gs));
+        note(hipLaunchKernel(pck, dim3(Pc.nbands * Pc.ncol_tiles), dim3(cost_tile_threads_rt(R)), cargs, cost_lds, gs));
         if (tile_end[k] > tile_beg[k]) {  // all of the pair's tiles, both views
           PairDev P = pd[order[k]];
           BilateralK bk = ca.bk;
@@ -892,7 +890,7 @@ extern "C" int rsv_batch_plan_create(const rsv_pair_desc* pairs, int32_t n, cons
       if (cost_grid_mode) c.items += g_cost[g];  // one workgroup per item of the group
       void* cargs[] = {&c};
       if (cost_blocks(g) > 0)
-        note(hipLaunchKernel(ck, dim3(cost_blocks(g)), dim3(kCostThreads), cargs, cost_lds, gs));
+        note(hipLaunchKernel(ck, dim3(cost_blocks(g)), dim3(cost_tile_threads_rt(R)), cargs, cost_lds, gs));
       if (agg_blocks(g) > 0) {
         void* aargs[] = {&a};
         note(hipLaunchKernel(ak, dim3(agg_blocks(g)), dim3(kAggItemThreads), aargs, agg_lds, gs));

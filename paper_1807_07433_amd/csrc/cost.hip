@@ -1,37 +1,34 @@
 // rsv_cost_volume, rsv_cost_volume_joint: ZNCC reference and target cost volumes
 // (Sec. II-B.1, Eq. 3-5), as two dense volumes or as one joint volume.
-// One block per tile of 64 left-block centres x 4 rows (cost_tile.hpp); the grid
-// spans centres u = 0 .. W + D - 2 so that the target volume is filled where
-// x + d leaves the image.  LDS holds the left tile (64 + 2R columns), the warped
-// tile (64 + D - 1 + 2R columns) and 1/e_r of every target centre of the tile.
-#include "cost_tile.hpp"
+// One block per tile of 64 left-block centres x cost_tile_rows<R>() rows: the direct
+// tile (cost_tile.hpp) for 3x3 and 5x5 blocks, the sliding-sum tile (cost_box.hpp)
+// for 7x7 and 9x9.  The grid spans centres u = 0 .. W + D - 2 so that the target
+// volume is filled where x + d leaves the image.
+#include "cost_box.hpp"
 
 namespace rsv {
 
-constexpr int kCostTH = 4;
-
 template <int R, typename TL, bool TAR>
-__global__ __launch_bounds__(kCostTW* kCostTH, R <= 3 ? 4 : 1) void cost_volume_kernel(
+__global__ __launch_bounds__(cost_tile_threads<R>(), cost_uses_box<R>() ? 1 : 4) void cost_volume_kernel(
     const TL* __restrict__ left, int64_t lpitch, const float* __restrict__ warped, int H, int W,
     int D, float sigma_min, CostOut out) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   auto warped_at = [&](int y, int x) { return warped[static_cast<int64_t>(y) * W + x]; };
-  cost_tile<R, kCostTH, TAR>(left, lpitch, warped_at, H, W, D, sigma_min, blockIdx.x * kCostTW,
-                        blockIdx.y * kCostTH, out, smem);
+  cost_tile_for<R, TAR>(left, lpitch, warped_at, H, W, D, sigma_min, blockIdx.x * kCostTW,
+                        blockIdx.y * cost_tile_rows<R>(), out, smem);
 }
 
 template <int R, typename TL>
 int launch_cost(const rsv_image& left, const float* warped, const rsv_params* p, const CostOut& out,
                 hipStream_t st) {
   const int H = left.height, W = left.width, D = p->D;
-  const size_t lds = sizeof(float) * cost_tile_lds_floats(D, R, kCostTH);
-  const dim3 block(kCostTW * kCostTH);
-  const dim3 grid((W + D - 1 + kCostTW - 1) / kCostTW, (H + kCostTH - 1) / kCostTH);
+  const size_t lds = cost_tile_lds(R, D);
+  const dim3 block(cost_tile_threads<R>());
+  const dim3 grid((W + D - 1 + kCostTW - 1) / kCostTW, (H + cost_tile_rows<R>() - 1) / cost_tile_rows<R>());
   auto kern = out.tar ? cost_volume_kernel<R, TL, true> : cost_volume_kernel<R, TL, false>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) {
       set_hip_error(e);
       return RSV_E_HIP;

@@ -62,11 +62,25 @@ def test_lds_traffic_of_the_tiles():
     raw6 = 28 * 28
     tile6 = 2 * 16 * raw6 * 2 + 16 * 8 * 2 * 64 * 16 + 2 * 16 * 256 * 4
     assert bench.agg_lds_bytes(1280, 720, 64, 6) == 80 * 45 * (4 * tile6 + 1024 * 8 * 8 * 2 * 4)
-    # cost, r = 3, 21 x 180 blocks of 64 x 4 centres: per entry a window column of 7 and
-    # 1/e_r; per block the fills (10 rows of 133 warped + 70 left columns), two row
-    # pairs x 127 target centres reading 8 x 7 values and writing 2, 256 left blocks of 49
-    per_block = 256 * 64 * 8 + 10 * (133 + 70) + 2 * 127 * (8 * 7 + 2) + 256 * 49
-    assert bench.cost_lds_bytes(1280, 720, 64, 3) == 21 * 180 * 4 * per_block
+    # cost, r = 2 (direct tile), 21 x 180 blocks of 64 x 4 centres: per entry a window
+    # column of 5 and 1/e_r; per block the fills (8 rows of 131 warped + 68 left columns),
+    # two row pairs x 127 target centres reading 6 x 5 values and writing 2, 256 left
+    # blocks of 25
+    per_block = 256 * 64 * 6 + 8 * (131 + 68) + 2 * 127 * (6 * 5 + 2) + 256 * 25
+    assert bench.cost_lds_bytes(1280, 720, 64, 2) == 21 * 180 * 4 * per_block
+    # cost, r = 3 (sliding-sum tile), 21 x 45 blocks of 64 x 16 centres (22 rows with the
+    # halo, 70 left and 133 warped columns, 176 runs of 8 centres, 14 values per run),
+    # one chunk of 64 d.  Set-up: left fill, row sums (7 reads, 2 FP64 writes), S_l and
+    # 1/e_l (7 x 2 FP64 reads, 12 B written), the runs' left values, 8 waves reading
+    # 16 x 64 x 12 B.
+    setup = 22 * 70 * 4 + 22 * 64 * (7 * 4 + 16) + 16 * 64 * (7 * 16 + 12) + 176 * 14 * 4 + 8 * 16 * 64 * 12
+    assert setup == 303248
+    # chunk: warped fill; 127 centres x 4 row groups, 10 rows of 7 reads; 12 B per statistic
+    chunk = 22 * 133 * 4 + 127 * 4 * 10 * 7 * 4 + 127 * 16 * 12
+    # per disparity: each run reads 14 values and writes 8 sums; each lane reads 22 sums
+    # and 16 (S_r, 1/e_r)
+    per_d = 176 * (14 * 4 + 8 * 8) + 64 * (22 * 8 + 16 * 12)
+    assert bench.cost_lds_bytes(1280, 720, 64, 3) == 21 * 45 * (setup + chunk + 64 * per_d)
 
 
 def test_kernel_rooflines_with_the_selection_folded_in():
