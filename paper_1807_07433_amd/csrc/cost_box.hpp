@@ -285,8 +285,8 @@ __device__ __forceinline__ void cost_box_tile(const TL* __restrict__ left, int64
 // The sliding-sum tile issues about 2 (2R + 3) + 12 operations per entry against the
 // direct tile's (2R + 1)^2 + 3, but each of its disparities is a chain of LDS round
 // trips, which the direct tile does not have.  Measured at 1280x720, D = 64 (direct
-// tile, then this one): 3x3 0.057 / 0.090 ms, 7x7 0.117-0.121 / 0.106 ms, 9x9
-// 0.210 / 0.120 ms.  Blocks of 7x7 and larger take it.
+// tile, then this one): 3x3 0.057 / 0.090 ms, 5x5 0.090-0.093 / 0.099 ms, 7x7
+// 0.117-0.121 / 0.106 ms, 9x9 0.210 / 0.120 ms.  Blocks of 7x7 and larger take it.
 template <int R>
 constexpr bool cost_uses_box() { return R >= 3; }
 constexpr int kDirectTH = 4;  // rows of a direct tile (64 x 4 centres, 256 threads)
