@@ -269,8 +269,6 @@ def bench_batch(a, rsv, torch):
 
     # 64 sequential plain calls, buffers sized for the largest pair and reused
     f32 = dict(dtype=torch.float32, device=dev)
-    mx = max(c.pair.left.size * c.params.D for c in cases)
-    vols = [torch.empty(mx, **f32)]
     mxj = max(c.params.D * c.pair.left.shape[0] * rsv.joint_row_stride(c.pair.left.shape[1], c.params.D)
               for c in cases)
     jbuf = torch.empty(mxj, **f32)
@@ -284,23 +282,16 @@ def bench_batch(a, rsv, torch):
                               "disp_sub": torch.empty((H, W), **f32),
                               "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)},
                          dfin=torch.empty((H, W), **f32), xyz=torch.empty((H, W, 3), **f32),
-                         v=[t[:D * H * W].view(D, H, W) for t in vols],
                          j=jbuf[:D * H * rsv.joint_row_stride(W, D)].view(D, H, rsv.joint_row_stride(W, D))))
 
     def plain_all():
         for (left, right, plane, cam, D), c, o in zip(pairs, cases, outs):
-            ar, = o["v"]
             rsv.warp(right, plane, out=o["wp"])
             rsv.cost_volume_joint(left, o["wp"], c.params, out=o["j"])
             cr, ct = rsv.joint_views(o["j"], left.shape[1])
-            if rsv.aggregate_select_supported(left.shape[1], c.params):
-                rsv.aggregate_views(cr, ct, left, o["wp"], c.params, out=o["sel"])
-                rsv.lr_check(o["sel"]["disp_ref"], o["sel"]["disp_tar"], c.params.lr_threshold,
-                             out=o["sel"]["valid"])
-            else:
-                rsv.aggregate_argmax(ct, o["wp"], c.params, out=o["sel"]["disp_tar"])
-                rsv.aggregate(cr, left, c.params, out=ar)
-                rsv.select_subpixel(ar, None, c.params, out=o["sel"])
+            rsv.aggregate_views(cr, ct, left, o["wp"], c.params, out=o["sel"])
+            rsv.lr_check(o["sel"]["disp_ref"], o["sel"]["disp_tar"], c.params.lr_threshold,
+                         out=o["sel"]["valid"])
             rsv.triangulate(o["sel"]["disp_sub"], o["sel"]["valid"], plane, cam, out_disp=o["dfin"],
                             out_xyz=o["xyz"])
 
@@ -665,16 +656,12 @@ def bench_sweep(a, rsv, torch, case, L, R):
     wp = torch.empty((H, W), **f32)
     joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
     cref, ctar = rsv.joint_views(joint, W)
-    aref = None
     sel = {"disp_ref": torch.empty((H, W), **i32), "disp_tar": torch.empty((H, W), **i32),
            "disp_sub": torch.empty((H, W), **f32), "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
     grid = {}
     for r in (1, 2, 3, 4):
         for rho in (1, 2, 3, 4, 5, 6):
             prm = dataclasses.replace(prm0, block_radius=r, agg_radius=rho)
-            fused = rsv.aggregate_select_supported(W, prm)
-            if not fused and aref is None:
-                aref = torch.empty((D, H, W), **f32)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
             def run(record):
@@ -683,17 +670,10 @@ def bench_sweep(a, rsv, torch, case, L, R):
                 rsv.cost_volume_joint(L, wp, prm, out=joint)
                 if record:
                     ev[1].record()
-                if fused:
-                    rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
-                    if record:
-                        ev[2].record()
-                    rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
-                else:
-                    rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])
-                    if record:
-                        ev[2].record()
-                    rsv.aggregate(cref, L, prm, out=aref)
-                    rsv.select_subpixel(aref, None, prm, out=sel)
+                rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
+                if record:
+                    ev[2].record()
+                rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
                 if record:
                     ev[3].record()
             rsv.warp(R, case.plane, out=wp)
@@ -791,20 +771,17 @@ def main():
     wp = torch.empty((H, W), **f32)
     joint = torch.empty((D, H, rsv.joint_row_stride(W, D)), **f32)
     cref, ctar = rsv.joint_views(joint, W)  # both cost volumes, views of the joint one
-    aref = None if rsv.aggregate_select_supported(W, prm) else torch.empty((D, H, W), **f32)
     sel = {"disp_ref": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_tar": torch.empty((H, W), dtype=torch.int32, device=dev),
            "disp_sub": torch.empty((H, W), **f32),
            "valid": torch.empty((H, W), dtype=torch.uint8, device=dev)}
     dfin = torch.empty((H, W), **f32)
     xyz = torch.empty((H, W, 3), **f32)
-    # Where the LDS-loaded tile runs (radius <= 5, W >= 4), both views are aggregated in
-    # one launch with WTA and Eq. 12 folded in ("aggregate_views"), then Eq. 11
-    # ("lr_check"); no aggregated volume is written.  Otherwise the target volume is
-    # reduced to its argmax and the reference volume is written and selected from.
-    fused = rsv.aggregate_select_supported(W, prm)
-    stages = ["warp", "cost_volume"] + (["aggregate_views", "lr_check"] if fused else
-                                        ["aggregate_tar", "aggregate_ref", "select_subpixel"]) + ["triangulate"]
+    # Both views are aggregated in one launch with WTA and Eq. 12 folded in
+    # ("aggregate_views"; the LDS-loaded tile where radius <= 5 and W >= 4, else the
+    # register-staged one), then Eq. 11 ("lr_check"); no aggregated volume is written.
+    fused = True
+    stages = ["warp", "cost_volume", "aggregate_views", "lr_check", "triangulate"]
 
     def step(ev=None):
         marks = iter(ev) if ev is not None else None
@@ -817,16 +794,9 @@ def main():
         mark()
         rsv.cost_volume_joint(L, wp, prm, out=joint)
         mark()
-        if fused:
-            rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
-            mark()
-            rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
-        else:
-            rsv.aggregate_argmax(ctar, wp, prm, out=sel["disp_tar"])  # the target volume only feeds its argmax
-            mark()
-            rsv.aggregate(cref, L, prm, out=aref)
-            mark()
-            rsv.select_subpixel(aref, None, prm, out=sel)
+        rsv.aggregate_views(cref, ctar, L, wp, prm, out=sel)
+        mark()
+        rsv.lr_check(sel["disp_ref"], sel["disp_tar"], prm.lr_threshold, out=sel["valid"])
         mark()
         rsv.triangulate(sel["disp_sub"], sel["valid"], case.plane, cam, out_disp=dfin, out_xyz=xyz)
         mark()
@@ -921,7 +891,7 @@ def main():
         out["differentiable"] = bench_diff(a, rsv, torch)
     if case.pair.extra.get("bumps"):
         out["accuracy"] = accuracy_block(case, cam, xyz)
-    if not a.no_restricted and fused:
+    if not a.no_restricted and rsv.aggregate_select_supported(W, prm):  # the windowed tile: radius <= 5, W >= 4
         out["restricted"] = bench_restricted(a, rsv, torch, case, L, R, cam, sel, dfin, stage_ms)
     if not a.no_plane:
         out["plane"] = bench_plane(a, rsv, torch, dfin, sel["valid"])

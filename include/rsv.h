@@ -219,16 +219,20 @@ int rsv_aggregate_select(const float* cost, int64_t plane_stride, int64_t row_st
  * the reference view to its winner and Eq. 12 as rsv_aggregate_select does; the
  * left-right check (Eq. 11) is left to rsv_lr_check, which needs the complete target
  * map.  disp_tar, disp_ref and disp_sub equal those of rsv_aggregate_argmax followed
- * by rsv_aggregate_select bit for bit; no aggregated volume is written.  Runs where
- * the cost tiles are loaded straight into LDS: agg_radius <= 5 and W >= 4.
+ * by rsv_select_subpixel_ref (the winner and Eq. 12) bit for bit; no aggregated volume
+ * is written.  Every window radius and width: where agg_radius <= 5 and W >= 4 the
+ * cost tiles are loaded straight into LDS; otherwise the register-staged tile of
+ * rsv_aggregate runs, with the selection's scan over d kept in LDS.
  *   cost_ref(d, v, u) = cost_ref[d*ref_plane_stride + v*ref_row_stride + u] (the
  *             reference view), cost_tar likewise (the target view; e.g. both views of
  *             one joint volume)
  *   guide_ref the left image (u8 or f32);  guide_tar the warped right image (f32),
  *             of the same H, W
  *   disp_tar, disp_ref out, int32 [H][W];  disp_sub out, float32 [H][W]
- * Errors: as rsv_aggregate_select; RSV_E_DTYPE for a guide_tar that is not float32,
- * RSV_E_SHAPE for guides of different sizes. */
+ * Errors: RSV_E_NULL, RSV_E_ALIGN, RSV_E_PARAM (radii out of range, lr_threshold < 0),
+ * RSV_E_SHAPE (row stride < W, plane stride < 1, (H - 1) * row stride + W or a plane
+ * stride above 2^26, guides of different sizes), RSV_E_DTYPE for a guide_tar that is
+ * not float32, RSV_E_HIP. */
 int rsv_aggregate_views(const float* cost_ref, int64_t ref_plane_stride, int64_t ref_row_stride,
                         const float* cost_tar, int64_t tar_plane_stride, int64_t tar_row_stride,
                         rsv_image guide_ref, rsv_image guide_tar, const rsv_params* p,

@@ -57,7 +57,7 @@ class AggregatedZNCC(torch.autograd.Function):
 def select(left, right, plane, params, return_joint: bool = False):
     """Plain-path selection for the current plane, in its fastest form (joint cost
     volume, both views aggregated in one launch with the selection folded in, then the
-    left-right check, where that runs): returns (disp_ref int32, mask uint8) with
+    left-right check): returns (disp_ref int32, mask uint8) with
     mask = left-right valid and 0 < d < D-1 (pixels where Eq. 12 applies); with
     return_joint, also the joint cost volume, which AggregatedZNCC takes for the same
     plane."""
@@ -65,12 +65,8 @@ def select(left, right, plane, params, return_joint: bool = False):
     wp = ops.warp(right, plane)
     joint = ops.cost_volume_joint(left, wp, params)
     cref, ctar = ops.joint_views(joint, W)
-    if ops.aggregate_select_supported(W, params):
-        sel = ops.aggregate_views(cref, ctar, left, wp, params)
-        sel["valid"] = ops.lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold)
-    else:
-        dtar = ops.aggregate_argmax(ctar, wp, params)
-        sel = ops.select_subpixel(ops.aggregate(cref, left, params), None, params, out={"disp_tar": dtar})
+    sel = ops.aggregate_views(cref, ctar, left, wp, params)
+    sel["valid"] = ops.lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold)
     d = sel["disp_ref"]
     mask = (sel["valid"].bool() & (d > 0) & (d < int(params.D) - 1)).to(torch.uint8)
     return (d, mask, joint) if return_joint else (d, mask)

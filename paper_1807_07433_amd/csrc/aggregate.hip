@@ -15,6 +15,7 @@
 #include "agg_tile_dma.hpp"
 #include "argmax_sink.hpp"
 #include "select_math.hpp"
+#include "wta_sink.hpp"
 
 namespace rsv {
 
@@ -230,6 +231,66 @@ __global__ __launch_bounds__(1024) void aggregate_views_kernel(
   }
 }
 
+// Both views on the register-staged tile (agg_tile.hpp), for windows the LDS-loaded
+// tile does not take (rho = 6, or W < 4): the item order of the kernel above, and per
+// block the select kernel's scan over d through WtaSink (wta_sink.hpp), so the maps
+// equal those of the unfused path (aggregation, then selection) bit for bit.
+template <int A, typename TGR>
+__global__ __launch_bounds__(1024) void aggregate_views_rs_kernel(
+    const float* __restrict__ cref, int64_t rps, int rrs, const float* __restrict__ ctar, int64_t tps, int trs,
+    const TGR* __restrict__ gref, int64_t grp, const float* __restrict__ gtar, int64_t gtp, int H, int W, int D,
+    BilateralK bk, int32_t* __restrict__ dtar, int32_t* __restrict__ dref, float* __restrict__ dsub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tiles_x = (W + 15) >> 4, tiles_y = (H + 15) >> 4;
+  const int k = xcd_run_item<kViewsXcdRun>(blockIdx.x, 2 * tiles_x * tiles_y);
+  const int ty = k / (2 * tiles_x), r = k - ty * 2 * tiles_x;
+  const bool ref = r < tiles_x;  // uniform per block
+  const int by = ty * 16, bx = (ref ? r : r - tiles_x) * 16;
+  WtaState* st = reinterpret_cast<WtaState*>(smem + agg_tile_lds_bytes<A, 16>());
+  WtaSink sink{st, D, ref};
+  if (ref) {
+    auto guide_at = [&](int Y, int X) { return pixel(gref, grp, Y, X); };
+    agg_tile<A, 16>(cref, rps, rrs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  } else {
+    auto guide_at = [&](int Y, int X) { return pixel(gtar, gtp, Y, X); };
+    agg_tile<A, 16>(ctar, tps, trs, H, W, D, bk, by, bx, guide_at, sink, smem);
+  }
+  // thread q < 256 wrote its own pixel's state in the last sink call
+  if (threadIdx.x < 256) {
+    const int q = threadIdx.x;
+    const int Y = by + (q >> 4), X = bx + (q & 15);
+    if (Y < H && X < W) {
+      const int64_t i = static_cast<int64_t>(Y) * W + X;
+      if (ref) {
+        dref[i] = st->arg[q];
+        dsub[i] = parabola(st->arg[q], st->best[q], st->am[q], st->ap[q], D);
+      } else {
+        dtar[i] = st->arg[q];
+      }
+    }
+  }
+}
+
+template <int A, typename TGR>
+int launch_agg_views_rs(const float* cref, int64_t rps, int rrs, const float* ctar, int64_t tps, int trs,
+                        const rsv_image& gr, const rsv_image& gt, const rsv_params* p, int32_t* dtar, int32_t* dref,
+                        float* dsub, hipStream_t st) {
+  const int tiles = ((gr.width + 15) / 16) * ((gr.height + 15) / 16);
+  const BilateralK bk = bilateral_constants(p->gamma_d, p->gamma_r);
+  const size_t lds = agg_tile_lds_bytes<A, 16>() + sizeof(WtaState);
+  auto kern = aggregate_views_rs_kernel<A, TGR>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds));
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RSV_E_HIP;
+  }
+  kern<<<dim3(2 * tiles), dim3(1024), lds, st>>>(cref, rps, rrs, ctar, tps, trs, static_cast<const TGR*>(gr.data),
+                                                 gr.pitch, static_cast<const float*>(gt.data), gt.pitch, gr.height,
+                                                 gr.width, p->D, bk, dtar, dref, dsub);
+  return check_launch();
+}
+
 template <int A, typename TGR>
 int launch_agg_views(const float* cref, int64_t rps, int rrs, const float* ctar, int64_t tps, int trs,
                      const rsv_image& gr, const rsv_image& gt, const rsv_params* p, int32_t* dtar, int32_t* dref,
@@ -258,6 +319,17 @@ template <typename TGR>
 int dispatch_agg_views(const float* cref, int64_t rps, int rrs, const float* ctar, int64_t tps, int trs,
                        const rsv_image& gr, const rsv_image& gt, const rsv_params* p, int32_t* dtar, int32_t* dref,
                        float* dsub, hipStream_t st) {
+  if (p->agg_radius > 5 || gr.width < 4) {  // the register-staged tile
+    switch (p->agg_radius) {
+      case 1: return launch_agg_views_rs<1, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      case 2: return launch_agg_views_rs<2, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      case 3: return launch_agg_views_rs<3, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      case 4: return launch_agg_views_rs<4, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      case 5: return launch_agg_views_rs<5, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      case 6: return launch_agg_views_rs<6, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
+      default: return RSV_E_PARAM;
+    }
+  }
   switch (p->agg_radius) {
     case 1: return launch_agg_views<1, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
     case 2: return launch_agg_views<2, TGR>(cref, rps, rrs, ctar, tps, trs, gr, gt, p, dtar, dref, dsub, st);
@@ -462,11 +534,10 @@ int validate_views(const float* cost_ref, int64_t rps, int64_t rrs, const float*
   if (!aligned(cost_ref, 4) || !aligned(cost_tar, 4) || !aligned(dtar, 4) || !aligned(dref, 4) || !aligned(dsub, 4))
     return RSV_E_ALIGN;
   if (gt.dtype != RSV_F32) return RSV_E_DTYPE;
-  if (p->agg_radius > 5) return RSV_E_PARAM;
   if (gt.width != gr.width || gt.height != gr.height) return RSV_E_SHAPE;
   const int64_t H = gr.height, W = gr.width;
   for (int64_t rs : {rrs, trs})
-    if (W < 4 || rs < W || (H - 1) * rs + W > kAggMaxPixels) return RSV_E_SHAPE;
+    if (rs < W || (H - 1) * rs + W > kAggMaxPixels) return RSV_E_SHAPE;
   for (int64_t ps : {rps, tps})
     if (ps < 1 || ps > kAggMaxPixels) return RSV_E_SHAPE;
   return RSV_OK;

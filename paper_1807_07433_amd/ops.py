@@ -218,9 +218,9 @@ def aggregate_select(cost: torch.Tensor, guide: torch.Tensor, params, disp_tar: 
 def aggregate_views(cost_ref: torch.Tensor, cost_tar: torch.Tensor, guide_ref: torch.Tensor,
                     guide_tar: torch.Tensor, params, out: dict | None = None) -> dict:
     """Both views aggregated in one launch (rsv_aggregate_views): disp_tar as
-    aggregate_argmax gives it, disp_ref and disp_sub as aggregate_select gives them,
-    bit for bit; the left-right check is lr_check's.  guide_tar is the float32
-    warped right image.  Runs where aggregate_select_supported holds."""
+    aggregate_argmax gives it, disp_ref and disp_sub as the selection gives them (the
+    winner and Eq. 12), bit for bit; the left-right check is lr_check's.  guide_tar is
+    the float32 warped right image.  Any window radius and width."""
     lib = load()
     D, H, W = cost_ref.shape
     for t, n in ((cost_ref, "cost_ref"), (cost_tar, "cost_tar")):
@@ -570,15 +570,15 @@ def reconstruct(left: torch.Tensor, right: torch.Tensor, plane, camera, params,
     one joint volume (rsv_cost_volume_joint); otherwise two dense volumes.  With
     tar_volume=False the target volume is reduced to its argmax as it is aggregated
     (rsv_aggregate_argmax) and "agg_tar" is None.  With ref_volume=False as well (and
-    where rsv_aggregate_select runs, without top2) both views are aggregated in one
-    launch with the selection folded in (rsv_aggregate_views, then rsv_lr_check) and
-    "agg_ref" is None.  Every other output is the same."""
+    without top2) both views are aggregated in one launch with the selection folded in
+    (rsv_aggregate_views, then rsv_lr_check) and "agg_ref" is None.  Every other output
+    is the same."""
     wp = warp(right, plane)
     if joint:
         cref, ctar = joint_views(cost_volume_joint(left, wp, params), left.shape[1])
     else:
         cref, ctar = cost_volume(left, wp, params)
-    if not tar_volume and not ref_volume and not want_top2 and aggregate_select_supported(left.shape[1], params):
+    if not tar_volume and not ref_volume and not want_top2:
         sel = aggregate_views(cref, ctar, left, wp, params)
         sel["valid"] = lr_check(sel["disp_ref"], sel["disp_tar"], params.lr_threshold)
         dfin, xyz = triangulate(sel["disp_sub"], sel["valid"], plane, camera)

@@ -225,9 +225,9 @@ def test_aggregate_select_validation(lib):
 
 def test_aggregate_views_and_lr_check_validation(lib):
     """rsv_aggregate_views rejects bad arguments before launching: nulls, alignment,
-    strides, guides of different sizes, a target guide that is not float32, radii the
-    LDS-loaded tile cannot take, widths below 4; rsv_lr_check: nulls, alignment, sizes
-    and a negative tolerance."""
+    strides, guides of different sizes, a target guide that is not float32, a window
+    radius out of range; rsv_lr_check: nulls, alignment, sizes and a negative
+    tolerance."""
     p = _params()
     A, B, Cc, Dd, E = (FAKE + i * 4096 for i in range(5))
     f = lib.rsv_aggregate_views
@@ -245,9 +245,8 @@ def test_aggregate_views_and_lr_check_validation(lib):
     assert call(a4=0) == -2                                        # plane stride < 1
     assert call(a7=_img(h=31, dtype=1)) == -2                      # guides of different sizes
     assert call(a7=_img()) == -4                                   # target guide must be float32
-    assert call(a8=C.byref(_params(agg_radius=6))) == -3
-    assert call(a6=_img(w=3), a7=_img(w=3, dtype=1), a2=3, a5=3, a1=96, a4=97) == -2  # W < 4
     assert call(a8=C.byref(_params(lr_threshold=-1))) == -3
+    assert call(a8=C.byref(_params(agg_radius=7))) == -3            # beyond RSV_MAX_AGG_RADIUS
     cv = lib.rsv_cost_argmax_views
     assert cv(None, 32 * 48, 48, B, 32 * 48 + 1, 48, 32, 48, 16, Cc, Dd, None) == -1
     assert cv(A, 32 * 48, 48, B, 32 * 48 + 1, 48, 32, 48, 16, Cc, None, None) == -1

@@ -135,12 +135,13 @@ def test_small_every_stage(rsv_gpu, H, W, D, r, rho, seed, dtype, a2):
         fused = rsv.aggregate_select(jref, L, prm, dt)
         for k in ("disp_ref", "disp_sub", "valid"):
             assert torch.equal(fused[k], sel[k]), k
-        _say("  rsv_aggregate_views + rsv_lr_check (both views in one launch)")
-        vw = rsv.aggregate_views(jref, jtar, L, wp, prm)
-        assert torch.equal(vw["disp_tar"], dt), "disp_tar of the two-view launch"
-        for k in ("disp_ref", "disp_sub"):
-            assert torch.equal(vw[k], sel[k]), k
-        assert torch.equal(rsv.lr_check(vw["disp_ref"], vw["disp_tar"], prm.lr_threshold), sel["valid"])
+    # every window and width: the LDS-loaded tile, or the register-staged one at rho = 6 or W < 4
+    _say("  rsv_aggregate_views + rsv_lr_check (both views in one launch)")
+    vw = rsv.aggregate_views(jref, jtar, L, wp, prm)
+    assert torch.equal(vw["disp_tar"], dt), "disp_tar of the two-view launch"
+    for k in ("disp_ref", "disp_sub"):
+        assert torch.equal(vw[k], sel[k]), k
+    assert torch.equal(rsv.lr_check(vw["disp_ref"], vw["disp_tar"], prm.lr_threshold), sel["valid"])
     top2 = P.to_np(sel["top2"])
     P.check_close("best", top2[0], ref["best"], P.AGG_TOL)
     if D > 1:
@@ -429,13 +430,12 @@ def _fused_target_matches(rsv, case, out):
     assert f["agg_tar"] is None
     for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
         assert torch.equal(f[k].nan_to_num(), out[k].nan_to_num()), k
-    if rsv.aggregate_select_supported(p.left.shape[1], case.params):
-        _say("  selection folded into the reference aggregation as well: every output equal")
-        g = rsv.reconstruct(_gpu(p.left), _gpu(p.right), case.plane, _camera(case), case.params, tar_volume=False,
-                            ref_volume=False)
-        assert g["agg_ref"] is None
-        for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
-            assert torch.equal(g[k].nan_to_num(), out[k].nan_to_num()), k
+    _say("  both views in one launch with the selection folded in: every output equal")
+    g = rsv.reconstruct(_gpu(p.left), _gpu(p.right), case.plane, _camera(case), case.params, tar_volume=False,
+                        ref_volume=False)
+    assert g["agg_ref"] is None
+    for k in ("disp_ref", "disp_tar", "disp_sub", "valid", "disp_final", "xyz"):
+        assert torch.equal(g[k].nan_to_num(), out[k].nan_to_num()), k
 
 
 def test_full_road1280_d64_sampled(rsv_gpu):
