@@ -80,7 +80,7 @@ def source_sha(paths):
 
 CSRC = os.path.join(ROOT, "paper_1807_07433_amd", "csrc")
 _AGG_SOURCES = ["aggregate.hip", "agg_tile_dma.hpp", "agg_tile.hpp", "aggregate_mfma.hpp", "argmax_sink.hpp",
-                "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"]
+                "wta_sink.hpp", "select_math.hpp", "fp16_split.hpp", "bilateral_math.hpp", "rsv_internal.hpp"]
 KERNEL_SOURCES = {
     "cost_volume": ["cost.hip", "cost_box.hpp", "cost_tile.hpp", "zncc_math.hpp", "rsv_internal.hpp"],
     "aggregate_views": _AGG_SOURCES,
